@@ -1,0 +1,191 @@
+/*
+ * tdpd.h -- C ABI of the MI355X tDPD + red-blood-cell time-step library.
+ *
+ * The library advances the particle system of transport dissipative particle
+ * dynamics with RBC membranes (Blumers et al., arXiv:1611.06163):
+ *   - pair forces: conservative, dissipative and random, Eqs. (3)-(5), with
+ *     the fluctuation-dissipation pairing of Eq. (6), summed as in Eq. (2);
+ *   - concentration fluxes: Fickian and random, Eqs. (8)-(9) with the pairing
+ *     of Eq. (10), summed as in Eq. (7), for n_species species per particle;
+ *   - membrane bonded terms (Section 2.2): WLC and POW springs, Eqs. (13)-(14),
+ *     bond viscosity and its random partner, Eqs. (15)-(16), global and local
+ *     area and global volume constraints, Eqs. (17)-(18), bending, Eq. (19);
+ *   - velocity-Verlet integration of Eqs. (1)-(2) and (7).
+ * Every step runs in HIP kernels on the device; the host only enqueues.
+ *
+ * Conventions shared by all calls:
+ *   - Every function returns a tdpd_status: 0 on success, < 0 on error.
+ *     Nothing throws across the ABI.  tdpd_last_error() gives a message.
+ *   - Host buffers passed in are read during the call and stay owned by the
+ *     caller; host buffers passed out are caller-allocated with the stated
+ *     size.  Device memory belongs to the library; it is obtained through
+ *     the caller's allocator callback when one is given, else hipMalloc.
+ *   - Particle arrays are in gid order: gid = index in the array given to
+ *     tdpd_set_state.  Vectors are AoS [n][3] float32, concentrations
+ *     [n][n_species] float32.
+ *   - The HIP stream given at creation is borrowed; every kernel is enqueued
+ *     on it.  Calls are not thread-safe for one system.
+ */
+#ifndef TDPD_H
+#define TDPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TDPD_OK = 0,
+  TDPD_ERR_INVALID_ARG = -1,   /* bad pointer, size or parameter */
+  TDPD_ERR_BOX_TOO_SMALL = -2, /* fewer than 3 cells of size > max(rc, rcc) per side */
+  TDPD_ERR_OOM = -3,           /* device allocation failed */
+  TDPD_ERR_HIP = -4,           /* a HIP runtime call failed */
+  TDPD_ERR_NONFINITE = -5,     /* a force or state value became NaN/Inf */
+  TDPD_ERR_BOND_OVEREXTENDED = -6, /* a WLC bond reached its maximum length */
+  TDPD_ERR_STATE = -7,         /* call out of order (e.g. step before set_state) */
+  TDPD_ERR_UNSUPPORTED = -8,   /* valid request outside what the library handles */
+  TDPD_ERR_CAPACITY = -9       /* an output buffer was too small */
+} tdpd_status;
+
+#define TDPD_MAX_TYPES 4
+#define TDPD_MAX_SPECIES 8
+
+/* Terms bitmask (tdpd_params.terms); all set by default. */
+#define TDPD_TERM_CONSERVATIVE 1    /* Eq. (3) */
+#define TDPD_TERM_DISSIPATIVE 2     /* Eq. (4) */
+#define TDPD_TERM_RANDOM 4          /* Eq. (5) */
+#define TDPD_TERM_FLUX_FICK 8       /* Eq. (8) */
+#define TDPD_TERM_FLUX_RANDOM 16    /* Eq. (9) (needs m_s > 0) */
+#define TDPD_TERM_BOND 32           /* Eqs. (13)-(14) */
+#define TDPD_TERM_BOND_VISCOUS 64   /* Eq. (15) */
+#define TDPD_TERM_BOND_RANDOM 128   /* Eq. (16) */
+#define TDPD_TERM_AREA 256          /* Eq. (17) */
+#define TDPD_TERM_VOLUME 512        /* Eq. (18) */
+#define TDPD_TERM_BENDING 1024      /* Eq. (19) */
+#define TDPD_TERM_BODY_FORCE 2048   /* constant external force on mobile particles */
+#define TDPD_TERMS_ALL 4095
+
+/* Particle flags word: bits 0-7 type index (< n_types), bit 8 frozen
+   (never moved, F = Q = 0, concentrations held fixed; used for walls). */
+#define TDPD_FLAG_FROZEN (1u << 8)
+
+typedef struct {
+  float box[3];      /* periodic box lengths; positions live in [0, L) */
+  float rc;          /* force cutoff r_c, Eqs. (3)-(5) */
+  float rcc;         /* flux cutoff r_cc, Eqs. (8)-(9) */
+  float dt;          /* time step */
+  float kT;          /* k_B T */
+  float rho;         /* number density in Eq. (10) */
+  float m_s;         /* solute mass ratio in Eq. (10); 0 switches Q^R off */
+  float s_exp;       /* w_D = (1 - r/rc)^s_exp, w_R = w_D^(1/2) */
+  float sc_exp;      /* w_DC = (1 - r/rcc)^sc_exp, w_RC = w_DC^(1/2) */
+  int32_t n_types;   /* 1..TDPD_MAX_TYPES */
+  int32_t n_species; /* 1..TDPD_MAX_SPECIES */
+  float alpha[TDPD_MAX_TYPES * TDPD_MAX_TYPES]; /* [ti*n_types+tj], symmetric */
+  float gamma[TDPD_MAX_TYPES * TDPD_MAX_TYPES];
+  float sigma[TDPD_MAX_TYPES * TDPD_MAX_TYPES];
+  float kappa[TDPD_MAX_SPECIES * TDPD_MAX_TYPES * TDPD_MAX_TYPES]; /* [(s*T+ti)*T+tj] */
+  float body_force[3];
+  int32_t wall_axis; /* -1: none; else mobile particles crossing wall_w or
+                        L - wall_w on that axis are reflected */
+  float wall_w;
+  uint64_t seed;     /* Philox key */
+  uint32_t box_id;   /* part of the Philox counter, < 2^24 */
+  int32_t terms;     /* TDPD_TERM_* mask */
+} tdpd_params;
+
+typedef struct {
+  float p;        /* WLC persistence length, Eq. (13) */
+  float x0;       /* rest extension l0 / l_m of every bond */
+  float m_pow;    /* POW exponent m, Eq. (14); k_p per bond makes l0 force-free */
+  float kb;       /* bending constant, Eq. (19) */
+  float theta0;   /* spontaneous angle; NaN = mean dihedral of the rest shape */
+  float kg, kl, kv; /* global area, local area, volume constants, Eqs. (17)-(18) */
+  float gamma_t, gamma_c; /* bond viscosities, Eqs. (15)-(16); 3 gamma_c >= gamma_t */
+} tdpd_mesh_params;
+
+typedef struct tdpd_sys tdpd_sys;
+typedef void *(*tdpd_alloc_fn)(size_t bytes, void *user); /* returns device memory or NULL */
+typedef void (*tdpd_free_fn)(void *ptr, void *user);
+
+/* Create a system.  p is copied.  hip_stream may be NULL (default stream).
+   alloc/free may both be NULL (hipMalloc/hipFree).  Checks: cutoffs > 0,
+   n_types/n_species in range, sigma^2 = 2 kT gamma within 1e-4 relative
+   (Eq. 6), at least 3 cells of edge > max(rc, rcc) per axis. */
+int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn alloc,
+                tdpd_free_fn free_fn, void *user, tdpd_sys **out);
+
+/* Set the whole particle state: n particles, pos [n][3] (wrapped into the box
+   by the library), vel [n][3], conc [n][n_species], flags [n].  All host
+   pointers.  Resets the step counter to 0 and drops membranes added before. */
+int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const float *vel,
+                   const float *conc, const uint32_t *flags);
+
+/* Register a membrane mesh: nv vertices of its rest shape ref_xyz [nv][3]
+   (FP64, unwrapped), ntri triangles tri [ntri][3] ordered counter-clockwise
+   seen from outside, forming a closed connected surface.  Rest quantities
+   come from ref_xyz (Section 2.2): per-bond l0, l_m = l0/x0, k_p cancelling
+   the WLC force at l0; per-triangle A_{0,j}; A_0 = sum; V_0 = rest volume;
+   theta0 as given or the mean rest dihedral. */
+int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref_xyz, int32_t ntri,
+                  const int32_t *tri, const tdpd_mesh_params *mp, int32_t *mesh_id);
+
+/* Bind particles [first_gid, first_gid + nv) to one cell of mesh mesh_id
+   (vertex v is particle first_gid + v).  Pair forces between vertices of the
+   same cell are left to the bonded terms; fluxes act between all pairs. */
+int tdpd_add_rbc(tdpd_sys *s, int32_t mesh_id, int64_t first_gid, int32_t *rbc_id);
+
+/* Evaluate F and Q at the current state with random-number step counter k,
+   treating the stored velocities and concentrations as the ones the
+   dissipative force and fluxes see.  Asynchronous. */
+int tdpd_compute_forces(tdpd_sys *s, uint32_t k);
+
+/* Advance n_steps velocity-Verlet steps; step n draws random numbers with
+   counter k = n.  The first call after set_state evaluates the forces at
+   k = 0 first.  Asynchronous: errors found by kernels surface at the next
+   tdpd_sync or tdpd_get_*. */
+int tdpd_step(tdpd_sys *s, int32_t n_steps);
+
+/* Wait for the stream, then read and clear the device error word. */
+int tdpd_sync(tdpd_sys *s);
+
+/* Copy state to host buffers in gid order; any pointer may be NULL. */
+int tdpd_get_state(tdpd_sys *s, float *pos, float *vel, float *conc);
+/* Last evaluated forces [n][3] and concentration rates [n][n_species]. */
+int tdpd_get_forces(tdpd_sys *s, float *F, float *Q);
+
+/* Unordered pairs {gid_i < gid_j} with 0 < d^2 < fl(rcut^2) at the current
+   positions (which = 0: rcut = rc, 1: rcut = rcc), enumerated by the pair
+   kernel's own cell search.  Writes up to cap pairs to ij [cap][2] in no
+   particular order and the total to *n_out; TDPD_ERR_CAPACITY if n_out > cap. */
+int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *ij, int64_t *n_out);
+
+/* FP64 diagnostics: out[0..2] total momentum of mobile particles, out[3] kT
+   = sum |v - vbar|^2 / (3 (N_mobile - 1)), out[4..4+S) total concentration
+   per species, then per cell (A^t, V^t).  cap = doubles available. */
+int tdpd_diagnostics(tdpd_sys *s, double *out, int64_t cap);
+
+/* Kernel timing with HIP events recorded on the system's stream around each
+   phase of a force evaluation.  mask bits: TDPD_PHASE_* (0 disables).
+   tdpd_get_timing waits for the stream, returns the summed duration in ms
+   and the launch count of one phase since the last call, and resets it. */
+#define TDPD_PHASE_PAIR 1      /* pair force + flux kernel */
+#define TDPD_PHASE_BIN 2       /* kick/drift/key + radix sort + cell bounds + reorder */
+#define TDPD_PHASE_MEMBRANE 4  /* K-Gather + membrane forces */
+#define TDPD_PHASE_KICK 8      /* second half kick */
+int tdpd_set_timing(tdpd_sys *s, int32_t mask);
+int tdpd_get_timing(tdpd_sys *s, int32_t phase, double *total_ms, int64_t *launches);
+
+int64_t tdpd_num_particles(const tdpd_sys *s);
+int64_t tdpd_step_counter(const tdpd_sys *s);
+/* Number of coincident particle pairs (d^2 == 0) met since set_state. */
+int64_t tdpd_coincident_pairs(tdpd_sys *s);
+const char *tdpd_last_error(const tdpd_sys *s);
+void tdpd_destroy(tdpd_sys *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDPD_H */

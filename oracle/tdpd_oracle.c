@@ -539,8 +539,10 @@ static void unwrap_rbc(const orc_sys *s, int r, const double *pos, double *u) {
 
 /* Membrane forces (added into F, indexed by gid), energies (bond, area,
    volume, bending) and per-RBC total area and volume. */
+static double vnorm(const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
 static int membrane(const orc_sys *s, int64_t n, const double *pos, const double *vel,
-                    uint32_t k, double *F, double *energy, double *av) {
+                    uint32_t k, double *F, double *energy, double *av, double *Fabs) {
   const orc_params *p = &s->p;
   const int terms = p->terms;
   int err = 0;
@@ -551,6 +553,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
     if (g0 < 0 || g0 + M->nv > n) return -1;
     double *u = (double *)malloc(sizeof(double) * 3 * M->nv);
     double *f = (double *)calloc(3 * M->nv, sizeof(double));
+    double *fab = (double *)calloc(M->nv, sizeof(double));
     unwrap_rbc(s, r, pos, u);
     const double *vv = vel + 3 * g0;
     /* bonds, Eqs. (13)-(16) */
@@ -612,6 +615,8 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
         f[3 * a + q] += fa[q];
         f[3 * b + q] -= fa[q];
       }
+      fab[a] += vnorm(fa);
+      fab[b] += vnorm(fa);
     }
     /* area and volume, Eqs. (17)-(18) */
     double At = 0, Vt = 0;
@@ -652,6 +657,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
           sub3(P[(v + 2) % 3], P[(v + 1) % 3], opp);
           cross3(nh, opp, g);
           for (int q = 0; q < 3; ++q) f[3 * I[v] + q] -= (cg + cl) * 0.5 * g[q];
+          fab[I[v]] += fabs(cg + cl) * 0.5 * vnorm(g);
         }
       }
       if (terms & T_VOL) {
@@ -659,10 +665,13 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
         double g[3];
         cross3(b, c, g);
         for (int q = 0; q < 3; ++q) f[3 * ia + q] -= cv * g[q] / 6.0;
+        fab[ia] += fabs(cv) * vnorm(g) / 6.0;
         cross3(c, a, g);
         for (int q = 0; q < 3; ++q) f[3 * ib + q] -= cv * g[q] / 6.0;
+        fab[ib] += fabs(cv) * vnorm(g) / 6.0;
         cross3(a, b, g);
         for (int q = 0; q < 3; ++q) f[3 * ic + q] -= cv * g[q] / 6.0;
+        fab[ic] += fabs(cv) * vnorm(g) / 6.0;
       }
     }
     /* bending, Eq. (19) */
@@ -675,14 +684,19 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
         dihedral_grad(P[0], P[1], P[2], P[3], g);
         const double coef = -mp->kb * sin(th - M->theta0);
         if (energy) energy[3] += mp->kb * (1 - cos(th - M->theta0));
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v < 4; ++v) {
           for (int a = 0; a < 3; ++a) f[3 * D[v] + a] += coef * g[v][a];
+          fab[D[v]] += fabs(coef) * vnorm(g[v]);
+        }
       }
     }
-    for (int v = 0; v < M->nv; ++v)
+    for (int v = 0; v < M->nv; ++v) {
       for (int a = 0; a < 3; ++a) F[3 * (g0 + v) + a] += f[3 * v + a];
+      if (Fabs) Fabs[g0 + v] += fab[v];
+    }
     free(u);
     free(f);
+    free(fab);
   }
   return err;
 }
@@ -700,7 +714,7 @@ static double powp(double w, double e) { return w > 0 ? pow(w, e) : 0.0; }
 int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *vel,
                const double *conc, const uint32_t *flags, uint32_t k,
                const uint8_t *which, double *F, double *Q, double *av,
-               double *energy, int64_t *nzero_out) {
+               double *energy, int64_t *nzero_out, double *Fabs, double *Qabs) {
   const orc_params *p = &s->p;
   const int n = (int)n64, S = p->n_species, T = p->n_types;
   const int terms = p->terms;
@@ -721,6 +735,9 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
       double *Fi = F + 3 * i, *Qi = Q + (size_t)S * i;
       Fi[0] = Fi[1] = Fi[2] = 0;
       for (int sp = 0; sp < S; ++sp) Qi[sp] = 0;
+      if (Fabs) Fabs[i] = 0;
+      if (Qabs)
+        for (int sp = 0; sp < S; ++sp) Qabs[(size_t)S * i + sp] = 0;
       if (which && !which[i]) continue;
       if (flags[i] & FROZEN_BIT) continue;
       int nz = 0;
@@ -752,13 +769,18 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
             fs += p->sigma[ti * T + tj] * powp(w, 0.5 * p->s_exp) * z[0] * isdt;
           }
           for (int a = 0; a < 3; ++a) Fi[a] += fs * e[a];
+          if (Fabs) Fabs[i] += fabs(fs);
         }
         if (d2 < rcc2) {
           const double wc = 1.0 - r / p->rcc;
           for (int sp = 0; sp < S; ++sp) {
             const double kap = p->kappa[(sp * T + ti) * T + tj];
             const double ci = conc[(size_t)S * i + sp], cj = conc[(size_t)S * j + sp];
-            if (terms & T_FICK) Qi[sp] += -kap * powp(wc, p->sc_exp) * (ci - cj);
+            if (terms & T_FICK) {
+              const double qd = -kap * powp(wc, p->sc_exp) * (ci - cj);
+              Qi[sp] += qd;
+              if (Qabs) Qabs[(size_t)S * i + sp] += fabs(qd);
+            }
             if ((terms & T_FRAND) && p->m_s > 0) {
               const double eps = p->m_s * sqrt(kap * p->rho * fmax(ci + cj, 0.0));
               double z[2];
@@ -766,13 +788,19 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
               orc_pair_normals(p, k, (uint32_t)i, (uint32_t)j, (uint32_t)stream, z);
               /* zeta_ij = -zeta_ji: the draw belongs to the lower gid */
               const double zeta = (i < j) ? z[word] : -z[word];
-              Qi[sp] += eps * powp(wc, 0.5 * p->sc_exp) * isdt * zeta;
+              const double qr = eps * powp(wc, 0.5 * p->sc_exp) * isdt * zeta;
+              Qi[sp] += qr;
+              if (Qabs) Qabs[(size_t)S * i + sp] += fabs(qr);
             }
           }
         }
       }
-      if (terms & T_BODY)
+      if (terms & T_BODY) {
         for (int a = 0; a < 3; ++a) Fi[a] += p->body_force[a];
+        if (Fabs) Fabs[i] += sqrt(p->body_force[0] * p->body_force[0] +
+                                  p->body_force[1] * p->body_force[1] +
+                                  p->body_force[2] * p->body_force[2]);
+      }
     }
     free(list);
   }
@@ -780,13 +808,16 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
   int err = 0;
   if (s->nrbc > 0) {
     double *Fm = (double *)calloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
-    err = membrane(s, n, pos, vel, k, Fm, energy, av);
+    double *Fma = Fabs ? (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double)) : NULL;
+    err = membrane(s, n, pos, vel, k, Fm, energy, av, Fma);
     if (err >= 0)
       for (int i = 0; i < n; ++i) {
         if ((which && !which[i]) || (flags[i] & FROZEN_BIT)) continue;
         for (int a = 0; a < 3; ++a) F[3 * i + a] += Fm[3 * i + a];
+        if (Fabs) Fabs[i] += Fma[i];
       }
     free(Fm);
+    free(Fma);
   }
   for (int i = 0; i < 3 * n && err >= 0; ++i)
     if (!isfinite(F[i])) err |= E_NONFINITE;
@@ -801,7 +832,7 @@ int orc_membrane(const orc_sys *s, int64_t n, const double *pos, const double *v
                  uint32_t k, double *F, double *energy, double *av) {
   for (int64_t i = 0; i < 3 * n; ++i) F[i] = 0;
   if (energy) energy[0] = energy[1] = energy[2] = energy[3] = 0;
-  return membrane(s, n, pos, vel, k, F, energy, av);
+  return membrane(s, n, pos, vel, k, F, energy, av, NULL);
 }
 
 /* ------------------------------------------------------------- integrator */
@@ -839,7 +870,7 @@ int orc_step(const orc_sys *s, int64_t n64, double *pos, double *vel, double *co
     }
     for (int a = 0; a < 3; ++a) pos[3 * i + a] = wrap_pos(pos[3 * i + a], p->box[a]);
   }
-  const int err = orc_forces(s, n, pos, vel, conc, flags, k, NULL, F, Q, av, NULL, NULL);
+  const int err = orc_forces(s, n, pos, vel, conc, flags, k, NULL, F, Q, av, NULL, NULL, NULL, NULL);
   for (int i = 0; i < n; ++i) {
     if (flags[i] & FROZEN_BIT) continue;
     for (int a = 0; a < 3; ++a) vel[3 * i + a] += h * F[3 * i + a];

@@ -1,0 +1,365 @@
+// kernels_core.hip -- binning (LSD radix sort of cell keys), reordering,
+// velocity-Verlet kicks, diagnostics and gid-order gathers.
+#include "launch.h"
+
+namespace tdpd {
+
+// ------------------------------------------------------------- radix sort
+// LSD radix sort with 8-bit digits.  Each pass: (1) per-tile digit histogram,
+// (2) one exclusive scan over [digit][tile] (digit-major, so tiles of equal
+// digit are consecutive and the scatter is stable), (3) per-tile scatter with
+// ranks from wavefront ballots.  Tiles are 2048 keys: 256 threads x 8 rounds.
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+constexpr int kScanThreads = 1024;
+
+static inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+size_t radix_hist_words(int64_t n) { return size_t(kRadix) * size_t(sort_tiles(n) > 0 ? sort_tiles(n) : 1); }
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t *__restrict__ keys,
+                                                             int64_t n, int shift,
+                                                             uint32_t *__restrict__ hist,
+                                                             int64_t ntiles) {
+  __shared__ uint32_t h[kRadix];
+  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) h[d] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kSortTile;
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) hist[int64_t(d) * ntiles + blockIdx.x] = h[d];
+}
+
+// Exclusive scan of `total` words in place, one workgroup; thread t owns the
+// contiguous chunk [t*chunk, (t+1)*chunk).
+__global__ void __launch_bounds__(kScanThreads) k_scan_inplace(uint32_t *__restrict__ a,
+                                                               int64_t total) {
+  __shared__ uint32_t part[kScanThreads];
+  const int64_t chunk = (total + kScanThreads - 1) / kScanThreads;
+  const int64_t b = int64_t(threadIdx.x) * chunk;
+  const int64_t e = b + chunk < total ? b + chunk : total;
+  uint32_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += a[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the partial sums
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int64_t i = b; i < e; ++i) {
+    const uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint32_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, int64_t n, int shift, const uint32_t *__restrict__ hist,
+    int64_t ntiles) {
+  constexpr int kWaves = kSortThreads / 64;
+  __shared__ uint32_t base[kRadix];
+  __shared__ uint32_t wcnt[kWaves][kRadix];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int d = tid; d < kRadix; d += kSortThreads) base[d] = hist[int64_t(d) * ntiles + blockIdx.x];
+  const uint64_t lt = __lanemask_lt();
+  const int64_t tile0 = int64_t(blockIdx.x) * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    for (int q = tid; q < kWaves * kRadix; q += kSortThreads) (&wcnt[0][0])[q] = 0;
+    __syncthreads();
+    const int64_t i = tile0 + r * kSortThreads + tid;
+    const bool valid = i < n;
+    uint32_t key = 0, val = 0, digit = 0;
+    if (valid) {
+      key = kin[i];
+      val = vin[i];
+      digit = (key >> shift) & (kRadix - 1);
+    }
+    // lanes of this wavefront holding the same digit
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (digit >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      same &= bit ? m : ~m;
+    }
+    const uint32_t rank = __popcll(same & lt);
+    if (valid && rank == 0) wcnt[wave][digit] = __popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = base[digit] + rank;
+      for (int w = 0; w < wave; ++w) off += wcnt[w][digit];
+      kout[off] = key;
+      vout[off] = val;
+    }
+    __syncthreads();
+    for (int d = tid; d < kRadix; d += kSortThreads) {
+      uint32_t t = 0;
+      for (int w = 0; w < kWaves; ++w) t += wcnt[w][d];
+      base[d] += t;
+    }
+    __syncthreads();
+  }
+}
+
+void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
+                uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, uint32_t *hist,
+                int64_t n, int key_bits, hipStream_t st) {
+  if (n <= 0) return;
+  const int passes = key_bits <= kRadixBits ? 1 : (key_bits + kRadixBits - 1) / kRadixBits;
+  const int64_t ntiles = sort_tiles(n);
+  // ping-pong so that the last pass lands in *_out
+  const uint32_t *ki = keys_in, *vi = vals_in;
+  for (int p = 0; p < passes; ++p) {
+    const bool last = p == passes - 1;
+    const bool to_out = ((passes - 1 - p) % 2) == 0;
+    uint32_t *ko = to_out ? keys_out : keys_tmp;
+    uint32_t *vo = to_out ? vals_out : vals_tmp;
+    (void)last;
+    const int shift = p * kRadixBits;
+    hipLaunchKernelGGL(k_radix_hist, dim3(unsigned(ntiles)), dim3(kSortThreads), 0, st, ki, n,
+                       shift, hist, ntiles);
+    hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(kScanThreads), 0, st, hist,
+                       int64_t(kRadix) * ntiles);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(unsigned(ntiles)), dim3(kSortThreads), 0, st, ki, vi,
+                       ko, vo, n, shift, hist, ntiles);
+    ki = ko;
+    vi = vo;
+  }
+}
+
+// ------------------------------------------------------------- integrator
+__global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const float *__restrict__ F,
+                                                 const float *__restrict__ Q, int64_t n,
+                                                 uint32_t *__restrict__ keys,
+                                                 uint32_t *__restrict__ vals, int integrate) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float x = s.x[i], y = s.y[i], z = s.z[i];
+  if (integrate && !info_frozen(s.info[i])) {
+    const float h = pc.half_dt;
+    float vx = s.vx[i] + h * F[3 * i];
+    float vy = s.vy[i] + h * F[3 * i + 1];
+    float vz = s.vz[i] + h * F[3 * i + 2];
+    for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+    x += pc.dt * vx;
+    y += pc.dt * vy;
+    z += pc.dt * vz;
+    if (pc.wall_axis >= 0) {
+      float *c = pc.wall_axis == 0 ? &x : (pc.wall_axis == 1 ? &y : &z);
+      const float L = pc.L[pc.wall_axis], w = pc.wall_w;
+      bool hit = false;
+      if (*c < w) {
+        *c = 2.f * w - *c;
+        hit = true;
+      } else if (*c > L - w) {
+        *c = 2.f * (L - w) - *c;
+        hit = true;
+      }
+      if (hit) {
+        vx = -vx;
+        vy = -vy;
+        vz = -vz;
+      }
+    }
+    x = wrap_coord(x, pc.L[0]);
+    y = wrap_coord(y, pc.L[1]);
+    z = wrap_coord(z, pc.L[2]);
+    s.x[i] = x;
+    s.y[i] = y;
+    s.z[i] = z;
+    s.vx[i] = vx;
+    s.vy[i] = vy;
+    s.vz[i] = vz;
+  }
+  const int cx = cell_coord(x, pc.inv_h[0], pc.nc[0]);
+  const int cy = cell_coord(y, pc.inv_h[1], pc.nc[1]);
+  const int cz = cell_coord(z, pc.inv_h[2], pc.nc[2]);
+  keys[i] = uint32_t((cz * pc.nc[1] + cy) * pc.nc[0] + cx);
+  vals[i] = uint32_t(i);
+}
+
+void launch_prekick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
+                    uint32_t *keys, uint32_t *vals, bool integrate, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_prekick, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s, F, Q, n,
+                     keys, vals, int(integrate));
+}
+
+// F, Q are per particle in sorted order: F [n][3], Q [n][S]
+__global__ void __launch_bounds__(256) k_postkick(PairConst pc, State s, const float *__restrict__ F,
+                                                  const float *__restrict__ Q, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (info_frozen(s.info[i])) return;
+  const float h = pc.half_dt;
+  s.vx[i] += h * F[3 * i];
+  s.vy[i] += h * F[3 * i + 1];
+  s.vz[i] += h * F[3 * i + 2];
+  for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+}
+
+void launch_postkick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
+                     hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_postkick, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s, F, Q, n);
+}
+
+// ------------------------------------------------------------- cell bounds
+__global__ void __launch_bounds__(256) k_cell_bounds(const uint32_t *__restrict__ keys, int64_t n,
+                                                     int64_t ncell, uint32_t *__restrict__ start) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t k = keys[p];
+  const int64_t kp = p ? int64_t(keys[p - 1]) : -1;
+  for (int64_t c = kp + 1; c <= k; ++c) start[c] = uint32_t(p);
+  if (p == n - 1)
+    for (int64_t c = k + 1; c <= ncell; ++c) start[c] = uint32_t(n);
+}
+
+void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
+                        uint32_t *cell_start, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_cell_bounds, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, sorted_keys,
+                     n, ncell, cell_start);
+}
+
+// ------------------------------------------------------------- reorder
+__global__ void __launch_bounds__(256) k_reorder(State a, State b, const uint32_t *__restrict__ perm,
+                                                 int64_t n, int nspec,
+                                                 uint32_t *__restrict__ slot_of_gid) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t q = perm[p];
+  b.x[p] = a.x[q];
+  b.y[p] = a.y[q];
+  b.z[p] = a.z[q];
+  b.vx[p] = a.vx[q];
+  b.vy[p] = a.vy[q];
+  b.vz[p] = a.vz[q];
+  for (int sp = 0; sp < nspec; ++sp) b.C[sp * n + p] = a.C[sp * n + q];
+  const uint32_t g = a.gid[q];
+  b.gid[p] = g;
+  b.info[p] = a.info[q];
+  slot_of_gid[g] = uint32_t(p);
+}
+
+void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
+                    uint32_t *slot_of_gid, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_reorder, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, src, dst, perm,
+                     n, nspec, slot_of_gid);
+}
+
+// ------------------------------------------------------------- diagnostics
+// Fixed-order FP64 reduction: block b sums its contiguous 1024-particle span
+// through an LDS tree; a second one-block pass sums the block partials.
+constexpr int kDiagThreads = 256;
+constexpr int kDiagSpan = 1024;
+constexpr int kDiagFields = 5 + kMaxS;
+
+__global__ void __launch_bounds__(kDiagThreads) k_diag_partial(State s, int64_t n, int nspec,
+                                                               double *__restrict__ partial) {
+  __shared__ double red[kDiagThreads];
+  double acc[kDiagFields];
+  for (int f = 0; f < kDiagFields; ++f) acc[f] = 0.0;
+  const int64_t b0 = int64_t(blockIdx.x) * kDiagSpan;
+  for (int r = 0; r < kDiagSpan / kDiagThreads; ++r) {
+    const int64_t i = b0 + r * kDiagThreads + threadIdx.x;
+    if (i >= n) break;
+    if (!info_frozen(s.info[i])) {
+      const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+      acc[0] += vx;
+      acc[1] += vy;
+      acc[2] += vz;
+      acc[3] += vx * vx + vy * vy + vz * vz;
+      acc[4] += 1.0;
+    }
+    for (int sp = 0; sp < nspec; ++sp) acc[5 + sp] += s.C[sp * n + i];
+  }
+  for (int f = 0; f < 5 + nspec; ++f) {
+    red[threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int off = kDiagThreads / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * kDiagFields + f] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double *__restrict__ partial,
+                                                             int64_t nblocks, int nfields,
+                                                             double *__restrict__ out) {
+  __shared__ double red[kDiagThreads];
+  for (int f = 0; f < nfields; ++f) {
+    double a = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kDiagThreads) a += partial[b * kDiagFields + f];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int off = kDiagThreads / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[f] = red[0];
+    __syncthreads();
+  }
+}
+
+void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hipStream_t st) {
+  const int64_t nb = n > 0 ? (n + kDiagSpan - 1) / kDiagSpan : 0;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_diag_partial, dim3(unsigned(nb)), dim3(kDiagThreads), 0, st, s, n, nspec,
+                       partial);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, st, partial, nb, 5 + nspec, out);
+}
+
+// ------------------------------------------------------------- gid order
+__global__ void __launch_bounds__(256) k_gather_gid(State s, const uint32_t *__restrict__ slot,
+                                                    int64_t n, int nspec, const float *__restrict__ F,
+                                                    const float *__restrict__ Q, float *pos,
+                                                    float *vel, float *conc, float *Fo, float *Qo) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const uint32_t p = slot[g];
+  if (pos) {
+    pos[3 * g] = s.x[p];
+    pos[3 * g + 1] = s.y[p];
+    pos[3 * g + 2] = s.z[p];
+  }
+  if (vel) {
+    vel[3 * g] = s.vx[p];
+    vel[3 * g + 1] = s.vy[p];
+    vel[3 * g + 2] = s.vz[p];
+  }
+  if (conc)
+    for (int sp = 0; sp < nspec; ++sp) conc[nspec * g + sp] = s.C[sp * n + p];
+  if (Fo) {
+    Fo[3 * g] = F[3 * p];
+    Fo[3 * g + 1] = F[3 * p + 1];
+    Fo[3 * g + 2] = F[3 * p + 2];
+  }
+  if (Qo)
+    for (int sp = 0; sp < nspec; ++sp) Qo[nspec * g + sp] = Q[nspec * p + sp];
+}
+
+void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, int nspec,
+                             const float *F, const float *Q, float *pos, float *vel, float *conc,
+                             float *Fo, float *Qo, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_gid, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, s,
+                     slot_of_gid, n, nspec, F, Q, pos, vel, conc, Fo, Qo);
+}
+
+}  // namespace tdpd

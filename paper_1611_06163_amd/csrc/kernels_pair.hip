@@ -1,0 +1,216 @@
+// kernels_pair.hip -- tDPD pair forces (Eqs. 3-6) and concentration fluxes
+// (Eqs. 8-10) over the cell list.
+//
+// Full-shell gather: particle i sums F_ij over every neighbour j itself, so
+// no atomics are needed and the result is deterministic.  F_ij and F_ji are
+// evaluated by the same expressions with d and v_ij negated and the same
+// pair noise (Philox counter keyed by the unordered gid pair), so the two
+// evaluations are exact negatives of each other.
+#include "launch.h"
+
+namespace tdpd {
+
+// Pair interaction of home particle i with candidate j at FP32 displacement
+// d = x_j + s - x_i (d2 = |d|^2 under the exact predicate, 0 < d2 < rmax2).
+struct PairAcc {
+  float fx, fy, fz;
+  float q[kMaxS];
+};
+
+__device__ __forceinline__ void pair_term(const PairConst &pc, float dx, float dy, float dz, float d2,
+                                          float vxi, float vyi, float vzi, float vxj, float vyj,
+                                          float vzj, const float *ci, const float *cj, int ti,
+                                          int tj, bool same_body, uint32_t gi, uint32_t gj,
+                                          uint32_t k, PairAcc &acc) {
+  const float rinv = __builtin_amdgcn_rsqf(d2);
+  const float r = d2 * rinv;
+  // e_ij points from j to i: e = -d / r
+  const float ex = -dx * rinv, ey = -dy * rinv, ez = -dz * rinv;
+  const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
+  const bool need_noise =
+      (d2 < pc.rc2 && !same_body && (pc.terms & TDPD_TERM_RANDOM)) ||
+      (d2 < pc.rcc2 && pc.ms_rho > 0.f && (pc.terms & TDPD_TERM_FLUX_RANDOM));
+  u32x4 w = {0, 0, 0, 0};
+  if (need_noise) w = philox10(k, lo, hi, pc.ctr3, pc.seed_lo, pc.seed_hi);
+  if (d2 < pc.rc2 && !same_body) {
+    const int tt = ti * pc.n_types + tj;
+    const float wc = fmaxf(1.f - r * pc.inv_rc, 0.f);
+    float fs = 0.f;
+    if (pc.terms & TDPD_TERM_CONSERVATIVE) fs += pc.alpha[tt] * wc;
+    const float wr = powu(wc, pc.s_half);
+    if (pc.terms & TDPD_TERM_DISSIPATIVE) {
+      const float ev = ex * (vxi - vxj) + ey * (vyi - vyj) + ez * (vzi - vzj);
+      fs -= pc.gamma[tt] * wr * wr * ev;
+    }
+    if (pc.terms & TDPD_TERM_RANDOM) fs += pc.sigma[tt] * wr * gauss(w.a, w.b) * pc.isdt;
+    acc.fx += fs * ex;
+    acc.fy += fs * ey;
+    acc.fz += fs * ez;
+  }
+  if (d2 < pc.rcc2) {
+    const float wq = fmaxf(1.f - r * pc.inv_rcc, 0.f);
+    const float wdc = pc.sc_exp == 2.f ? wq * wq : powu(wq, pc.sc_exp);
+    for (int sp = 0; sp < pc.n_species; ++sp) {
+      const float kap = pc.kappa[(sp * pc.n_types + ti) * pc.n_types + tj];
+      float q = 0.f;
+      if (pc.terms & TDPD_TERM_FLUX_FICK) q -= kap * wdc * (ci[sp] - cj[sp]);
+      if (pc.ms_rho > 0.f && (pc.terms & TDPD_TERM_FLUX_RANDOM)) {
+        const float eps = __builtin_amdgcn_sqrtf(pc.ms_rho * kap * fmaxf(ci[sp] + cj[sp], 0.f));
+        float z;
+        if (sp == 0) {
+          z = gauss(w.c, w.d);
+        } else {
+          const u32x4 w2 = philox10(k, lo, hi, pc.ctr3 | uint32_t((sp + 1) >> 1), pc.seed_lo,
+                                    pc.seed_hi);
+          z = (sp & 1) ? gauss(w2.a, w2.b) : gauss(w2.c, w2.d);
+        }
+        if (gi > gj) z = -z;  // zeta_ij = -zeta_ji
+        q += eps * powu(wq, pc.sc_half) * pc.isdt * z;
+      }
+      acc.q[sp] += q;
+    }
+  }
+}
+
+// ------------------------------------------------------------ simple kernel
+// One thread per home particle (sorted order), scanning the 27 neighbour
+// cells of its own cell in global memory.
+__global__ void __launch_bounds__(256) k_pair_simple(PairConst pc, State s,
+                                                     const uint32_t *__restrict__ cell_keys,
+                                                     const uint32_t *__restrict__ cell_start,
+                                                     int64_t n, uint32_t k, float *__restrict__ F,
+                                                     float *__restrict__ Q,
+                                                     unsigned long long *nzero, uint32_t *err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int S = pc.n_species;
+  const uint32_t infoi = s.info[i];
+  PairAcc acc;
+  acc.fx = acc.fy = acc.fz = 0.f;
+  for (int sp = 0; sp < kMaxS; ++sp) acc.q[sp] = 0.f;
+  if (!info_frozen(infoi)) {
+    const float xi = s.x[i], yi = s.y[i], zi = s.z[i];
+    const float vxi = s.vx[i], vyi = s.vy[i], vzi = s.vz[i];
+    float ci[kMaxS], cj[kMaxS];
+    for (int sp = 0; sp < S; ++sp) ci[sp] = s.C[sp * n + i];
+    const uint32_t gi = s.gid[i];
+    const int ti = info_type(infoi), bi = info_body(infoi);
+    const uint32_t key = cell_keys[i];
+    const int cx = int(key % uint32_t(pc.nc[0]));
+    const int cy = int((key / uint32_t(pc.nc[0])) % uint32_t(pc.nc[1]));
+    const int cz = int(key / uint32_t(pc.nc[0] * pc.nc[1]));
+    unsigned zero = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+      int qz = cz + dz;
+      float sz = 0.f;
+      if (qz < 0) { qz += pc.nc[2]; sz = -pc.L[2]; }
+      else if (qz >= pc.nc[2]) { qz -= pc.nc[2]; sz = pc.L[2]; }
+      for (int dy = -1; dy <= 1; ++dy) {
+        int qy = cy + dy;
+        float sy = 0.f;
+        if (qy < 0) { qy += pc.nc[1]; sy = -pc.L[1]; }
+        else if (qy >= pc.nc[1]) { qy -= pc.nc[1]; sy = pc.L[1]; }
+        for (int dx = -1; dx <= 1; ++dx) {
+          int qx = cx + dx;
+          float sx = 0.f;
+          if (qx < 0) { qx += pc.nc[0]; sx = -pc.L[0]; }
+          else if (qx >= pc.nc[0]) { qx -= pc.nc[0]; sx = pc.L[0]; }
+          const uint32_t c = uint32_t((qz * pc.nc[1] + qy) * pc.nc[0] + qx);
+          const uint32_t j0 = cell_start[c], j1 = cell_start[c + 1];
+          for (uint32_t j = j0; j < j1; ++j) {
+            const float ddx = disp(s.x[j], sx, xi);
+            const float ddy = disp(s.y[j], sy, yi);
+            const float ddz = disp(s.z[j], sz, zi);
+            const float d2 = dist2(ddx, ddy, ddz);
+            if (d2 == 0.f) {
+              if (j != uint32_t(i)) ++zero;
+              continue;
+            }
+            if (!(d2 < pc.rmax2)) continue;
+            const uint32_t infoj = s.info[j];
+            const int bj = info_body(infoj);
+            for (int sp = 0; sp < S; ++sp) cj[sp] = s.C[sp * n + j];
+            pair_term(pc, ddx, ddy, ddz, d2, vxi, vyi, vzi, s.vx[j], s.vy[j], s.vz[j], ci, cj, ti,
+                      info_type(infoj), bi >= 0 && bi == bj, gi, s.gid[j], k, acc);
+          }
+        }
+      }
+    }
+    if (zero) atomicAdd(nzero, (unsigned long long)zero);
+    if (pc.terms & TDPD_TERM_BODY_FORCE) {
+      acc.fx += pc.body_force[0];
+      acc.fy += pc.body_force[1];
+      acc.fz += pc.body_force[2];
+    }
+    if (!(isfinite(acc.fx) && isfinite(acc.fy) && isfinite(acc.fz))) atomicOr(err, kErrNonfinite);
+  }
+  F[3 * i] = acc.fx;
+  F[3 * i + 1] = acc.fy;
+  F[3 * i + 2] = acc.fz;
+  for (int sp = 0; sp < S; ++sp) Q[S * i + sp] = acc.q[sp];
+}
+
+void launch_pair_simple(const PairConst &pc, State s, const uint32_t *cell_keys,
+                        const uint32_t *cell_start, int64_t n, uint32_t k, float *F, float *Q,
+                        unsigned long long *nzero, uint32_t *err, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pair_simple, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s,
+                     cell_keys, cell_start, n, k, F, Q, nzero, err);
+}
+
+// ------------------------------------------------------------ pair listing
+__global__ void __launch_bounds__(256) k_pair_emit(PairConst pc, State s,
+                                                   const uint32_t *__restrict__ cell_keys,
+                                                   const uint32_t *__restrict__ cell_start,
+                                                   int64_t n, float rcut2, int32_t *out,
+                                                   int64_t cap, unsigned long long *count) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float xi = s.x[i], yi = s.y[i], zi = s.z[i];
+  const uint32_t gi = s.gid[i];
+  const uint32_t key = cell_keys[i];
+  const int cx = int(key % uint32_t(pc.nc[0]));
+  const int cy = int((key / uint32_t(pc.nc[0])) % uint32_t(pc.nc[1]));
+  const int cz = int(key / uint32_t(pc.nc[0] * pc.nc[1]));
+  for (int dz = -1; dz <= 1; ++dz) {
+    int qz = cz + dz;
+    float sz = 0.f;
+    if (qz < 0) { qz += pc.nc[2]; sz = -pc.L[2]; }
+    else if (qz >= pc.nc[2]) { qz -= pc.nc[2]; sz = pc.L[2]; }
+    for (int dy = -1; dy <= 1; ++dy) {
+      int qy = cy + dy;
+      float sy = 0.f;
+      if (qy < 0) { qy += pc.nc[1]; sy = -pc.L[1]; }
+      else if (qy >= pc.nc[1]) { qy -= pc.nc[1]; sy = pc.L[1]; }
+      for (int dx = -1; dx <= 1; ++dx) {
+        int qx = cx + dx;
+        float sx = 0.f;
+        if (qx < 0) { qx += pc.nc[0]; sx = -pc.L[0]; }
+        else if (qx >= pc.nc[0]) { qx -= pc.nc[0]; sx = pc.L[0]; }
+        const uint32_t c = uint32_t((qz * pc.nc[1] + qy) * pc.nc[0] + qx);
+        for (uint32_t j = cell_start[c]; j < cell_start[c + 1]; ++j) {
+          const uint32_t gj = s.gid[j];
+          if (gj <= gi) continue;
+          const float d2 = dist2(disp(s.x[j], sx, xi), disp(s.y[j], sy, yi), disp(s.z[j], sz, zi));
+          if (d2 > 0.f && d2 < rcut2) {
+            const unsigned long long pos = atomicAdd(count, 1ull);
+            if (int64_t(pos) < cap) {
+              out[2 * pos] = int32_t(gi);
+              out[2 * pos + 1] = int32_t(gj);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+void launch_pair_emit(const PairConst &pc, State s, const uint32_t *cell_keys,
+                      const uint32_t *cell_start, int64_t n, float rcut2, int32_t *out,
+                      int64_t cap, unsigned long long *count, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pair_emit, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s,
+                     cell_keys, cell_start, n, rcut2, out, cap, count);
+}
+
+}  // namespace tdpd

@@ -1,0 +1,89 @@
+// launch.h -- host-side launchers of the library's HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tdpd_device.h"
+
+namespace tdpd {
+
+// Radix sort of (key, value) u32 pairs; keys < 2^key_bits.  tmp buffers of
+// the same length; hist needs radix_hist_words(n) words.  Result in
+// keys_out/vals_out.  Stable.
+size_t radix_hist_words(int64_t n);
+void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
+                uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, uint32_t *hist,
+                int64_t n, int key_bits, hipStream_t st);
+
+// First half kick + drift + walls + wrap + cell key (one thread per particle).
+void launch_prekick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
+                    uint32_t *keys, uint32_t *vals, bool integrate, hipStream_t st);
+// cell_start[c] = first sorted index of cell c, cell_start[ncell] = n.
+void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
+                        uint32_t *cell_start, hipStream_t st);
+// dst[p] = src[perm[p]] for every state plane; slot_of_gid[gid] = p.
+void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
+                    uint32_t *slot_of_gid, hipStream_t st);
+// Second half kick (mobile particles).
+void launch_postkick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
+                     hipStream_t st);
+
+// Pair forces and fluxes, one thread per particle (sorted order).
+void launch_pair_simple(const PairConst &pc, State s, const uint32_t *cell_keys,
+                        const uint32_t *cell_start, int64_t n, uint32_t k, float *F, float *Q,
+                        unsigned long long *nzero, uint32_t *err, hipStream_t st);
+// Pair forces and fluxes, cell-tiled kernel (one wavefront per home cell).
+void launch_pair_tiled(const PairConst &pc, State s, const uint32_t *cell_start, int64_t ncell,
+                       int64_t n, uint32_t k, float *F, float *Q, unsigned long long *nzero,
+                       uint32_t *err, hipStream_t st);
+// Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
+void launch_pair_emit(const PairConst &pc, State s, const uint32_t *cell_keys,
+                      const uint32_t *cell_start, int64_t n, float rcut2, int32_t *out,
+                      int64_t cap, unsigned long long *count, hipStream_t st);
+
+// FP64 diagnostics in fixed order: [P0,P1,P2, sum v^2, n_mobile, C_0..C_{S-1}]
+void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hipStream_t st);
+
+// Copy (AoS <-> SoA) in gid order.
+void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, int nspec,
+                             const float *F, const float *Q, float *pos, float *vel, float *conc,
+                             float *Fo, float *Qo, hipStream_t st);
+
+// ------------------------------------------------------------- membrane
+struct MeshDev {
+  int nv, ntri;
+  const int32_t *tri;        // [ntri][3]
+  const int32_t *bond_off;   // [nv+1]
+  const int32_t *bond_nbr;   // [nb]
+  const float2 *bond_par;    // [nb] (l_m, k_p)
+  const int32_t *tri_off;    // [nv+1]
+  const int4 *tri_inc;       // [nt] (b, c, tri index, -)
+  const int32_t *dih_off;    // [nv+1]
+  const int4 *dih_inc;       // [nd] (a, b, c, d)
+  const uint8_t *dih_role;   // [nd]
+  const float *A0t;          // [ntri]
+  float A0, V0, theta0;
+  float p, m_pow, kb, kg, kl, kv, gamma_t, gamma_c;
+};
+
+struct MembraneConst {
+  float L[3], invL[3];
+  float kT, dt;
+  uint32_t seed_lo, seed_hi, ctr3;
+  int terms;
+};
+
+// Per cell: FP64 total area/volume and centroid update (K-Gather).
+void launch_rbc_gather(const MembraneConst &mc, const MeshDev *meshes, const int32_t *rbc_mesh,
+                       const int64_t *rbc_first, int nrbc, State s, const uint32_t *slot_of_gid,
+                       double *av, double *centroid, hipStream_t st);
+// Per vertex: bonds, area/volume constraint forces (K-Apply) and bending,
+// added into F (sorted order).
+void launch_membrane_forces(const MembraneConst &mc, const MeshDev *meshes,
+                            const int32_t *rbc_mesh, const int64_t *rbc_first,
+                            const int64_t *rbc_voff, int nrbc, int64_t nvert_total, State s,
+                            const uint32_t *slot_of_gid, const double *av, uint32_t k, float *F,
+                            uint32_t *err, hipStream_t st);
+
+}  // namespace tdpd

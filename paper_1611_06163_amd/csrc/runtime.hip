@@ -1,0 +1,857 @@
+// runtime.hip -- host runtime behind the C ABI of include/tdpd.h: parameter
+// validation, device buffers, membrane topology, the per-step launch
+// sequence, state readback.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "launch.h"
+
+using namespace tdpd;
+
+namespace {
+
+struct HostMesh {
+  int nv = 0, ntri = 0;
+  std::vector<int32_t> tri;
+  std::vector<int32_t> bond_off, bond_nbr;
+  std::vector<float2> bond_par;
+  std::vector<int32_t> tri_off, dih_off;
+  std::vector<int4> tri_inc, dih_inc;
+  std::vector<uint8_t> dih_role;
+  std::vector<float> A0t;
+  std::vector<std::pair<int, int>> bfs;  // (vertex, parent) breadth-first order
+  double A0 = 0, V0 = 0, theta0 = 0, max_radius = 0;
+  tdpd_mesh_params mp{};
+  MeshDev dev{};  // device pointers once uploaded
+};
+
+static double d_theta(const double *a, const double *b, const double *c, const double *d) {
+  // signed angle between the outward normals of (a,b,c) and (d,c,b)
+  double ba[3], ca[3], cd[3], bd[3], n1[3], n2[3], e[3], x[3];
+  for (int q = 0; q < 3; ++q) {
+    ba[q] = b[q] - a[q]; ca[q] = c[q] - a[q];
+    cd[q] = c[q] - d[q]; bd[q] = b[q] - d[q];
+    e[q] = c[q] - b[q];
+  }
+  auto cr = [](const double *u, const double *v, double *o) {
+    o[0] = u[1] * v[2] - u[2] * v[1];
+    o[1] = u[2] * v[0] - u[0] * v[2];
+    o[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  cr(ba, ca, n1);
+  cr(cd, bd, n2);
+  cr(n1, n2, x);
+  const double le = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+  return std::atan2((x[0] * e[0] + x[1] * e[1] + x[2] * e[2]) / le,
+                    n1[0] * n2[0] + n1[1] * n2[1] + n1[2] * n2[2]);
+}
+
+}  // namespace
+
+struct tdpd_sys {
+  tdpd_params prm{};
+  PairConst pc{};
+  MembraneConst mc{};
+  hipStream_t st = nullptr;
+  tdpd_alloc_fn alloc = nullptr;
+  tdpd_free_fn free_fn = nullptr;
+  void *user = nullptr;
+  std::vector<void *> blocks;
+  std::string err;
+
+  int64_t n = 0;
+  int S = 1;
+  int64_t ncell = 0;
+  int key_bits = 1;
+  bool have_state = false, uploaded = false, forces_valid = false;
+  int64_t step = 0;
+
+  // host copies kept until upload
+  std::vector<float> h_pos, h_vel, h_conc;
+  std::vector<uint32_t> h_flags;
+
+  State A{}, B{};
+  bool cur_A = true;
+  float *F = nullptr, *Q = nullptr;
+  uint32_t *keys = nullptr, *vals = nullptr, *keys_tmp = nullptr, *vals_tmp = nullptr;
+  uint32_t *keys_s = nullptr, *perm = nullptr, *hist = nullptr, *cell_start = nullptr;
+  uint32_t *slot_of_gid = nullptr;
+  unsigned long long *nzero = nullptr, *pair_count = nullptr;
+  uint32_t *errw = nullptr;
+  double *diag_partial = nullptr, *diag_out = nullptr;
+
+  std::vector<HostMesh> meshes;
+  std::vector<int32_t> rbc_mesh;
+  std::vector<int64_t> rbc_first, rbc_voff;
+  MeshDev *d_meshes = nullptr;
+  int32_t *d_rbc_mesh = nullptr;
+  int64_t *d_rbc_first = nullptr, *d_rbc_voff = nullptr;
+  double *d_av = nullptr, *d_centroid = nullptr;
+  int64_t nvert = 0;
+  int pair_kernel = 1;  // 0: one thread per particle, 1: cell-tiled
+  // event timing per phase (index = log2 of TDPD_PHASE_*)
+  int timing_mask = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[4];
+  size_t ev_used[4] = {0, 0, 0, 0};
+
+  State &cur() { return cur_A ? A : B; }
+  State &nxt() { return cur_A ? B : A; }
+
+  int fail(int code, const std::string &m) {
+    err = m;
+    return code;
+  }
+  void *dalloc(size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~size_t(255);
+    void *p = nullptr;
+    if (alloc) {
+      p = alloc(bytes, user);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p) blocks.push_back(p);
+    return p;
+  }
+  void destroy_events() {
+    for (int q = 0; q < 4; ++q) {
+      for (auto &e : ev_pool[q]) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
+      ev_pool[q].clear();
+      ev_used[q] = 0;
+    }
+  }
+  // start/stop a timed phase; returns false if timing is off for it
+  bool phase_begin(int q) {
+    if (!(timing_mask & (1 << q))) return false;
+    if (ev_used[q] == ev_pool[q].size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return false;
+      ev_pool[q].push_back({a, b});
+    }
+    (void)hipEventRecord(ev_pool[q][ev_used[q]].first, st);
+    return true;
+  }
+  void phase_end(int q, bool on) {
+    if (!on) return;
+    (void)hipEventRecord(ev_pool[q][ev_used[q]].second, st);
+    ++ev_used[q];
+  }
+  void release_all() {
+    for (void *p : blocks) {
+      if (free_fn) free_fn(p, user);
+      else if (!alloc) (void)hipFree(p);
+    }
+    blocks.clear();
+  }
+};
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return s->fail(TDPD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static bool is_finite_f(float v) { return std::isfinite(v); }
+
+static float wrap_host(float x, float L) {
+  if (x < 0.f) x += L;
+  if (x >= L) x -= L;
+  if (x >= L || x < 0.f) x = 0.f;
+  return x;
+}
+
+extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn alloc,
+                           tdpd_free_fn free_fn, void *user, tdpd_sys **out) {
+  if (!p || !out) return TDPD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return TDPD_ERR_INVALID_ARG;
+  if (p->n_types < 1 || p->n_types > TDPD_MAX_TYPES || p->n_species < 1 ||
+      p->n_species > TDPD_MAX_SPECIES)
+    return TDPD_ERR_INVALID_ARG;
+  if (!(p->rc > 0.f) || !(p->rcc > 0.f) || !(p->dt > 0.f) || !(p->kT >= 0.f) ||
+      !(p->s_exp >= 0.f) || !(p->sc_exp >= 0.f) || !(p->m_s >= 0.f) || !(p->rho >= 0.f))
+    return TDPD_ERR_INVALID_ARG;
+  if (p->box_id >= (1u << 24)) return TDPD_ERR_INVALID_ARG;
+  if (p->wall_axis < -1 || p->wall_axis > 2) return TDPD_ERR_INVALID_ARG;
+  const int T = p->n_types;
+  for (int i = 0; i < T; ++i)
+    for (int j = 0; j < T; ++j) {
+      const float g = p->gamma[i * T + j], sg = p->sigma[i * T + j];
+      if (p->alpha[i * T + j] != p->alpha[j * T + i] || g != p->gamma[j * T + i] ||
+          sg != p->sigma[j * T + i] || g < 0.f)
+        return TDPD_ERR_INVALID_ARG;
+      // fluctuation-dissipation pairing, Eq. (6)
+      const double lhs = double(sg) * sg, rhs = 2.0 * p->kT * g;
+      if (std::fabs(lhs - rhs) > 1e-4 * std::max(1.0, std::max(lhs, rhs))) return TDPD_ERR_INVALID_ARG;
+      for (int sp = 0; sp < p->n_species; ++sp) {
+        const float k1 = p->kappa[(sp * T + i) * T + j], k2 = p->kappa[(sp * T + j) * T + i];
+        if (k1 != k2 || k1 < 0.f) return TDPD_ERR_INVALID_ARG;
+      }
+    }
+  const float rmax = std::max(p->rc, p->rcc);
+  int nc[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(p->box[a] > 0.f)) return TDPD_ERR_INVALID_ARG;
+    nc[a] = int(std::floor(double(p->box[a]) / (double(rmax) * (1.0 + 1e-4))));
+    if (nc[a] < 3) return TDPD_ERR_BOX_TOO_SMALL;
+  }
+  if (p->wall_axis >= 0 && !(p->wall_w > 0.f && 2.f * p->wall_w < p->box[p->wall_axis]))
+    return TDPD_ERR_INVALID_ARG;
+  tdpd_sys *s = new tdpd_sys();
+  s->prm = *p;
+  s->st = reinterpret_cast<hipStream_t>(hip_stream);
+  s->alloc = alloc;
+  s->free_fn = free_fn;
+  s->user = user;
+  s->S = p->n_species;
+  PairConst &pc = s->pc;
+  for (int a = 0; a < 3; ++a) {
+    pc.L[a] = p->box[a];
+    pc.invL[a] = 1.f / p->box[a];
+    pc.halfL[a] = 0.5f * p->box[a];
+    pc.nc[a] = nc[a];
+    pc.inv_h[a] = float(nc[a]) / p->box[a];
+    pc.body_force[a] = p->body_force[a];
+  }
+  s->ncell = int64_t(nc[0]) * nc[1] * nc[2];
+  s->key_bits = 1;
+  while ((int64_t(1) << s->key_bits) < s->ncell) ++s->key_bits;
+  pc.rc = p->rc;
+  pc.rcc = p->rcc;
+  pc.rc2 = p->rc * p->rc;
+  pc.rcc2 = p->rcc * p->rcc;
+  pc.rmax2 = std::max(pc.rc2, pc.rcc2);
+  pc.inv_rc = 1.f / p->rc;
+  pc.inv_rcc = 1.f / p->rcc;
+  pc.s_half = 0.5f * p->s_exp;
+  pc.sc_exp = p->sc_exp;
+  pc.sc_half = 0.5f * p->sc_exp;
+  pc.dt = p->dt;
+  pc.half_dt = 0.5f * p->dt;
+  pc.isdt = float(1.0 / std::sqrt(double(p->dt)));
+  pc.ms_rho = p->m_s * p->m_s * p->rho;
+  pc.n_types = T;
+  pc.n_species = p->n_species;
+  std::memcpy(pc.alpha, p->alpha, sizeof(pc.alpha));
+  std::memcpy(pc.gamma, p->gamma, sizeof(pc.gamma));
+  std::memcpy(pc.sigma, p->sigma, sizeof(pc.sigma));
+  std::memcpy(pc.kappa, p->kappa, sizeof(pc.kappa));
+  pc.wall_axis = p->wall_axis;
+  pc.wall_w = p->wall_w;
+  pc.seed_lo = uint32_t(p->seed & 0xffffffffu);
+  pc.seed_hi = uint32_t(p->seed >> 32);
+  pc.ctr3 = p->box_id << 8;
+  pc.terms = p->terms;
+  MembraneConst &mc = s->mc;
+  for (int a = 0; a < 3; ++a) {
+    mc.L[a] = pc.L[a];
+    mc.invL[a] = pc.invL[a];
+  }
+  mc.kT = p->kT;
+  mc.dt = p->dt;
+  mc.seed_lo = pc.seed_lo;
+  mc.seed_hi = pc.seed_hi;
+  mc.ctr3 = pc.ctr3;
+  mc.terms = p->terms;
+  if (const char *e = std::getenv("TDPD_PAIR_KERNEL")) s->pair_kernel = std::atoi(e);
+  *out = s;
+  return TDPD_OK;
+}
+
+extern "C" void tdpd_destroy(tdpd_sys *s) {
+  if (!s) return;
+  if (s->uploaded) (void)hipStreamSynchronize(s->st);
+  s->destroy_events();
+  s->release_all();
+  delete s;
+}
+
+extern "C" const char *tdpd_last_error(const tdpd_sys *s) { return s ? s->err.c_str() : "null system"; }
+extern "C" int64_t tdpd_num_particles(const tdpd_sys *s) { return s ? s->n : 0; }
+extern "C" int64_t tdpd_step_counter(const tdpd_sys *s) { return s ? s->step : 0; }
+
+extern "C" int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const float *vel,
+                              const float *conc, const uint32_t *flags) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (n < 0 || n >= (int64_t(1) << 31) || (n > 0 && (!pos || !vel || !conc || !flags)))
+    return s->fail(TDPD_ERR_INVALID_ARG, "set_state: bad size or null pointer");
+  const int S = s->S;
+  for (int64_t i = 0; i < n; ++i) {
+    if ((flags[i] & 0xffu) >= uint32_t(s->prm.n_types) || (flags[i] & ~0x1ffu))
+      return s->fail(TDPD_ERR_INVALID_ARG, "set_state: bad flags word");
+    for (int a = 0; a < 3; ++a)
+      if (!is_finite_f(pos[3 * i + a]) || !is_finite_f(vel[3 * i + a]))
+        return s->fail(TDPD_ERR_NONFINITE, "set_state: non-finite position or velocity");
+    for (int sp = 0; sp < S; ++sp)
+      if (!is_finite_f(conc[S * i + sp])) return s->fail(TDPD_ERR_NONFINITE, "set_state: non-finite concentration");
+  }
+  if (s->uploaded) (void)hipStreamSynchronize(s->st);
+  s->release_all();
+  s->uploaded = false;
+  s->forces_valid = false;
+  s->meshes.clear();
+  s->rbc_mesh.clear();
+  s->rbc_first.clear();
+  s->n = n;
+  s->step = 0;
+  s->h_pos.assign(pos, pos + 3 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      float x = s->h_pos[3 * i + a];
+      const float L = s->prm.box[a];
+      if (x < -L || x >= 2.f * L) x = x - L * std::floor(x / L);  // far outside: fold first
+      s->h_pos[3 * i + a] = wrap_host(x, L);
+    }
+  s->h_vel.assign(vel, vel + 3 * n);
+  s->h_conc.assign(conc, conc + int64_t(S) * n);
+  s->h_flags.assign(flags, flags + n);
+  for (int64_t i = 0; i < n; ++i)
+    if (s->h_flags[i] & TDPD_FLAG_FROZEN)
+      for (int a = 0; a < 3; ++a) s->h_vel[3 * i + a] = 0.f;
+  s->have_state = true;
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref, int32_t ntri,
+                             const int32_t *tri, const tdpd_mesh_params *mp, int32_t *mesh_id) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (!s->have_state || s->uploaded) return s->fail(TDPD_ERR_STATE, "add_mesh: call after set_state, before stepping");
+  if (nv < 4 || ntri < 4 || !ref || !tri || !mp || nv > 65535)
+    return s->fail(TDPD_ERR_INVALID_ARG, "add_mesh: bad sizes");
+  if (!(mp->p > 0.f) || !(mp->x0 > 0.f && mp->x0 < 1.f) || !(mp->m_pow > 0.f) ||
+      mp->gamma_t < 0.f || 3.f * mp->gamma_c < mp->gamma_t)
+    return s->fail(TDPD_ERR_INVALID_ARG, "add_mesh: bad membrane parameters");
+  HostMesh M;
+  M.nv = nv;
+  M.ntri = ntri;
+  M.mp = *mp;
+  M.tri.assign(tri, tri + 3 * ntri);
+  std::map<std::pair<int, int>, int> owner;  // directed edge -> triangle
+  for (int t = 0; t < ntri; ++t)
+    for (int e = 0; e < 3; ++e) {
+      const int a = tri[3 * t + e], b = tri[3 * t + (e + 1) % 3];
+      if (a < 0 || a >= nv || b < 0 || b >= nv || a == b || owner.count({a, b}))
+        return s->fail(TDPD_ERR_INVALID_ARG, "add_mesh: not a consistently oriented manifold");
+      owner[{a, b}] = t;
+    }
+  std::vector<std::vector<std::pair<int, int>>> bonds(nv);  // (nbr, edge index)
+  std::vector<double> l0;
+  std::vector<std::vector<int>> tris(nv);
+  std::vector<int4> dihs;  // (a, b, c, d)
+  for (auto &kv : owner) {
+    const int a = kv.first.first, b = kv.first.second;
+    if (a > b) continue;
+    auto it = owner.find({b, a});
+    if (it == owner.end()) return s->fail(TDPD_ERR_INVALID_ARG, "add_mesh: surface not closed");
+    const int t1 = kv.second, t2 = it->second;
+    int a0 = -1, d0 = -1;
+    for (int e = 0; e < 3; ++e) {
+      if (tri[3 * t1 + e] != a && tri[3 * t1 + e] != b) a0 = tri[3 * t1 + e];
+      if (tri[3 * t2 + e] != a && tri[3 * t2 + e] != b) d0 = tri[3 * t2 + e];
+    }
+    const int ei = int(l0.size());
+    double d[3];
+    for (int q = 0; q < 3; ++q) d[q] = ref[3 * b + q] - ref[3 * a + q];
+    l0.push_back(std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]));
+    bonds[a].push_back({b, ei});
+    bonds[b].push_back({a, ei});
+    dihs.push_back(make_int4(a0, a, b, d0));  // t1 = (a0, a, b) holds a->b
+  }
+  // breadth-first order over bonds (for unwrapping at upload)
+  {
+    std::vector<char> seen(nv, 0);
+    M.bfs.push_back({0, -1});
+    seen[0] = 1;
+    for (size_t q = 0; q < M.bfs.size(); ++q) {
+      const int v = M.bfs[q].first;
+      for (auto &nb : bonds[v])
+        if (!seen[nb.first]) {
+          seen[nb.first] = 1;
+          M.bfs.push_back({nb.first, v});
+        }
+    }
+    if (int(M.bfs.size()) != nv) return s->fail(TDPD_ERR_INVALID_ARG, "add_mesh: surface not connected");
+  }
+  const double kT = s->prm.kT, x0 = mp->x0;
+  const double fwlc0 = kT / mp->p * (0.25 / ((1 - x0) * (1 - x0)) - 0.25 + x0);
+  M.bond_off.assign(nv + 1, 0);
+  for (int v = 0; v < nv; ++v) {
+    M.bond_off[v] = int(M.bond_nbr.size());
+    for (auto &nb : bonds[v]) {
+      const double L0 = l0[nb.second];
+      M.bond_nbr.push_back(nb.first);
+      M.bond_par.push_back(make_float2(float(L0 / x0), float(fwlc0 * std::pow(L0, double(mp->m_pow)))));
+    }
+  }
+  M.bond_off[nv] = int(M.bond_nbr.size());
+  // triangles: per-vertex incidences (other two vertices, counter-clockwise)
+  M.A0 = 0;
+  M.V0 = 0;
+  M.A0t.resize(ntri);
+  for (int t = 0; t < ntri; ++t) {
+    const double *a = ref + 3 * tri[3 * t], *b = ref + 3 * tri[3 * t + 1], *c = ref + 3 * tri[3 * t + 2];
+    const double u[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double w[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const double nn[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    const double At = 0.5 * std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    M.A0t[t] = float(At);
+    M.A0 += At;
+    M.V0 += (a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+             a[2] * (b[0] * c[1] - b[1] * c[0])) / 6.0;
+    for (int e = 0; e < 3; ++e) tris[tri[3 * t + e]].push_back(t);
+  }
+  M.tri_off.assign(nv + 1, 0);
+  for (int v = 0; v < nv; ++v) {
+    M.tri_off[v] = int(M.tri_inc.size());
+    for (int t : tris[v]) {
+      int e = 0;
+      while (tri[3 * t + e] != v) ++e;
+      M.tri_inc.push_back(make_int4(tri[3 * t + (e + 1) % 3], tri[3 * t + (e + 2) % 3], t, 0));
+    }
+  }
+  M.tri_off[nv] = int(M.tri_inc.size());
+  // dihedrals: per-vertex incidences with the vertex's role
+  std::vector<std::vector<std::pair<int, int>>> dv(nv);  // (dihedral, role)
+  double th_sum = 0;
+  for (size_t q = 0; q < dihs.size(); ++q) {
+    const int4 D = dihs[q];
+    dv[D.x].push_back({int(q), 0});
+    dv[D.y].push_back({int(q), 1});
+    dv[D.z].push_back({int(q), 2});
+    dv[D.w].push_back({int(q), 3});
+    th_sum += d_theta(ref + 3 * D.x, ref + 3 * D.y, ref + 3 * D.z, ref + 3 * D.w);
+  }
+  M.theta0 = std::isnan(mp->theta0) ? th_sum / double(dihs.size()) : double(mp->theta0);
+  M.dih_off.assign(nv + 1, 0);
+  for (int v = 0; v < nv; ++v) {
+    M.dih_off[v] = int(M.dih_inc.size());
+    for (auto &pr : dv[v]) {
+      M.dih_inc.push_back(dihs[pr.first]);
+      M.dih_role.push_back(uint8_t(pr.second));
+    }
+  }
+  M.dih_off[nv] = int(M.dih_inc.size());
+  // largest distance from the rest centroid (for the periodic-image limit)
+  double cen[3] = {0, 0, 0};
+  for (int v = 0; v < nv; ++v)
+    for (int q = 0; q < 3; ++q) cen[q] += ref[3 * v + q] / nv;
+  for (int v = 0; v < nv; ++v) {
+    double r2 = 0;
+    for (int q = 0; q < 3; ++q) r2 += (ref[3 * v + q] - cen[q]) * (ref[3 * v + q] - cen[q]);
+    M.max_radius = std::max(M.max_radius, std::sqrt(r2));
+  }
+  for (int a = 0; a < 3; ++a)
+    if (1.25 * M.max_radius + 1.0 > 0.5 * s->prm.box[a])
+      return s->fail(TDPD_ERR_UNSUPPORTED, "add_mesh: cell too large for the periodic box");
+  s->meshes.push_back(std::move(M));
+  if (mesh_id) *mesh_id = int32_t(s->meshes.size() - 1);
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_add_rbc(tdpd_sys *s, int32_t mesh_id, int64_t first_gid, int32_t *rbc_id) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (!s->have_state || s->uploaded) return s->fail(TDPD_ERR_STATE, "add_rbc: call after set_state, before stepping");
+  if (mesh_id < 0 || mesh_id >= int(s->meshes.size())) return s->fail(TDPD_ERR_INVALID_ARG, "add_rbc: bad mesh id");
+  const int nv = s->meshes[mesh_id].nv;
+  if (first_gid < 0 || first_gid + nv > s->n) return s->fail(TDPD_ERR_INVALID_ARG, "add_rbc: gid range outside the state");
+  if (s->rbc_mesh.size() >= 65534) return s->fail(TDPD_ERR_UNSUPPORTED, "add_rbc: too many cells");
+  for (int64_t g = first_gid; g < first_gid + nv; ++g)
+    if ((s->h_flags[g] >> 16) != 0 || (s->h_flags[g] & TDPD_FLAG_FROZEN))
+      return s->fail(TDPD_ERR_INVALID_ARG, "add_rbc: particle already bound or frozen");
+  const uint32_t body = uint32_t(s->rbc_mesh.size()) + 1;
+  for (int64_t g = first_gid; g < first_gid + nv; ++g) s->h_flags[g] |= body << 16;
+  s->rbc_mesh.push_back(mesh_id);
+  s->rbc_first.push_back(first_gid);
+  if (rbc_id) *rbc_id = int32_t(s->rbc_mesh.size() - 1);
+  return TDPD_OK;
+}
+
+template <class T>
+static T *dallocT(tdpd_sys *s, size_t count) {
+  return static_cast<T *>(s->dalloc(sizeof(T) * (count ? count : 1)));
+}
+
+template <class T>
+static int upload(tdpd_sys *s, T **dst, const std::vector<T> &v) {
+  *dst = dallocT<T>(s, v.size());
+  if (!*dst) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s->st));
+  return TDPD_OK;
+}
+
+static int alloc_state(tdpd_sys *s, State &st) {
+  const int64_t n = s->n;
+  float *blk = dallocT<float>(s, size_t(6 + s->S) * n);
+  uint32_t *ib = dallocT<uint32_t>(s, size_t(2) * n);
+  if (!blk || !ib) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  st.x = blk;
+  st.y = blk + n;
+  st.z = blk + 2 * n;
+  st.vx = blk + 3 * n;
+  st.vy = blk + 4 * n;
+  st.vz = blk + 5 * n;
+  st.C = blk + 6 * n;
+  st.gid = ib;
+  st.info = ib + n;
+  return TDPD_OK;
+}
+
+// Allocate device memory and upload state and membranes (once per set_state).
+static int prepare(tdpd_sys *s) {
+  if (!s->have_state) return s->fail(TDPD_ERR_STATE, "no state: call tdpd_set_state first");
+  if (s->uploaded) return TDPD_OK;
+  const int64_t n = s->n;
+  const int S = s->S;
+  int rc;
+  if ((rc = alloc_state(s, s->A)) || (rc = alloc_state(s, s->B))) return rc;
+  s->cur_A = true;
+  s->F = dallocT<float>(s, 3 * size_t(n));
+  s->Q = dallocT<float>(s, size_t(S) * n);
+  s->keys = dallocT<uint32_t>(s, n);
+  s->vals = dallocT<uint32_t>(s, n);
+  s->keys_tmp = dallocT<uint32_t>(s, n);
+  s->vals_tmp = dallocT<uint32_t>(s, n);
+  s->keys_s = dallocT<uint32_t>(s, n);
+  s->perm = dallocT<uint32_t>(s, n);
+  s->hist = dallocT<uint32_t>(s, radix_hist_words(n));
+  s->cell_start = dallocT<uint32_t>(s, size_t(s->ncell) + 1);
+  s->slot_of_gid = dallocT<uint32_t>(s, n);
+  s->nzero = dallocT<unsigned long long>(s, 2);
+  s->pair_count = s->nzero + 1;
+  s->errw = dallocT<uint32_t>(s, 1);
+  s->diag_partial = dallocT<double>(s, size_t((n + 1023) / 1024 + 1) * (5 + kMaxS));
+  s->diag_out = dallocT<double>(s, 5 + kMaxS);
+  if (!s->F || !s->Q || !s->keys || !s->vals || !s->keys_tmp || !s->vals_tmp || !s->keys_s ||
+      !s->perm || !s->hist || !s->cell_start || !s->slot_of_gid || !s->nzero || !s->errw ||
+      !s->diag_partial || !s->diag_out)
+    return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  // SoA planes in gid order
+  std::vector<float> planes(size_t(6 + S) * n);
+  std::vector<uint32_t> ints(2 * size_t(n));
+  for (int64_t i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a) {
+      planes[a * n + i] = s->h_pos[3 * i + a];
+      planes[(3 + a) * n + i] = s->h_vel[3 * i + a];
+    }
+    for (int sp = 0; sp < S; ++sp) planes[(6 + sp) * n + i] = s->h_conc[S * i + sp];
+    ints[i] = uint32_t(i);
+    ints[n + i] = s->h_flags[i];
+  }
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(s->A.x, planes.data(), sizeof(float) * planes.size(), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->A.gid, ints.data(), sizeof(uint32_t) * ints.size(), hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->slot_of_gid, ints.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemsetAsync(s->F, 0, sizeof(float) * 3 * n, s->st));
+    HIPCHK(hipMemsetAsync(s->Q, 0, sizeof(float) * S * n, s->st));
+  }
+  HIPCHK(hipMemsetAsync(s->nzero, 0, 2 * sizeof(unsigned long long), s->st));
+  HIPCHK(hipMemsetAsync(s->errw, 0, sizeof(uint32_t), s->st));
+  // membranes
+  const int nrbc = int(s->rbc_mesh.size());
+  s->nvert = 0;
+  if (nrbc > 0) {
+    std::vector<MeshDev> md(s->meshes.size());
+    for (size_t m = 0; m < s->meshes.size(); ++m) {
+      HostMesh &M = s->meshes[m];
+      MeshDev &D = md[m];
+      int32_t *tri, *bo, *bn, *to, *dof;
+      float2 *bp;
+      int4 *ti, *di;
+      uint8_t *dr;
+      float *a0t;
+      if ((rc = upload(s, &tri, M.tri)) || (rc = upload(s, &bo, M.bond_off)) ||
+          (rc = upload(s, &bn, M.bond_nbr)) || (rc = upload(s, &bp, M.bond_par)) ||
+          (rc = upload(s, &to, M.tri_off)) || (rc = upload(s, &ti, M.tri_inc)) ||
+          (rc = upload(s, &dof, M.dih_off)) || (rc = upload(s, &di, M.dih_inc)) ||
+          (rc = upload(s, &dr, M.dih_role)) || (rc = upload(s, &a0t, M.A0t)))
+        return rc;
+      D.nv = M.nv;
+      D.ntri = M.ntri;
+      D.tri = tri;
+      D.bond_off = bo;
+      D.bond_nbr = bn;
+      D.bond_par = bp;
+      D.tri_off = to;
+      D.tri_inc = ti;
+      D.dih_off = dof;
+      D.dih_inc = di;
+      D.dih_role = dr;
+      D.A0t = a0t;
+      D.A0 = float(M.A0);
+      D.V0 = float(M.V0);
+      D.theta0 = float(M.theta0);
+      D.p = M.mp.p;
+      D.m_pow = M.mp.m_pow;
+      D.kb = M.mp.kb;
+      D.kg = M.mp.kg;
+      D.kl = M.mp.kl;
+      D.kv = M.mp.kv;
+      D.gamma_t = M.mp.gamma_t;
+      D.gamma_c = M.mp.gamma_c;
+      M.dev = D;
+    }
+    s->rbc_voff.assign(nrbc + 1, 0);
+    std::vector<double> cen(3 * size_t(nrbc));
+    for (int r = 0; r < nrbc; ++r) {
+      const HostMesh &M = s->meshes[s->rbc_mesh[r]];
+      s->rbc_voff[r + 1] = s->rbc_voff[r] + M.nv;
+      // unwrapped centroid: breadth-first along bonds at nearest images
+      std::vector<double> u(3 * size_t(M.nv));
+      const int64_t g0 = s->rbc_first[r];
+      for (auto &vp : M.bfs) {
+        const int v = vp.first, par = vp.second;
+        for (int a = 0; a < 3; ++a) {
+          const double x = s->h_pos[3 * (g0 + v) + a];
+          if (par < 0) {
+            u[3 * v + a] = x;
+          } else {
+            const double L = s->prm.box[a];
+            double d = x - s->h_pos[3 * (g0 + par) + a];
+            d -= L * std::nearbyint(d / L);
+            u[3 * v + a] = u[3 * par + a] + d;
+          }
+        }
+      }
+      for (int a = 0; a < 3; ++a) {
+        double c = 0;
+        for (int v = 0; v < M.nv; ++v) c += u[3 * v + a];
+        c /= M.nv;
+        const double L = s->prm.box[a];
+        c -= L * std::floor(c / L);
+        cen[3 * r + a] = c;
+        for (int v = 0; v < M.nv; ++v)
+          if (std::fabs(u[3 * v + a] - c - L * std::nearbyint((u[3 * v + a] - c) / L)) > 0.45 * L)
+            return s->fail(TDPD_ERR_UNSUPPORTED, "add_rbc: cell spans half the box");
+      }
+    }
+    s->nvert = s->rbc_voff[nrbc];
+    if ((rc = upload(s, &s->d_meshes, md)) || (rc = upload(s, &s->d_rbc_mesh, s->rbc_mesh)) ||
+        (rc = upload(s, &s->d_rbc_first, s->rbc_first)) || (rc = upload(s, &s->d_rbc_voff, s->rbc_voff)) ||
+        (rc = upload(s, &s->d_centroid, cen)))
+      return rc;
+    s->d_av = dallocT<double>(s, 2 * size_t(nrbc));
+    if (!s->d_av) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+    HIPCHK(hipMemsetAsync(s->d_av, 0, sizeof(double) * 2 * nrbc, s->st));
+  }
+  HIPCHK(hipStreamSynchronize(s->st));  // host vectors may be released after this
+  s->uploaded = true;
+  return TDPD_OK;
+}
+
+// One force evaluation at step counter k, optionally wrapped in the two
+// velocity-Verlet half kicks.
+static int evaluate(tdpd_sys *s, uint32_t k, bool integrate) {
+  const int64_t n = s->n;
+  if (n == 0) {
+    s->forces_valid = true;
+    return TDPD_OK;
+  }
+  hipStream_t st = s->st;
+  const bool tb = s->phase_begin(1);
+  launch_prekick(s->pc, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate, st);
+  radix_sort(s->keys, s->vals, s->keys_tmp, s->vals_tmp, s->keys_s, s->perm, s->hist, n,
+             s->key_bits, st);
+  launch_cell_bounds(s->keys_s, n, s->ncell, s->cell_start, st);
+  launch_reorder(s->cur(), s->nxt(), s->perm, n, s->S, s->slot_of_gid, st);
+  s->phase_end(1, tb);
+  s->cur_A = !s->cur_A;
+  const bool tp = s->phase_begin(0);
+  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
+  // one-thread-per-particle kernel
+  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
+  // it also packs a particle slot into 26 bits of a ring entry
+  if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26))
+    launch_pair_simple(s->pc, s->cur(), s->keys_s, s->cell_start, n, k, s->F, s->Q, s->nzero,
+                       s->errw, st);
+  else
+    launch_pair_tiled(s->pc, s->cur(), s->cell_start, s->ncell, n, k, s->F, s->Q, s->nzero,
+                      s->errw, st);
+  s->phase_end(0, tp);
+  const int nrbc = int(s->rbc_mesh.size());
+  const bool tm = nrbc > 0 && s->phase_begin(2);
+  if (nrbc > 0) {
+    launch_rbc_gather(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, nrbc, s->cur(),
+                      s->slot_of_gid, s->d_av, s->d_centroid, st);
+    launch_membrane_forces(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, s->d_rbc_voff, nrbc,
+                           s->nvert, s->cur(), s->slot_of_gid, s->d_av, k, s->F, s->errw, st);
+  }
+  s->phase_end(2, tm);
+  const bool tk = integrate && s->phase_begin(3);
+  if (integrate) launch_postkick(s->pc, s->cur(), s->F, s->Q, n, st);
+  s->phase_end(3, tk);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return s->fail(TDPD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  s->forces_valid = true;
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_compute_forces(tdpd_sys *s, uint32_t k) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  int rc = prepare(s);
+  if (rc) return rc;
+  return evaluate(s, k, false);
+}
+
+extern "C" int tdpd_step(tdpd_sys *s, int32_t n_steps) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (n_steps < 0) return s->fail(TDPD_ERR_INVALID_ARG, "step: negative count");
+  int rc = prepare(s);
+  if (rc) return rc;
+  if (!s->forces_valid && (rc = evaluate(s, 0, false))) return rc;
+  for (int i = 0; i < n_steps; ++i) {
+    if (s->step >= 0xffffffffLL) return s->fail(TDPD_ERR_UNSUPPORTED, "step counter exhausted");
+    ++s->step;
+    if ((rc = evaluate(s, uint32_t(s->step), true))) return rc;
+  }
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_sync(tdpd_sys *s) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (!s->uploaded) return TDPD_OK;
+  HIPCHK(hipStreamSynchronize(s->st));
+  uint32_t e = 0;
+  HIPCHK(hipMemcpy(&e, s->errw, sizeof(e), hipMemcpyDeviceToHost));
+  if (e) {
+    HIPCHK(hipMemset(s->errw, 0, sizeof(uint32_t)));
+    if (e & kErrOverext) return s->fail(TDPD_ERR_BOND_OVEREXTENDED, "a membrane bond reached its maximum extension");
+    if (e & kErrNonfinite) return s->fail(TDPD_ERR_NONFINITE, "a force became non-finite");
+  }
+  return TDPD_OK;
+}
+
+static int ensure_forces(tdpd_sys *s) {
+  int rc = prepare(s);
+  if (rc) return rc;
+  if (!s->forces_valid && (rc = evaluate(s, 0, false))) return rc;
+  return tdpd_sync(s);
+}
+
+static int readback(tdpd_sys *s, float *pos, float *vel, float *conc, float *F, float *Q) {
+  int rc = ensure_forces(s);
+  if (rc) return rc;
+  const int64_t n = s->n;
+  if (n == 0) return TDPD_OK;
+  const int S = s->S;
+  // temporary device AoS buffers, then one copy each
+  float *buf = dallocT<float>(s, size_t(n) * (9 + 2 * S));
+  if (!buf) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  float *dp = buf, *dv = buf + 3 * n, *dc = buf + 6 * n, *dF = dc + S * n, *dQ = dF + 3 * n;
+  launch_gather_gid_order(s->cur(), s->slot_of_gid, n, S, s->F, s->Q, pos ? dp : nullptr,
+                          vel ? dv : nullptr, conc ? dc : nullptr, F ? dF : nullptr,
+                          Q ? dQ : nullptr, s->st);
+  hipError_t e = hipSuccess;
+  if (pos && e == hipSuccess) e = hipMemcpyAsync(pos, dp, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, s->st);
+  if (vel && e == hipSuccess) e = hipMemcpyAsync(vel, dv, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, s->st);
+  if (conc && e == hipSuccess) e = hipMemcpyAsync(conc, dc, sizeof(float) * S * n, hipMemcpyDeviceToHost, s->st);
+  if (F && e == hipSuccess) e = hipMemcpyAsync(F, dF, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, s->st);
+  if (Q && e == hipSuccess) e = hipMemcpyAsync(Q, dQ, sizeof(float) * S * n, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  // release the temporary
+  s->blocks.pop_back();
+  if (s->free_fn) s->free_fn(buf, s->user);
+  else if (!s->alloc) (void)hipFree(buf);
+  if (e != hipSuccess) return s->fail(TDPD_ERR_HIP, std::string("readback: ") + hipGetErrorString(e));
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_get_state(tdpd_sys *s, float *pos, float *vel, float *conc) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  return readback(s, pos, vel, conc, nullptr, nullptr);
+}
+
+extern "C" int tdpd_get_forces(tdpd_sys *s, float *F, float *Q) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  return readback(s, nullptr, nullptr, nullptr, F, Q);
+}
+
+extern "C" int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *ij, int64_t *n_out) {
+  if (!s || !n_out || cap < 0 || (cap > 0 && !ij) || (which != 0 && which != 1)) return TDPD_ERR_INVALID_ARG;
+  int rc = ensure_forces(s);
+  if (rc) return rc;
+  *n_out = 0;
+  if (s->n == 0) return TDPD_OK;
+  int32_t *dout = dallocT<int32_t>(s, 2 * size_t(cap > 0 ? cap : 1));
+  if (!dout) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  HIPCHK(hipMemsetAsync(s->pair_count, 0, sizeof(unsigned long long), s->st));
+  launch_pair_emit(s->pc, s->cur(), s->keys_s, s->cell_start, s->n, which ? s->pc.rcc2 : s->pc.rc2,
+                   dout, cap, s->pair_count, s->st);
+  unsigned long long cnt = 0;
+  hipError_t e = hipMemcpyAsync(&cnt, s->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  const int64_t m = std::min<int64_t>(int64_t(cnt), cap);
+  if (e == hipSuccess && m > 0) e = hipMemcpy(ij, dout, sizeof(int32_t) * 2 * m, hipMemcpyDeviceToHost);
+  s->blocks.pop_back();
+  if (s->free_fn) s->free_fn(dout, s->user);
+  else if (!s->alloc) (void)hipFree(dout);
+  if (e != hipSuccess) return s->fail(TDPD_ERR_HIP, std::string("get_pairs: ") + hipGetErrorString(e));
+  *n_out = int64_t(cnt);
+  if (int64_t(cnt) > cap) return s->fail(TDPD_ERR_CAPACITY, "get_pairs: buffer too small");
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_diagnostics(tdpd_sys *s, double *out, int64_t cap) {
+  if (!s || !out) return TDPD_ERR_INVALID_ARG;
+  const int S = s->S;
+  const int nrbc = int(s->rbc_mesh.size());
+  const int64_t need = 4 + S + 2 * int64_t(nrbc);
+  if (cap < need) return s->fail(TDPD_ERR_CAPACITY, "diagnostics: buffer too small");
+  int rc = ensure_forces(s);
+  if (rc) return rc;
+  double d[5 + kMaxS];
+  launch_diag(s->cur(), s->n, S, s->diag_partial, s->diag_out, s->st);
+  HIPCHK(hipMemcpyAsync(d, s->diag_out, sizeof(double) * (5 + S), hipMemcpyDeviceToHost, s->st));
+  if (nrbc > 0)
+    HIPCHK(hipMemcpyAsync(out + 4 + S, s->d_av, sizeof(double) * 2 * nrbc, hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  const double nm = d[4];
+  out[0] = d[0];
+  out[1] = d[1];
+  out[2] = d[2];
+  out[3] = nm > 1 ? (d[3] - (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / nm) / (3.0 * (nm - 1)) : 0.0;
+  for (int sp = 0; sp < S; ++sp) out[4 + sp] = d[5 + sp];
+  return TDPD_OK;
+}
+
+extern "C" int64_t tdpd_coincident_pairs(tdpd_sys *s) {
+  if (!s || !s->uploaded) return 0;
+  unsigned long long v = 0;
+  if (hipStreamSynchronize(s->st) != hipSuccess) return -1;
+  if (hipMemcpy(&v, s->nzero, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  return int64_t(v);
+}
+
+extern "C" int tdpd_set_timing(tdpd_sys *s, int32_t mask) {
+  if (!s || mask < 0 || mask > 15) return TDPD_ERR_INVALID_ARG;
+  s->timing_mask = mask;
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_get_timing(tdpd_sys *s, int32_t phase, double *total_ms, int64_t *launches) {
+  if (!s || !total_ms || !launches) return TDPD_ERR_INVALID_ARG;
+  int q = -1;
+  for (int b = 0; b < 4; ++b)
+    if (phase == (1 << b)) q = b;
+  if (q < 0) return s->fail(TDPD_ERR_INVALID_ARG, "get_timing: phase must be one TDPD_PHASE_* bit");
+  HIPCHK(hipStreamSynchronize(s->st));
+  double tot = 0;
+  for (size_t i = 0; i < s->ev_used[q]; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->ev_pool[q][i].first, s->ev_pool[q][i].second));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *launches = int64_t(s->ev_used[q]);
+  s->ev_used[q] = 0;
+  return TDPD_OK;
+}

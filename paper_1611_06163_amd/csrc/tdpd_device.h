@@ -1,0 +1,130 @@
+// tdpd_device.h -- device-side data structures and inline math shared by the
+// HIP kernels of the tDPD + RBC library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tdpd.h"
+
+namespace tdpd {
+
+constexpr uint32_t kFrozen = 1u << 8;
+constexpr int kMaxT = TDPD_MAX_TYPES;
+constexpr int kMaxS = TDPD_MAX_SPECIES;
+
+// info word of a particle: type (bits 0-7) | frozen (bit 8) | (body + 1) << 16
+__host__ __device__ inline int info_type(uint32_t w) { return int(w & 0xffu); }
+__host__ __device__ inline bool info_frozen(uint32_t w) { return (w & kFrozen) != 0; }
+__host__ __device__ inline int info_body(uint32_t w) { return int(w >> 16) - 1; }
+
+// Error bits written by kernels (sticky until the host reads them).
+constexpr uint32_t kErrOverext = 1u;
+constexpr uint32_t kErrNonfinite = 2u;
+
+// Parameters of the pair kernel and integrator, passed by value.
+struct PairConst {
+  float L[3], invL[3], halfL[3];
+  int nc[3];          // cells per axis
+  float inv_h[3];     // cells per unit length
+  float rc, rcc, rc2, rcc2, rmax2;
+  float inv_rc, inv_rcc;
+  float s_half;       // w_R = w^(s/2)
+  float sc_exp, sc_half;
+  float isdt;         // 1/sqrt(dt)
+  float dt, half_dt;
+  float ms_rho;       // m_s^2 * rho
+  int n_types, n_species;
+  float alpha[kMaxT * kMaxT], gamma[kMaxT * kMaxT], sigma[kMaxT * kMaxT];
+  float kappa[kMaxS * kMaxT * kMaxT];
+  float body_force[3];
+  int wall_axis;
+  float wall_w;
+  uint32_t seed_lo, seed_hi, ctr3;  // ctr3 = box_id << 8
+  int terms;
+};
+
+// State planes of one particle ordering.
+struct State {
+  float *x, *y, *z, *vx, *vy, *vz;
+  float *C;            // [S][N]
+  uint32_t *gid, *info;
+};
+
+// ------------------------------------------------------------------ Philox
+// Philox-4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products whose high halves are mixed into the other counter words with
+// the round key; the key advances by the Weyl constants between rounds.
+struct u32x4 {
+  uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c0;
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c2;
+    const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+    c1 = uint32_t(p1);
+    c3 = uint32_t(p0);
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// uniform in (0,1): (2*(bits>>9)+1) * 2^-24, exact in FP32
+__device__ __forceinline__ float u01(uint32_t bits) {
+  return float((bits >> 9) * 2u + 1u) * 5.9604644775390625e-8f;
+}
+
+// Box-Muller normal from two words.  v_log_f32 is log2; v_cos_f32 takes its
+// argument in revolutions, so cos(2 pi u) is one instruction.
+__device__ __forceinline__ float gauss(uint32_t w0, uint32_t w1) {
+  const float u0 = u01(w0), u1 = u01(w1);
+  const float r2 = -1.3862943611198906f * __builtin_amdgcn_logf(u0);  // -2 ln u0
+  return __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_cosf(u1);
+}
+
+// ------------------------------------------------------------ predicate
+// FP32 displacement component x_j + s - x_i, rounded exactly as specified
+// (no contraction), s the periodic image shift.
+__device__ __forceinline__ float disp(float xj, float s, float xi) {
+  return __fsub_rn(__fadd_rn(xj, s), xi);
+}
+__device__ __forceinline__ float dist2(float dx, float dy, float dz) {
+  return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
+}
+
+// w^e for w in [0,1]; zero at w <= 0
+__device__ __forceinline__ float powu(float w, float e) {
+  return w > 0.f ? __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(w)) : 0.f;
+}
+
+// x^e for x > 0 (any e); zero at x <= 0
+__device__ __forceinline__ float powu_any(float x, float e) {
+  return x > 0.f ? __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(x)) : 0.f;
+}
+
+__device__ __forceinline__ float wrap_coord(float x, float L) {
+  if (x < 0.f) x += L;
+  if (x >= L) x -= L;
+  if (x >= L || x < 0.f) x = 0.f;
+  return x;
+}
+
+__device__ __forceinline__ int cell_coord(float x, float inv_h, int n) {
+  int c = int(x * inv_h);
+  c = c < 0 ? 0 : c;
+  return c >= n ? n - 1 : c;
+}
+
+__device__ __forceinline__ float min_image(float d, float L, float invL) {
+  return d - L * rintf(d * invL);
+}
+
+}  // namespace tdpd

@@ -220,8 +220,12 @@ def place_cells(template, n_cells, box, rng, lo=None, hi=None, min_sep=0.9,
         pts = pts + c
         if tree is not None:
             w = np.mod(pts, box)
-            d, _ = tree.query(w, k=1)
-            if np.min(d) < min_sep:
+            # a coarse subset rejects most overlapping tries cheaply
+            d, _ = tree.query(w[::16], k=1, distance_upper_bound=min_sep)
+            if np.isfinite(d).any():
+                continue
+            d, _ = tree.query(w, k=1, distance_upper_bound=min_sep)
+            if np.isfinite(d).any():
                 continue
         placed.append(pts)
         all_pts = np.concatenate([all_pts, np.mod(pts, box)])

@@ -1,0 +1,264 @@
+"""Python binding of libtdpd.so (include/tdpd.h): argument marshalling only.
+
+Every function below forwards to the C entry point of the same name; all
+computation runs in the library's HIP kernels.  Device memory comes from
+torch's caching allocator through the library's allocator callback, and
+kernels are enqueued on torch's current HIP stream.  The library must have
+been built (paper_1611_06163_amd/build.py); importing this module on a
+machine where it is missing raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdpd.so")
+
+MAX_TYPES, MAX_SPECIES = 4, 8
+TERM = dict(cons=1, diss=2, rand=4, fick=8, frand=16, bond=32, bvisc=64, brand=128,
+            area=256, vol=512, bend=1024, body=2048)
+TERMS_ALL = 4095
+FLAG_FROZEN = 1 << 8
+PHASE = dict(pair=1, bin=2, membrane=4, kick=8)
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BOX_TOO_SMALL", -3: "OOM", -4: "HIP",
+          -5: "NONFINITE", -6: "BOND_OVEREXTENDED", -7: "STATE", -8: "UNSUPPORTED",
+          -9: "CAPACITY"}
+
+
+class TdpdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class tdpd_params(C.Structure):
+    _fields_ = [
+        ("box", C.c_float * 3), ("rc", C.c_float), ("rcc", C.c_float), ("dt", C.c_float),
+        ("kT", C.c_float), ("rho", C.c_float), ("m_s", C.c_float), ("s_exp", C.c_float),
+        ("sc_exp", C.c_float), ("n_types", C.c_int32), ("n_species", C.c_int32),
+        ("alpha", C.c_float * (MAX_TYPES * MAX_TYPES)),
+        ("gamma", C.c_float * (MAX_TYPES * MAX_TYPES)),
+        ("sigma", C.c_float * (MAX_TYPES * MAX_TYPES)),
+        ("kappa", C.c_float * (MAX_SPECIES * MAX_TYPES * MAX_TYPES)),
+        ("body_force", C.c_float * 3), ("wall_axis", C.c_int32), ("wall_w", C.c_float),
+        ("seed", C.c_uint64), ("box_id", C.c_uint32), ("terms", C.c_int32),
+    ]
+
+
+class tdpd_mesh_params(C.Structure):
+    _fields_ = [(f, C.c_float) for f in
+                ("p", "x0", "m_pow", "kb", "theta0", "kg", "kl", "kv", "gamma_t", "gamma_c")]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """Load libtdpd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1611_06163_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "tdpd_create": (C.c_int, [C.POINTER(tdpd_params), P, ALLOC_FN, FREE_FN, P,
+                                      C.POINTER(P)]),
+            "tdpd_set_state": (C.c_int, [P, I64, P, P, P, P]),
+            "tdpd_add_mesh": (C.c_int, [P, I32, P, I32, P, C.POINTER(tdpd_mesh_params),
+                                        C.POINTER(I32)]),
+            "tdpd_add_rbc": (C.c_int, [P, I32, I64, C.POINTER(I32)]),
+            "tdpd_compute_forces": (C.c_int, [P, C.c_uint32]),
+            "tdpd_step": (C.c_int, [P, I32]),
+            "tdpd_sync": (C.c_int, [P]),
+            "tdpd_get_state": (C.c_int, [P, P, P, P]),
+            "tdpd_get_forces": (C.c_int, [P, P, P]),
+            "tdpd_get_pairs": (C.c_int, [P, I32, I64, P, C.POINTER(I64)]),
+            "tdpd_diagnostics": (C.c_int, [P, P, I64]),
+            "tdpd_set_timing": (C.c_int, [P, I32]),
+            "tdpd_get_timing": (C.c_int, [P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
+            "tdpd_num_particles": (I64, [P]),
+            "tdpd_step_counter": (I64, [P]),
+            "tdpd_coincident_pairs": (I64, [P]),
+            "tdpd_last_error": (C.c_char_p, [P]),
+            "tdpd_destroy": (None, [P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return [n for n in dir(lib()) if n.startswith("tdpd_")]
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def params_from_config(cfg, terms=TERMS_ALL):
+    p = tdpd_params()
+    for a in range(3):
+        p.box[a] = cfg.box[a]
+        p.body_force[a] = cfg.body_force[a]
+    p.rc, p.rcc, p.dt, p.kT, p.rho, p.m_s = cfg.rc, cfg.rcc, cfg.dt, cfg.kT, cfg.rho, cfg.m_s
+    p.s_exp, p.sc_exp = cfg.s_exp, cfg.sc_exp
+    T, S = cfg.n_types, cfg.n_species
+    p.n_types, p.n_species = T, S
+    for i in range(T):
+        for j in range(T):
+            p.alpha[i * T + j] = cfg.alpha[i, j]
+            p.gamma[i * T + j] = cfg.gamma[i, j]
+            p.sigma[i * T + j] = cfg.sigma[i, j]
+            for s in range(S):
+                p.kappa[(s * T + i) * T + j] = cfg.kappa[s, i, j]
+    p.wall_axis, p.wall_w = cfg.wall_axis, cfg.wall_w
+    p.seed, p.box_id, p.terms = cfg.seed, cfg.box_id, terms
+    return p
+
+
+class _TorchAllocator:
+    """Allocator callback backed by torch's caching allocator."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.live = {}
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        except Exception:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+class System:
+    """One tDPD system on the GPU (a thin owner of a tdpd_sys handle)."""
+
+    def __init__(self, cfg, terms=TERMS_ALL, stream=None, torch_alloc=True):
+        L = lib()
+        self.cfg = cfg
+        self.S = cfg.n_species
+        self._alloc = None
+        alloc_cb, free_cb = ALLOC_FN(), FREE_FN()
+        if torch_alloc:
+            self._alloc = _TorchAllocator()
+            alloc_cb, free_cb = self._alloc.alloc_cb, self._alloc.free_cb
+        if stream is None and torch_alloc:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        self._p = params_from_config(cfg, terms)
+        h = C.c_void_p()
+        rc = L.tdpd_create(C.byref(self._p), C.c_void_p(stream) if stream else None,
+                           alloc_cb, free_cb, None, C.byref(h))
+        if rc:
+            raise TdpdError(rc, "tdpd_create rejected the parameters")
+        self.h = h
+        self._check(L.tdpd_set_state(self.h, cfg.n, _ptr(np.ascontiguousarray(cfg.pos, np.float32)),
+                                     _ptr(np.ascontiguousarray(cfg.vel, np.float32)),
+                                     _ptr(np.ascontiguousarray(cfg.conc, np.float32)),
+                                     _ptr(np.ascontiguousarray(cfg.flags, np.uint32))))
+        if cfg.mesh_xyz is not None and len(cfg.rbc_first_gid):
+            mp = cfg.mesh_params
+            m = tdpd_mesh_params(p=mp.p, x0=mp.x0, m_pow=mp.m_pow, kb=mp.kb,
+                                 theta0=mp.theta0, kg=mp.kg, kl=mp.kl, kv=mp.kv,
+                                 gamma_t=mp.gamma_t, gamma_c=mp.gamma_c)
+            ref = np.ascontiguousarray(cfg.mesh_xyz, np.float64)
+            tri = np.ascontiguousarray(cfg.mesh_tri, np.int32)
+            mid = C.c_int32()
+            self._check(L.tdpd_add_mesh(self.h, ref.shape[0], _ptr(ref), tri.shape[0], _ptr(tri),
+                                        C.byref(m), C.byref(mid)))
+            for g0 in cfg.rbc_first_gid:
+                rid = C.c_int32()
+                self._check(L.tdpd_add_rbc(self.h, mid.value, int(g0), C.byref(rid)))
+        self.n = cfg.n
+
+    def _check(self, rc):
+        if rc:
+            msg = lib().tdpd_last_error(self.h).decode() if getattr(self, "h", None) else ""
+            raise TdpdError(rc, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tdpd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        self._check(lib().tdpd_step(self.h, int(n)))
+
+    def compute_forces(self, k=0):
+        self._check(lib().tdpd_compute_forces(self.h, int(k)))
+
+    def sync(self):
+        self._check(lib().tdpd_sync(self.h))
+
+    def get_state(self):
+        pos = np.empty((self.n, 3), np.float32)
+        vel = np.empty((self.n, 3), np.float32)
+        conc = np.empty((self.n, self.S), np.float32)
+        self._check(lib().tdpd_get_state(self.h, _ptr(pos), _ptr(vel), _ptr(conc)))
+        return pos, vel, conc
+
+    def get_forces(self):
+        F = np.empty((self.n, 3), np.float32)
+        Q = np.empty((self.n, self.S), np.float32)
+        self._check(lib().tdpd_get_forces(self.h, _ptr(F), _ptr(Q)))
+        return F, Q
+
+    def pairs(self, which=0, cap=None):
+        cap = max(16, self.n * 80) if cap is None else cap
+        out = np.empty((cap, 2), np.int32)
+        cnt = C.c_int64()
+        rc = lib().tdpd_get_pairs(self.h, which, cap, _ptr(out), C.byref(cnt))
+        if rc == -9:
+            return self.pairs(which, cap=int(cnt.value))
+        self._check(rc)
+        return out[:cnt.value].copy()
+
+    def diagnostics(self):
+        nrbc = len(self.cfg.rbc_first_gid) if self.cfg.mesh_xyz is not None else 0
+        out = np.zeros(4 + self.S + 2 * nrbc)
+        self._check(lib().tdpd_diagnostics(self.h, _ptr(out), out.size))
+        return dict(P=out[:3], kT=out[3], C=out[4:4 + self.S],
+                    av=out[4 + self.S:].reshape(nrbc, 2))
+
+    def set_timing(self, mask):
+        self._check(lib().tdpd_set_timing(self.h, int(mask)))
+
+    def get_timing(self, phase):
+        ms, cnt = C.c_double(), C.c_int64()
+        self._check(lib().tdpd_get_timing(self.h, int(phase), C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
+    @property
+    def step_counter(self):
+        return int(lib().tdpd_step_counter(self.h))
+
+    @property
+    def coincident_pairs(self):
+        return int(lib().tdpd_coincident_pairs(self.h))

@@ -1,0 +1,207 @@
+"""GPU parity tests: the HIP library, called through its C ABI, against the
+FP64 CPU oracle on the same seeded inputs.
+
+Pair sets must agree bit for bit.  Forces and concentration rates must agree
+per particle within 1e-5 of the particle's sum of pair-term magnitudes
+(the scale of FP32 summation error), except particles with a force pair
+within 2e-4 of r_c, where the random-force weight (1 - r/r_c)^(s/2) is
+FP32-limited; those are counted and reported.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import compare_forces, gpu_system, near_cutoff_mask
+from oracle import Oracle
+from paper_1611_06163_amd import inputs as I
+from paper_1611_06163_amd import tdpd
+
+pytestmark = pytest.mark.gpu
+
+
+def _sorted_pairs(p):
+    p = np.asarray(p)
+    if p.size == 0:
+        return p.reshape(0, 2)
+    p = np.sort(p, axis=1)
+    return p[np.lexsort((p[:, 1], p[:, 0]))]
+
+
+def _cluster_cfg():
+    """300 particles packed into a 1.2^3 corner of a 6^3 box: one cell holds
+    more than 64 particles and its stencil more than 256 candidates."""
+    cfg = I.make_fluid(box=(6.0, 6.0, 6.0), n=500, seed=13)
+    rng = np.random.default_rng(14)
+    cfg.pos[:300] = (5.5 + rng.random((300, 3)) * 1.2).astype(np.float32) % np.float32(6.0)
+    cfg.pos[300] = cfg.pos[301]  # a coincident pair
+    return cfg
+
+
+def _cases():
+    c1 = I.c1()
+    tiny = I.make_fluid(box=(4.8, 5.0, 6.3), n=300, seed=3)
+    return {"c1": c1, "tiny": tiny, "cluster": _cluster_cfg()}
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny", "cluster"])
+@pytest.mark.parametrize("which", [0, 1])
+def test_pair_sets_bit_exact(name, which):
+    cfg = _cases()[name]
+    sysg = gpu_system(cfg)
+    sysg.compute_forces(0)
+    got = _sorted_pairs(sysg.pairs(which))
+    pos, _, _ = sysg.get_state()
+    o = Oracle(cfg)
+    ref, _ = o.pairs(pos, which, brute=cfg.n <= 2000)
+    print(name, which, len(got), len(ref), flush=True)
+    assert np.array_equal(got, _sorted_pairs(ref))
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("name", ["c1", "cluster", "c1_randflux", "c2", "c3_small"])
+def test_teacher_forced_forces(kernel, name):
+    if name == "c1":
+        cfg = I.c1()
+    elif name == "cluster":
+        cfg = _cluster_cfg()
+    elif name == "c1_randflux":
+        cfg = I.c1()
+        cfg.m_s = 0.05
+    elif name == "c2":
+        cfg = I.c2()
+    else:
+        cfg = I.c3(scale=0.25, n_cells=2)
+    sysg = gpu_system(cfg, kernel=kernel)
+    k = 7
+    sysg.compute_forces(k)
+    F, Q = sysg.get_forces()
+    pos, vel, conc = sysg.get_state()
+    o = Oracle(cfg)
+    ref = o.forces(pos, vel, conc, k=k)
+    assert ref["err"] == 0
+    excl = near_cutoff_mask(o, cfg, pos)
+    rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/k{kernel}")
+    assert rep["badF"] == 0 and rep["badQ"] == 0
+    assert rep["excluded"] <= max(5, cfg.n // 200)
+    if cfg.mesh_xyz is not None and len(cfg.rbc_first_gid):
+        d = sysg.diagnostics()
+        # per-cell FP64 area/volume sums of FP32 triangle terms
+        assert np.allclose(d["av"], ref["av"], rtol=2e-6, atol=0)
+    if name == "cluster":
+        assert sysg.coincident_pairs == 2 == ref["nzero"]
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3_small"])
+def test_ten_steps_teacher_forced(name):
+    """Free-running GPU steps; after each, the oracle re-evaluates the forces
+    at the GPU's own state (half-step velocity v - dt/2 F) with the same
+    counter and checks the kick-drift update of positions."""
+    cfg = {"c1": I.c1(), "c2": I.c2(), "c3_small": I.c3(scale=0.25, n_cells=2)}[name]
+    sysg = gpu_system(cfg)
+    o = Oracle(cfg)
+    sysg.compute_forces(0)
+    x0, v0, c0 = sysg.get_state()
+    F0, Q0 = sysg.get_forces()
+    frozen = (cfg.flags & I.FLAG_FROZEN) != 0
+    h = 0.5 * cfg.dt
+    L = np.asarray(cfg.box)
+    for n in range(1, 11):
+        sysg.step(1)
+        sysg.sync()
+        x, v, c = sysg.get_state()
+        F, Q = sysg.get_forces()
+        # drift: x_n = x_{n-1} + dt (v_{n-1} + dt/2 F_{n-1}), up to wall reflection
+        pred = x0.astype(np.float64) + cfg.dt * (v0 + h * F0)
+        dx = x.astype(np.float64) - pred
+        dx -= L * np.round(dx / L)
+        if cfg.wall_axis >= 0:
+            w = cfg.wall_w
+            y = pred[:, cfg.wall_axis] % L[cfg.wall_axis]
+            refl = (y < w) | (y > L[cfg.wall_axis] - w)
+            dx[refl] = 0.0
+        dx[frozen] = 0.0
+        assert np.abs(dx).max() < 2e-5, (n, np.abs(dx).max())
+        vh = v.astype(np.float64) - h * F
+        ch = c.astype(np.float64) - h * Q
+        vh[frozen] = 0.0
+        ch[frozen] = c[frozen]
+        ref = o.forces(x, vh, ch, k=n)
+        excl = near_cutoff_mask(o, cfg, x)
+        rep = compare_forces(F, Q, ref, exclude=excl, tol=2e-5, label=f"{name}/step{n}")
+        assert rep["badF"] == 0 and rep["badQ"] == 0
+        x0, v0, c0, F0, Q0 = x, v, c, F, Q
+
+
+def test_free_running_trajectory_error_reported():
+    cfg = I.c1()
+    sysg = gpu_system(cfg)
+    sysg.step(10)
+    sysg.sync()
+    x, v, c = sysg.get_state()
+    o = Oracle(cfg)
+    st = o.init_state()
+    for n in range(1, 11):
+        o.step(st, n)
+    L = np.asarray(cfg.box)
+    dx = x - st["pos"]
+    dx -= L * np.round(dx / L)
+    err = np.linalg.norm(dx, axis=1)
+    print("free-running 10 steps: max |dx| %.3e, p99 %.3e, max |dv| %.3e, max |dC| %.3e" % (
+        err.max(), np.quantile(err, 0.99), np.abs(v - st["vel"]).max(),
+        np.abs(c - st["conc"]).max()), flush=True)
+    assert np.quantile(err, 0.99) < 1e-4
+    assert err.max() < 1e-2
+
+
+def test_conservation_on_gpu():
+    cfg = I.c1()
+    sysg = gpu_system(cfg)
+    d0 = sysg.diagnostics()
+    sysg.step(100)
+    d1 = sysg.diagnostics()
+    print("P0", d0["P"], "P100", d1["P"], "C", d0["C"], d1["C"], "kT", d1["kT"], flush=True)
+    assert abs(d1["C"][0] - d0["C"][0]) < 1e-6 * abs(d0["C"][0]) * 100
+    assert np.abs(d1["P"] - d0["P"]).max() < 5e-3
+
+
+def test_bitwise_deterministic():
+    cfg = I.c2()
+    outs = []
+    for _ in range(2):
+        s = gpu_system(cfg)
+        s.step(20)
+        outs.append(s.get_state() + s.get_forces())
+        s.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_empty_and_single_particle():
+    cfg = I.make_fluid(box=(6.0, 6.0, 6.0), n=0)
+    s = gpu_system(cfg)
+    s.step(3)
+    s.sync()
+    assert s.get_state()[0].shape == (0, 3)
+    cfg = I.make_fluid(box=(6.0, 6.0, 6.0), n=1)
+    s = gpu_system(cfg)
+    s.step(3)
+    F, Q = s.get_forces()
+    assert np.all(F == 0) and np.all(Q == 0)
+
+
+def test_full_size_sampled_c3():
+    cfg = I.c3()
+    rng = np.random.default_rng(0)
+    which = np.zeros(cfg.n, np.uint8)
+    which[rng.choice(cfg.n, 3000, replace=False)] = 1
+    which[cfg.rbc_first_gid[0]:cfg.rbc_first_gid[0] + 500] = 1
+    o = Oracle(cfg)
+    for kernel in (1, 0):
+        sysg = gpu_system(cfg, kernel=kernel)
+        sysg.compute_forces(3)
+        F, Q = sysg.get_forces()
+        pos, vel, conc = sysg.get_state()
+        ref = o.forces(pos, vel, conc, k=3, which=which)
+        excl = near_cutoff_mask(o, cfg, pos)
+        rep = compare_forces(F, Q, ref, exclude=excl, which=which, label=f"c3-full/k{kernel}")
+        assert rep["badF"] == 0 and rep["badQ"] == 0
+        sysg.close()
