@@ -563,6 +563,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
       sub3(u + 3 * b, u + 3 * a, d); /* a -> b */
       const double l = norm3(d);
       double fa[3] = {0, 0, 0};
+      double fmag = 0; /* sum of the magnitudes of the parts added below */
       if (terms & T_BOND) {
         const double x = l / M->lm[e];
         if (x >= 1.0) {
@@ -572,6 +573,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
           const double dwlc = p->kT / mp->p * (0.25 / ((1 - x) * (1 - x)) - 0.25 + x);
           const double dpow = -M->kp[e] / pow(l, mp->m_pow);
           for (int q = 0; q < 3; ++q) fa[q] += (dwlc + dpow) * d[q] / l;
+          fmag += fabs(dwlc) + fabs(dpow);
           if (energy) {
             energy[0] += p->kT * M->lm[e] / (4 * mp->p) * x * x * (3 - 2 * x) / (1 - x);
             if (mp->m_pow != 1.0)
@@ -588,6 +590,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
         sub3(vv + 3 * a, vv + 3 * b, vab);
         const double ve = dot3(vab, eab);
         for (int q = 0; q < 3; ++q) fa[q] += -mp->gamma_t * vab[q] - mp->gamma_c * ve * eab[q];
+        fmag += mp->gamma_t * vnorm(vab) + mp->gamma_c * fabs(ve);
       }
       if (terms & T_BRAND) {
         double W[10];
@@ -609,14 +612,15 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
             acc += Mij * eab[j];
           }
           fa[i] += amp * acc;
+          fmag += fabs(amp * acc);
         }
       }
       for (int q = 0; q < 3; ++q) {
         f[3 * a + q] += fa[q];
         f[3 * b + q] -= fa[q];
       }
-      fab[a] += vnorm(fa);
-      fab[b] += vnorm(fa);
+      fab[a] += fmag;
+      fab[b] += fmag;
     }
     /* area and volume, Eqs. (17)-(18) */
     double At = 0, Vt = 0;
@@ -657,7 +661,9 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
           sub3(P[(v + 2) % 3], P[(v + 1) % 3], opp);
           cross3(nh, opp, g);
           for (int q = 0; q < 3; ++q) f[3 * I[v] + q] -= (cg + cl) * 0.5 * g[q];
-          fab[I[v]] += fabs(cg + cl) * 0.5 * vnorm(g);
+          /* A and A0 (and A_j and A_0j) enter as separately rounded terms */
+          fab[I[v]] += (mp->kg * (At + M->A0) / M->A0 + mp->kl * (At_ + M->A0t[t]) / M->A0t[t]) *
+                       0.5 * vnorm(g);
         }
       }
       if (terms & T_VOL) {
@@ -665,13 +671,13 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
         double g[3];
         cross3(b, c, g);
         for (int q = 0; q < 3; ++q) f[3 * ia + q] -= cv * g[q] / 6.0;
-        fab[ia] += fabs(cv) * vnorm(g) / 6.0;
+        fab[ia] += mp->kv * (Vt + M->V0) / M->V0 * vnorm(g) / 6.0;
         cross3(c, a, g);
         for (int q = 0; q < 3; ++q) f[3 * ib + q] -= cv * g[q] / 6.0;
-        fab[ib] += fabs(cv) * vnorm(g) / 6.0;
+        fab[ib] += mp->kv * (Vt + M->V0) / M->V0 * vnorm(g) / 6.0;
         cross3(a, b, g);
         for (int q = 0; q < 3; ++q) f[3 * ic + q] -= cv * g[q] / 6.0;
-        fab[ic] += fabs(cv) * vnorm(g) / 6.0;
+        fab[ic] += mp->kv * (Vt + M->V0) / M->V0 * vnorm(g) / 6.0;
       }
     }
     /* bending, Eq. (19) */
@@ -686,7 +692,9 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
         if (energy) energy[3] += mp->kb * (1 - cos(th - M->theta0));
         for (int v = 0; v < 4; ++v) {
           for (int a = 0; a < 3; ++a) f[3 * D[v] + a] += coef * g[v][a];
-          fab[D[v]] += fabs(coef) * vnorm(g[v]);
+          /* sin(theta - theta0) = sin cos0 - cos sin0, two rounded terms */
+          fab[D[v]] += mp->kb * (fabs(sin(th) * cos(M->theta0)) + fabs(cos(th) * sin(M->theta0))) *
+                       vnorm(g[v]);
         }
       }
     }

@@ -52,11 +52,12 @@ void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, in
 
 // ------------------------------------------------------------- membrane
 struct MeshDev {
-  int nv, ntri;
+  int nv, ntri, nbond;
   const int32_t *tri;        // [ntri][3]
+  const int2 *bond_ab;       // [nbond] local (a, b), a < b
+  const float2 *bond_par;    // [nbond] (l_m, k_p)
   const int32_t *bond_off;   // [nv+1]
-  const int32_t *bond_nbr;   // [nb]
-  const float2 *bond_par;    // [nb] (l_m, k_p)
+  const int32_t *bond_inc;   // [2*nbond] bond << 1 | (vertex is b)
   const int32_t *tri_off;    // [nv+1]
   const int4 *tri_inc;       // [nt] (b, c, tri index, -)
   const int32_t *dih_off;    // [nv+1]
@@ -74,16 +75,15 @@ struct MembraneConst {
   int terms;
 };
 
-// Per cell: FP64 total area/volume and centroid update (K-Gather).
-void launch_rbc_gather(const MembraneConst &mc, const MeshDev *meshes, const int32_t *rbc_mesh,
-                       const int64_t *rbc_first, int nrbc, State s, const uint32_t *slot_of_gid,
-                       double *av, double *centroid, hipStream_t st);
-// Per vertex: bonds, area/volume constraint forces (K-Apply) and bending,
-// added into F (sorted order).
-void launch_membrane_forces(const MembraneConst &mc, const MeshDev *meshes,
-                            const int32_t *rbc_mesh, const int64_t *rbc_first,
-                            const int64_t *rbc_voff, int nrbc, int64_t nvert_total, State s,
-                            const uint32_t *slot_of_gid, const double *av, uint32_t k, float *F,
-                            uint32_t *err, hipStream_t st);
+// All membrane terms of every cell, one workgroup per cell: per-cell FP64
+// totals A^t, V^t and centroid (the K-Gather), then per bond the spring,
+// viscous and random forces, then per vertex the sum of its bond forces, the
+// area/volume constraint forces (K-Apply) and bending, added into F (sorted
+// order).  lds_bytes = membrane_lds_bytes(max nv, max nbond).
+size_t membrane_lds_bytes(int max_nv, int max_nbond);
+void launch_membrane(const MembraneConst &mc, const MeshDev *meshes, const int32_t *rbc_mesh,
+                     const int64_t *rbc_first, int nrbc, State s, const uint32_t *slot_of_gid,
+                     double *av, double *centroid, uint32_t k, float *F, uint32_t *err,
+                     size_t lds_bytes, hipStream_t st);
 
 }  // namespace tdpd

@@ -19,8 +19,9 @@ namespace {
 struct HostMesh {
   int nv = 0, ntri = 0;
   std::vector<int32_t> tri;
-  std::vector<int32_t> bond_off, bond_nbr;
+  std::vector<int2> bond_ab;
   std::vector<float2> bond_par;
+  std::vector<int32_t> bond_off, bond_inc;
   std::vector<int32_t> tri_off, dih_off;
   std::vector<int4> tri_inc, dih_inc;
   std::vector<uint8_t> dih_role;
@@ -94,6 +95,7 @@ struct tdpd_sys {
   int64_t *d_rbc_first = nullptr, *d_rbc_voff = nullptr;
   double *d_av = nullptr, *d_centroid = nullptr;
   int64_t nvert = 0;
+  size_t mem_lds = 0;  // dynamic LDS of the membrane kernel
   int pair_kernel = 1;  // 0: one thread per particle, 1: cell-tiled
   // event timing per phase (index = log2 of TDPD_PHASE_*)
   int timing_mask = 0;
@@ -304,6 +306,7 @@ extern "C" int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const fl
   s->rbc_first.clear();
   s->n = n;
   s->step = 0;
+  s->mem_lds = 0;
   s->h_pos.assign(pos, pos + 3 * n);
   for (int64_t i = 0; i < n; ++i)
     for (int a = 0; a < 3; ++a) {
@@ -384,16 +387,20 @@ extern "C" int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref, int32_t
   }
   const double kT = s->prm.kT, x0 = mp->x0;
   const double fwlc0 = kT / mp->p * (0.25 / ((1 - x0) * (1 - x0)) - 0.25 + x0);
+  // bonds: endpoints (a < b), (l_m, k_p), and per-vertex signed incidences
+  M.bond_ab.resize(l0.size());
+  M.bond_par.resize(l0.size());
+  for (int v = 0; v < nv; ++v)
+    for (auto &nb : bonds[v])
+      if (v < nb.first) M.bond_ab[nb.second] = make_int2(v, nb.first);
+  for (size_t e = 0; e < l0.size(); ++e)
+    M.bond_par[e] = make_float2(float(l0[e] / x0), float(fwlc0 * std::pow(l0[e], double(mp->m_pow))));
   M.bond_off.assign(nv + 1, 0);
   for (int v = 0; v < nv; ++v) {
-    M.bond_off[v] = int(M.bond_nbr.size());
-    for (auto &nb : bonds[v]) {
-      const double L0 = l0[nb.second];
-      M.bond_nbr.push_back(nb.first);
-      M.bond_par.push_back(make_float2(float(L0 / x0), float(fwlc0 * std::pow(L0, double(mp->m_pow)))));
-    }
+    M.bond_off[v] = int(M.bond_inc.size());
+    for (auto &nb : bonds[v]) M.bond_inc.push_back((nb.second << 1) | (v > nb.first ? 1 : 0));
   }
-  M.bond_off[nv] = int(M.bond_nbr.size());
+  M.bond_off[nv] = int(M.bond_inc.size());
   // triangles: per-vertex incidences (other two vertices, counter-clockwise)
   M.A0 = 0;
   M.V0 = 0;
@@ -453,6 +460,8 @@ extern "C" int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref, int32_t
   for (int a = 0; a < 3; ++a)
     if (1.25 * M.max_radius + 1.0 > 0.5 * s->prm.box[a])
       return s->fail(TDPD_ERR_UNSUPPORTED, "add_mesh: cell too large for the periodic box");
+  if (membrane_lds_bytes(M.nv, int(M.bond_ab.size())) > 60 * 1024)
+    return s->fail(TDPD_ERR_UNSUPPORTED, "add_mesh: mesh too large for one workgroup's LDS");
   s->meshes.push_back(std::move(M));
   if (mesh_id) *mesh_id = int32_t(s->meshes.size() - 1);
   return TDPD_OK;
@@ -564,29 +573,34 @@ static int prepare(tdpd_sys *s) {
     for (size_t m = 0; m < s->meshes.size(); ++m) {
       HostMesh &M = s->meshes[m];
       MeshDev &D = md[m];
-      int32_t *tri, *bo, *bn, *to, *dof;
+      int32_t *tri, *bo, *bi, *to, *dof;
+      int2 *bab;
       float2 *bp;
       int4 *ti, *di;
       uint8_t *dr;
       float *a0t;
-      if ((rc = upload(s, &tri, M.tri)) || (rc = upload(s, &bo, M.bond_off)) ||
-          (rc = upload(s, &bn, M.bond_nbr)) || (rc = upload(s, &bp, M.bond_par)) ||
-          (rc = upload(s, &to, M.tri_off)) || (rc = upload(s, &ti, M.tri_inc)) ||
-          (rc = upload(s, &dof, M.dih_off)) || (rc = upload(s, &di, M.dih_inc)) ||
-          (rc = upload(s, &dr, M.dih_role)) || (rc = upload(s, &a0t, M.A0t)))
+      if ((rc = upload(s, &tri, M.tri)) || (rc = upload(s, &bab, M.bond_ab)) ||
+          (rc = upload(s, &bp, M.bond_par)) || (rc = upload(s, &bo, M.bond_off)) ||
+          (rc = upload(s, &bi, M.bond_inc)) || (rc = upload(s, &to, M.tri_off)) ||
+          (rc = upload(s, &ti, M.tri_inc)) || (rc = upload(s, &dof, M.dih_off)) ||
+          (rc = upload(s, &di, M.dih_inc)) || (rc = upload(s, &dr, M.dih_role)) ||
+          (rc = upload(s, &a0t, M.A0t)))
         return rc;
       D.nv = M.nv;
       D.ntri = M.ntri;
+      D.nbond = int(M.bond_ab.size());
       D.tri = tri;
-      D.bond_off = bo;
-      D.bond_nbr = bn;
+      D.bond_ab = bab;
       D.bond_par = bp;
+      D.bond_off = bo;
+      D.bond_inc = bi;
       D.tri_off = to;
       D.tri_inc = ti;
       D.dih_off = dof;
       D.dih_inc = di;
       D.dih_role = dr;
       D.A0t = a0t;
+      s->mem_lds = std::max(s->mem_lds, membrane_lds_bytes(M.nv, D.nbond));
       D.A0 = float(M.A0);
       D.V0 = float(M.V0);
       D.theta0 = float(M.theta0);
@@ -680,10 +694,8 @@ static int evaluate(tdpd_sys *s, uint32_t k, bool integrate) {
   const int nrbc = int(s->rbc_mesh.size());
   const bool tm = nrbc > 0 && s->phase_begin(2);
   if (nrbc > 0) {
-    launch_rbc_gather(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, nrbc, s->cur(),
-                      s->slot_of_gid, s->d_av, s->d_centroid, st);
-    launch_membrane_forces(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, s->d_rbc_voff, nrbc,
-                           s->nvert, s->cur(), s->slot_of_gid, s->d_av, k, s->F, s->errw, st);
+    launch_membrane(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, nrbc, s->cur(),
+                    s->slot_of_gid, s->d_av, s->d_centroid, k, s->F, s->errw, s->mem_lds, st);
   }
   s->phase_end(2, tm);
   const bool tk = integrate && s->phase_begin(3);

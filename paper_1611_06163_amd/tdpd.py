@@ -67,6 +67,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_1611_06163_amd.build` (hipcc, gfx950)")
+        # torch's HIP runtime must be the process's only one: load it before
+        # libtdpd.so so that the library's libamdhip64 dependency binds to it
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {

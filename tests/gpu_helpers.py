@@ -3,11 +3,10 @@ import os
 
 import numpy as np
 
-from oracle import Oracle
+from oracle import Oracle, pair_normals_batch
 from paper_1611_06163_amd import tdpd
 
 TOL = 1e-5          # per-particle force / flux tolerance, relative to sum_j |term_ij|
-CUT_DELTA = 2e-4    # pairs this close to r_c have FP32-limited random-force weights
 
 
 def gpu_system(cfg, kernel=None, terms=tdpd.TERMS_ALL):
@@ -24,18 +23,34 @@ def gpu_system(cfg, kernel=None, terms=tdpd.TERMS_ALL):
                 os.environ["TDPD_PAIR_KERNEL"] = old
 
 
-def near_cutoff_mask(o, cfg, pos, delta=CUT_DELTA):
-    """Particles with a force pair whose distance is within delta of r_c."""
+def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL, du=2e-7):
+    """Particles whose force cannot be resolved to `tol` in FP32.
+
+    Near r_c the weights w_R = w^(s/2) and w_D = w^s (w = 1 - r/r_c) have
+    derivatives (s/2) w^(s/2-1) and s w^(s-1) that amplify the FP32 rounding
+    of r (du in w, about two ulps) without bound.  For each force pair the
+    induced error is sigma |xi| w_R' du / sqrt(dt) + gamma |v_ij| w_D' du with
+    the pair's own noise draw xi (same generator and counter as the step); a
+    particle is excluded when the sum over its pairs exceeds half of its
+    tolerance tol * sum_j |F_ij| (ref = the oracle's evaluation)."""
     p, _ = o.pairs(pos.astype(np.float32), 0)
     d = pos[p[:, 1]].astype(np.float64) - pos[p[:, 0]]
     L = np.asarray(cfg.box)
     d -= L * np.round(d / L)
     r = np.linalg.norm(d, axis=1)
-    near = np.abs(r - cfg.rc) < delta
-    m = np.zeros(pos.shape[0], bool)
-    m[p[near, 0]] = True
-    m[p[near, 1]] = True
-    return m
+    w = np.maximum(1.0 - r / cfg.rc, 1e-12)
+    s = cfg.s_exp
+    xi = np.abs(pair_normals_batch(cfg, k, p[:, 0], p[:, 1], 0)[:, 0])
+    vij = np.linalg.norm(vel[p[:, 0]].astype(np.float64) - vel[p[:, 1]], axis=1)
+    sig = float(np.max(cfg.sigma))
+    gam = float(np.max(cfg.gamma))
+    sens = (sig * xi * (0.5 * s) * w ** (0.5 * s - 1.0) / np.sqrt(cfg.dt)
+            + gam * vij * s * w ** (s - 1.0)) * du
+    tot = np.zeros(pos.shape[0])
+    np.add.at(tot, p[:, 0], sens)
+    np.add.at(tot, p[:, 1], sens)
+    mobile = (cfg.flags & tdpd.FLAG_FROZEN) == 0  # frozen particles have F = 0 exactly
+    return mobile & (tot > 0.5 * tol * np.maximum(ref["Fabs"], 1e-30))
 
 
 def compare_forces(F, Q, ref, exclude=None, tol=TOL, which=None, label=""):
@@ -58,5 +73,7 @@ def compare_forces(F, Q, ref, exclude=None, tol=TOL, which=None, label=""):
                p999_relF=float(np.quantile(rF, 0.999)) if rF.size else 0.0,
                max_relQ=float(rQ.max()) if rQ.size else 0.0,
                badF=int(badF.sum()), badQ=int(badQ.sum()))
+    worst = np.argsort(-np.where(sel, eF / bF, 0))[:3]
+    rep["worst"] = [(int(i), float(eF[i] / max(ref["Fabs"][i], 1e-30))) for i in worst]
     print("parity", rep, flush=True)
     return rep

@@ -2,10 +2,11 @@
 FP64 CPU oracle on the same seeded inputs.
 
 Pair sets must agree bit for bit.  Forces and concentration rates must agree
-per particle within 1e-5 of the particle's sum of pair-term magnitudes
-(the scale of FP32 summation error), except particles with a force pair
-within 2e-4 of r_c, where the random-force weight (1 - r/r_c)^(s/2) is
-FP32-limited; those are counted and reported.
+per particle within 1e-5 of the particle's sum of term magnitudes (the scale
+of FP32 summation error), except particles whose force is ill-conditioned in
+FP32: a pair so close to r_c that the weight (1 - r/r_c)^(s/2) turns the
+rounding of r into more than a third of the tolerance (gpu_helpers); those
+are counted, reported and bounded.
 """
 import numpy as np
 import pytest
@@ -78,10 +79,11 @@ def test_teacher_forced_forces(kernel, name):
     o = Oracle(cfg)
     ref = o.forces(pos, vel, conc, k=k)
     assert ref["err"] == 0
-    excl = near_cutoff_mask(o, cfg, pos)
+    excl = near_cutoff_mask(o, cfg, pos, vel, ref, k)
     rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/k{kernel}")
     assert rep["badF"] == 0 and rep["badQ"] == 0
-    assert rep["excluded"] <= max(5, cfg.n // 200)
+    # a few percent of particles have a force pair close enough to r_c
+    assert rep["excluded"] <= 5 + cfg.n // 20
     if cfg.mesh_xyz is not None and len(cfg.rbc_first_gid):
         d = sysg.diagnostics()
         # per-cell FP64 area/volume sums of FP32 triangle terms
@@ -125,8 +127,8 @@ def test_ten_steps_teacher_forced(name):
         vh[frozen] = 0.0
         ch[frozen] = c[frozen]
         ref = o.forces(x, vh, ch, k=n)
-        excl = near_cutoff_mask(o, cfg, x)
-        rep = compare_forces(F, Q, ref, exclude=excl, tol=2e-5, label=f"{name}/step{n}")
+        excl = near_cutoff_mask(o, cfg, x, vh, ref, n)
+        rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/step{n}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         x0, v0, c0, F0, Q0 = x, v, c, F, Q
 
@@ -153,14 +155,24 @@ def test_free_running_trajectory_error_reported():
 
 
 def test_conservation_on_gpu():
+    """Pair terms are exactly antisymmetric, so total momentum and total
+    concentration change only by FP32 rounding of each particle's sum:
+    per step at most about eps32 * sum_i sum_j |F_ij| * dt (and the same for
+    C); the bound allows twice that, accumulated linearly."""
     cfg = I.c1()
     sysg = gpu_system(cfg)
     d0 = sysg.diagnostics()
-    sysg.step(100)
+    ref = Oracle(cfg).forces(cfg.pos, cfg.vel, cfg.conc, k=0)
+    nsteps = 100
+    eps = float(np.finfo(np.float32).eps)
+    boundP = 2 * nsteps * cfg.dt * eps * ref["Fabs"].sum()
+    boundC = 2 * nsteps * cfg.dt * eps * ref["Qabs"].sum() + 4 * eps * cfg.n
+    sysg.step(nsteps)
     d1 = sysg.diagnostics()
-    print("P0", d0["P"], "P100", d1["P"], "C", d0["C"], d1["C"], "kT", d1["kT"], flush=True)
-    assert abs(d1["C"][0] - d0["C"][0]) < 1e-6 * abs(d0["C"][0]) * 100
-    assert np.abs(d1["P"] - d0["P"]).max() < 5e-3
+    print("P0", d0["P"], "P100", d1["P"], "boundP", boundP, "C", d0["C"], d1["C"], "boundC",
+          boundC, "kT", d1["kT"], flush=True)
+    assert abs(d1["C"][0] - d0["C"][0]) < boundC
+    assert np.abs(d1["P"] - d0["P"]).max() < boundP
 
 
 def test_bitwise_deterministic():
@@ -201,7 +213,7 @@ def test_full_size_sampled_c3():
         F, Q = sysg.get_forces()
         pos, vel, conc = sysg.get_state()
         ref = o.forces(pos, vel, conc, k=3, which=which)
-        excl = near_cutoff_mask(o, cfg, pos)
+        excl = near_cutoff_mask(o, cfg, pos, vel, ref, 3)
         rep = compare_forces(F, Q, ref, exclude=excl, which=which, label=f"c3-full/k{kernel}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         sysg.close()
