@@ -79,6 +79,8 @@ def _load():
         L.orc_philox4x32.argtypes = [P, P, C.c_int, P]
         L.orc_pair_normals_batch.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_int64, P, P,
                                              C.c_uint32, P]
+        L.orc_pair_normals4.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32,
+                                        C.c_uint32, C.c_uint32, P]
         L.orc_u01.restype = C.c_double
         L.orc_u01.argtypes = [C.c_uint32]
         L.orc_pair_normals.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32,
@@ -135,6 +137,13 @@ def pair_normals(cfg, k, gi, gj, stream):
     p = _params_from(cfg)
     out = np.zeros(2)
     _load().orc_pair_normals(C.byref(p), k, gi, gj, stream, _ptr(out))
+    return out
+
+
+def pair_normals4(cfg, k, gi, gj, stream):
+    p = _params_from(cfg)
+    out = np.zeros(4)
+    _load().orc_pair_normals4(C.byref(p), k, gi, gj, stream, _ptr(out))
     return out
 
 

@@ -32,10 +32,12 @@
  * implemented here from its published definition.  Counter (k, min gid,
  * max gid, box_id<<8 | stream), key (seed_lo, seed_hi); uniforms
  * u = (2*(bits>>9)+1) * 2^-24; normals by Box-Muller, sqrt(-2 ln u0)
- * cos(2 pi u1), one per pair of words.  Stream 0 gives the pair force noise
- * xi (words 0,1) and the species-0 flux noise (words 2,3); stream m>=1 gives
- * species 2m-1 and 2m; streams 64..68 give the nine entries of the membrane
- * bond's Wiener matrix, row major.
+ * cos(2 pi u1) from a pair of words (and sqrt(-2 ln u0) sin(2 pi u1) where two
+ * normals per pair are drawn).  Stream 0 gives the pair force noise xi (cos
+ * of words 0,1) and the species-0 flux noise (cos of words 2,3); stream m>=1
+ * gives species 2m-1 and 2m the same way; streams 64, 65, 66 give twelve
+ * normals (cos, sin of words 0,1, then cos, sin of words 2,3, per stream),
+ * the first nine of which are the membrane bond's Wiener matrix, row major.
  */
 #include <math.h>
 #include <stdint.h>
@@ -155,6 +157,23 @@ void orc_pair_normals(const orc_params *p, uint32_t k, uint32_t gi, uint32_t gj,
   orc_philox4x32(ctr, key, 10, w);
   out[0] = box_muller(w[0], w[1]);
   out[1] = box_muller(w[2], w[3]);
+}
+
+/* four standard normals for the unordered pair: Box-Muller cos and sin of
+   words (0,1), then of words (2,3) */
+void orc_pair_normals4(const orc_params *p, uint32_t k, uint32_t gi, uint32_t gj,
+                       uint32_t stream, double out[4]) {
+  const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
+  const uint32_t ctr[4] = {k, lo, hi, (p->box_id << 8) | stream};
+  const uint32_t key[2] = {p->seed_lo, p->seed_hi};
+  uint32_t w[4];
+  orc_philox4x32(ctr, key, 10, w);
+  for (int h = 0; h < 2; ++h) {
+    const double r = sqrt(-2.0 * log(orc_u01(w[2 * h])));
+    const double a = 2.0 * M_PI * orc_u01(w[2 * h + 1]);
+    out[2 * h] = r * cos(a);
+    out[2 * h + 1] = r * sin(a);
+  }
 }
 
 /* ------------------------------------------------------------ predicate */
@@ -593,9 +612,9 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
         fmag += mp->gamma_t * vnorm(vab) + mp->gamma_c * fabs(ve);
       }
       if (terms & T_BRAND) {
-        double W[10];
-        for (int t = 0; t < 5; ++t)
-          orc_pair_normals(p, k, (uint32_t)(g0 + a), (uint32_t)(g0 + b), 64 + t, W + 2 * t);
+        double W[12];
+        for (int t = 0; t < 3; ++t)
+          orc_pair_normals4(p, k, (uint32_t)(g0 + a), (uint32_t)(g0 + b), 64 + t, W + 4 * t);
         double WS[9];
         for (int i = 0; i < 3; ++i)
           for (int j = 0; j < 3; ++j) WS[3 * i + j] = 0.5 * (W[3 * i + j] + W[3 * j + i]);

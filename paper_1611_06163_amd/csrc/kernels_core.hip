@@ -142,8 +142,11 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
 __global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const float *__restrict__ F,
                                                  const float *__restrict__ Q, int64_t n,
                                                  uint32_t *__restrict__ keys,
-                                                 uint32_t *__restrict__ vals, int integrate) {
+                                                 uint32_t *__restrict__ vals, int integrate,
+                                                 uint32_t *__restrict__ cell_count,
+                                                 uint32_t *__restrict__ kdev) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (integrate && kdev && i == 0) *kdev += 1u;  // step counter read by later kernels
   if (i >= n) return;
   float x = s.x[i], y = s.y[i], z = s.z[i];
   if (integrate && !info_frozen(s.info[i])) {
@@ -185,34 +188,139 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const fl
   const int cx = cell_coord(x, pc.inv_h[0], pc.nc[0]);
   const int cy = cell_coord(y, pc.inv_h[1], pc.nc[1]);
   const int cz = cell_coord(z, pc.inv_h[2], pc.nc[2]);
-  keys[i] = uint32_t((cz * pc.nc[1] + cy) * pc.nc[0] + cx);
-  vals[i] = uint32_t(i);
+  const uint32_t key = uint32_t((cz * pc.nc[1] + cy) * pc.nc[0] + cx);
+  keys[i] = key;
+  // counting binning: the value is this particle's (unordered) rank in its cell
+  vals[i] = cell_count ? atomicAdd(&cell_count[key], 1u) : uint32_t(i);
 }
 
 void launch_prekick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
-                    uint32_t *keys, uint32_t *vals, bool integrate, hipStream_t st) {
+                    uint32_t *keys, uint32_t *vals, bool integrate, uint32_t *cell_count,
+                    uint32_t *kdev, hipStream_t st) {
+  const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_prekick, dim3(unsigned(nb)), dim3(256), 0, st, pc, s, F, Q, n, keys, vals,
+                     int(integrate), cell_count, kdev);
+}
+
+// ------------------------------------------------------------- counting binning
+// A stable one-digit radix sort (radix = number of cells): the cell counts
+// come from atomic increments in k_prekick, one exclusive scan gives
+// cell_start, a scatter places every particle at start + its unordered rank,
+// and k_rank_gather replaces that rank by the particle's rank in previous
+// order among its cell (a count over the cell), so the final order is the
+// same as a stable sort's and does not depend on atomic ordering.
+__global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restrict__ count,
+                                                             int64_t ncell,
+                                                             uint32_t *__restrict__ start) {
+  __shared__ uint32_t part[kScanThreads];
+  const int64_t chunk = (ncell + kScanThreads - 1) / kScanThreads;
+  const int64_t b = int64_t(threadIdx.x) * chunk;
+  const int64_t e = b + chunk < ncell ? b + chunk : ncell;
+  uint32_t sum = 0;
+  for (int64_t c = b; c < e; ++c) sum += count[c];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int64_t c = b; c < e; ++c) {
+    const uint32_t v = count[c];
+    start[c] = run;
+    count[c] = 0u;  // ready for the next step
+    run += v;
+  }
+  if (threadIdx.x == kScanThreads - 1) start[ncell] = part[kScanThreads - 1];
+}
+
+__global__ void __launch_bounds__(256) k_scatter_rank(const uint32_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ rank,
+                                                      const uint32_t *__restrict__ start, int64_t n,
+                                                      uint32_t *__restrict__ tmp) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  tmp[start[keys[i]] + rank[i]] = uint32_t(i);
+}
+
+__global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uint32_t *__restrict__ tmp,
+                                                     const uint32_t *__restrict__ keys,
+                                                     const uint32_t *__restrict__ start, int64_t n,
+                                                     int nspec, uint32_t *__restrict__ slot_of_gid,
+                                                     uint32_t *__restrict__ keys_sorted) {
+  const int64_t p0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p0 >= n) return;
+  const uint32_t q = tmp[p0];
+  const uint32_t c = keys[q];
+  const uint32_t s0 = start[c], s1 = start[c + 1];
+  uint32_t r = 0;
+  for (uint32_t m = s0; m < s1; ++m) r += tmp[m] < q ? 1u : 0u;
+  const uint32_t p = s0 + r;
+  b.x[p] = a.x[q];
+  b.y[p] = a.y[q];
+  b.z[p] = a.z[q];
+  b.vx[p] = a.vx[q];
+  b.vy[p] = a.vy[q];
+  b.vz[p] = a.vz[q];
+  for (int sp = 0; sp < nspec; ++sp) b.C[sp * n + p] = a.C[sp * n + q];
+  const uint32_t g = a.gid[q];
+  b.gid[p] = g;
+  b.info[p] = a.info[q];
+  slot_of_gid[g] = p;
+  keys_sorted[p] = c;
+}
+
+void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
+                         uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
+                         int64_t n, int nspec, uint32_t *slot_of_gid, uint32_t *keys_sorted,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(kScanThreads), 0, st, cell_count, ncell, cell_start);
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_prekick, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s, F, Q, n,
-                     keys, vals, int(integrate));
+  const dim3 g(unsigned((n + 255) / 256));
+  hipLaunchKernelGGL(k_scatter_rank, g, dim3(256), 0, st, keys, rank, cell_start, n, tmp);
+  hipLaunchKernelGGL(k_rank_gather, g, dim3(256), 0, st, src, dst, tmp, keys, cell_start, n, nspec,
+                     slot_of_gid, keys_sorted);
 }
 
 // F, Q are per particle in sorted order: F [n][3], Q [n][S]
-__global__ void __launch_bounds__(256) k_postkick(PairConst pc, State s, const float *__restrict__ F,
-                                                  const float *__restrict__ Q, int64_t n) {
+__global__ void __launch_bounds__(256) k_postkick(PairConst pc, State s, float *__restrict__ F,
+                                                  const float *__restrict__ Q, int64_t n,
+                                                  VertexMap vm, int integrate) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  if (info_frozen(s.info[i])) return;
+  const uint32_t info = s.info[i];
+  float fx = F[3 * i], fy = F[3 * i + 1], fz = F[3 * i + 2];
+  const int body = info_body(info);
+  if (vm.Fm && body >= 0) {
+    const int64_t v = vm.rbc_voff[body] + (int64_t(s.gid[i]) - vm.rbc_first[body]);
+    fx += vm.Fm[3 * v];
+    fy += vm.Fm[3 * v + 1];
+    fz += vm.Fm[3 * v + 2];
+    F[3 * i] = fx;
+    F[3 * i + 1] = fy;
+    F[3 * i + 2] = fz;
+  }
+  if (!integrate || info_frozen(info)) return;
   const float h = pc.half_dt;
-  s.vx[i] += h * F[3 * i];
-  s.vy[i] += h * F[3 * i + 1];
-  s.vz[i] += h * F[3 * i + 2];
+  s.vx[i] += h * fx;
+  s.vy[i] += h * fy;
+  s.vz[i] += h * fz;
   for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
 }
 
-void launch_postkick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
-                     hipStream_t st) {
+void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,
+                     VertexMap vm, bool integrate, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_postkick, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s, F, Q, n);
+  hipLaunchKernelGGL(k_postkick, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s, F, Q, n,
+                     vm, int(integrate));
+}
+
+__global__ void k_set_counter(uint32_t *kdev, uint32_t k) { *kdev = k; }
+
+void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, kdev, k);
 }
 
 // ------------------------------------------------------------- cell bounds

@@ -61,13 +61,15 @@ size_t membrane_lds_bytes(int max_nv, int max_nbond) {
 
 __global__ void __launch_bounds__(kMemThreads) k_membrane(
     MembraneConst mc, const MeshDev *__restrict__ meshes, const int32_t *__restrict__ rbc_mesh,
-    const int64_t *__restrict__ rbc_first, State s, const uint32_t *__restrict__ slot_of_gid,
-    double *__restrict__ av, double *__restrict__ centroid, uint32_t k, float *__restrict__ F,
+    const int64_t *__restrict__ rbc_first, const int64_t *__restrict__ rbc_voff, State s,
+    const uint32_t *__restrict__ slot_of_gid, double *__restrict__ av,
+    double *__restrict__ centroid, const uint32_t *__restrict__ kdev, float *__restrict__ Fm,
     uint32_t *err) {
   extern __shared__ float lds[];
   __shared__ double red[kMemThreads];
   __shared__ double tot[5];
   const int r = blockIdx.x, tid = threadIdx.x;
+  const uint32_t k = *kdev;
   const MeshDev &M = meshes[rbc_mesh[r]];
   const int nv = M.nv;
   float *px = lds, *py = px + nv, *pz = py + nv, *wx = pz + nv, *wy = wx + nv, *wz = wy + nv;
@@ -164,12 +166,12 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
       if (terms & TDPD_TERM_BOND_RANDOM) {
         // a < b locally and gids are consecutive, so (g0+a, g0+b) is ordered
         const uint32_t ga = uint32_t(g0 + ab.x), gb = uint32_t(g0 + ab.y);
-        float W[10];
+        float W[12];  // streams 64..66: (cos, sin) of words (0,1) then (2,3); first 9 used
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
+        for (int q = 0; q < 3; ++q) {
           const u32x4 z = philox10(k, ga, gb, mc.ctr3 | uint32_t(64 + q), mc.seed_lo, mc.seed_hi);
-          W[2 * q] = gauss(z.a, z.b);
-          W[2 * q + 1] = gauss(z.c, z.d);
+          gauss2(z.a, z.b, W[4 * q], W[4 * q + 1]);
+          gauss2(z.c, z.d, W[4 * q + 2], W[4 * q + 3]);
         }
         const float trW = W[0] + W[4] + W[8];  // trace of W and of its symmetric part
         const float ex[3] = {e.x, e.y, e.z};
@@ -254,21 +256,22 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
         f.z += coef * g.z;
       }
     }
-    const uint32_t q = sl[v];
-    F[3 * q] += f.x;
-    F[3 * q + 1] += f.y;
-    F[3 * q + 2] += f.z;
+    const int64_t o = 3 * (rbc_voff[r] + v);
+    Fm[o] = f.x;
+    Fm[o + 1] = f.y;
+    Fm[o + 2] = f.z;
     if (!(isfinite(f.x) && isfinite(f.y) && isfinite(f.z))) atomicOr(err, kErrNonfinite);
   }
 }
 
 void launch_membrane(const MembraneConst &mc, const MeshDev *meshes, const int32_t *rbc_mesh,
-                     const int64_t *rbc_first, int nrbc, State s, const uint32_t *slot_of_gid,
-                     double *av, double *centroid, uint32_t k, float *F, uint32_t *err,
-                     size_t lds_bytes, hipStream_t st) {
+                     const int64_t *rbc_first, const int64_t *rbc_voff, int nrbc, State s,
+                     const uint32_t *slot_of_gid, double *av, double *centroid,
+                     const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
+                     hipStream_t st) {
   if (nrbc <= 0) return;
   hipLaunchKernelGGL(k_membrane, dim3(nrbc), dim3(kMemThreads), lds_bytes, st, mc, meshes, rbc_mesh,
-                     rbc_first, s, slot_of_gid, av, centroid, k, F, err);
+                     rbc_first, rbc_voff, s, slot_of_gid, av, centroid, kdev, Fm, err);
 }
 
 }  // namespace tdpd

@@ -78,9 +78,10 @@ __device__ __forceinline__ void pair_term(const PairConst &pc, float dx, float d
 __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc, State s,
                                                      const uint32_t *__restrict__ cell_keys,
                                                      const uint32_t *__restrict__ cell_start,
-                                                     int64_t n, uint32_t k, float *__restrict__ F,
-                                                     float *__restrict__ Q,
+                                                     int64_t n, const uint32_t *__restrict__ kdev,
+                                                     float *__restrict__ F, float *__restrict__ Q,
                                                      unsigned long long *nzero, uint32_t *err) {
+  const uint32_t k = *kdev;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int S = pc.n_species;
@@ -151,11 +152,11 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc, State s,
 }
 
 void launch_pair_simple(const PairConst &pc, State s, const uint32_t *cell_keys,
-                        const uint32_t *cell_start, int64_t n, uint32_t k, float *F, float *Q,
-                        unsigned long long *nzero, uint32_t *err, hipStream_t st) {
+                        const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
+                        float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_pair_simple, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s,
-                     cell_keys, cell_start, n, k, F, Q, nzero, err);
+                     cell_keys, cell_start, n, kdev, F, Q, nzero, err);
 }
 
 // ------------------------------------------------------------ pair listing

@@ -117,13 +117,15 @@ template <int NS>
 __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State s,
                                                             const uint32_t *__restrict__ cell_start,
                                                             int64_t ncell, int64_t per_xcd,
-                                                            int64_t n, uint32_t k,
+                                                            int64_t n,
+                                                            const uint32_t *__restrict__ kdev,
                                                             float *__restrict__ F,
                                                             float *__restrict__ Q,
                                                             unsigned long long *nzero,
                                                             uint32_t *err) {
   __shared__ TiledShared<NS> sh;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t k = *kdev;  // random-number step counter
   // consecutive workgroups go to different XCDs; give each XCD a contiguous
   // slab of cells so neighbouring cells share that XCD's L2
   const int64_t b = blockIdx.x;
@@ -157,7 +159,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
   const int nchunk = (ncand + 63) / 64;
   const int my_chunks = nchunk > w ? (nchunk - w + kWaves - 1) / kWaves : 0;
   const int h0 = int(cell_start[cell]), h1 = int(cell_start[cell + 1]);
-  unsigned long long zero = 0;
+  uint32_t zero = 0;  // coincident pairs seen by this lane
 
   for (int hb = h0; hb < h1; hb += kHome) {
     const int nh = min(kHome, h1 - hb);
@@ -234,13 +236,13 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
         }
 #pragma unroll
         for (int kk = 0; kk < kChunks; ++kk) {
+          if (cb + kk >= my_chunks) break;  // wave-uniform
           const float dx = __fsub_rn(cxs[kk], xi);
           const float dy = __fsub_rn(cys[kk], yi);
           const float dz = __fsub_rn(czs[kk], zi);
           const float d2 = dist2(dx, dy, dz);
           const bool live = cv[kk] && d2 > 0.f;
-          const uint64_t zm = __ballot(cv[kk] && d2 == 0.f && cj[kk] != self);
-          zero += __popcll(zm);
+          zero += (cv[kk] && d2 == 0.f && cj[kk] != self) ? 1u : 0u;
           if ((pc.terms & TDPD_TERM_FLUX_FICK) && live && d2 < pc.rcc2) {
             const float wdc = flux_weight(pc, d2);
 #pragma unroll
@@ -313,27 +315,27 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
     }
     __syncthreads();
   }
-  if (lane == 0 && zero) atomicAdd(nzero, zero);
+  if (zero) atomicAdd(nzero, (unsigned long long)zero);
 }
 
 void launch_pair_tiled(const PairConst &pc, State s, const uint32_t *cell_start, int64_t ncell,
-                       int64_t n, uint32_t k, float *F, float *Q, unsigned long long *nzero,
-                       uint32_t *err, hipStream_t st) {
+                       int64_t n, const uint32_t *kdev, float *F, float *Q,
+                       unsigned long long *nzero, uint32_t *err, hipStream_t st) {
   if (n <= 0 || ncell <= 0) return;
   const int64_t per_xcd = (ncell + 7) / 8;
   const dim3 grid(unsigned(per_xcd * 8)), block(64 * kWaves);
   if (pc.n_species <= 1)
     hipLaunchKernelGGL(k_pair_tiled<1>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
-                       k, F, Q, nzero, err);
+                       kdev, F, Q, nzero, err);
   else if (pc.n_species == 2)
     hipLaunchKernelGGL(k_pair_tiled<2>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
-                       k, F, Q, nzero, err);
+                       kdev, F, Q, nzero, err);
   else if (pc.n_species <= 4)
     hipLaunchKernelGGL(k_pair_tiled<4>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
-                       k, F, Q, nzero, err);
+                       kdev, F, Q, nzero, err);
   else
     hipLaunchKernelGGL(k_pair_tiled<8>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
-                       k, F, Q, nzero, err);
+                       kdev, F, Q, nzero, err);
 }
 
 }  // namespace tdpd

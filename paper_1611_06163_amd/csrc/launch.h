@@ -17,26 +17,48 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
                 int64_t n, int key_bits, hipStream_t st);
 
 // First half kick + drift + walls + wrap + cell key (one thread per particle).
+// With cell_count, vals gets the particle's unordered rank in its cell (the
+// counting binning); else vals = index (the radix binning).  With integrate
+// and kdev, the device step counter *kdev is incremented.
 void launch_prekick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
-                    uint32_t *keys, uint32_t *vals, bool integrate, hipStream_t st);
+                    uint32_t *keys, uint32_t *vals, bool integrate, uint32_t *cell_count,
+                    uint32_t *kdev, hipStream_t st);
+// Counting binning after launch_prekick: scan of the cell counts into
+// cell_start (counts zeroed for the next step), scatter, and the rank fix-up
+// fused with the reorder of every state plane into dst (slot_of_gid and the
+// sorted keys updated).  Same permutation as the stable radix sort.
+void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
+                         uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
+                         int64_t n, int nspec, uint32_t *slot_of_gid, uint32_t *keys_sorted,
+                         hipStream_t st);
 // cell_start[c] = first sorted index of cell c, cell_start[ncell] = n.
 void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
                         uint32_t *cell_start, hipStream_t st);
 // dst[p] = src[perm[p]] for every state plane; slot_of_gid[gid] = p.
 void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
                     uint32_t *slot_of_gid, hipStream_t st);
-// Second half kick (mobile particles).
-void launch_postkick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
-                     hipStream_t st);
+// Adds the membrane forces Fm (indexed by global vertex, see launch_membrane)
+// into F, then (integrate) the second half kick of mobile particles.
+struct VertexMap {
+  const float *Fm;          // [nvert][3] or null
+  const int64_t *rbc_first; // [nrbc]
+  const int64_t *rbc_voff;  // [nrbc]
+};
+void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,
+                     VertexMap vm, bool integrate, hipStream_t st);
+// Sets *kdev = k.
+void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st);
 
 // Pair forces and fluxes, one thread per particle (sorted order).
+// The random-number step counter k is read from device memory (*kdev) so a
+// captured graph of a step stays valid from step to step.
 void launch_pair_simple(const PairConst &pc, State s, const uint32_t *cell_keys,
-                        const uint32_t *cell_start, int64_t n, uint32_t k, float *F, float *Q,
-                        unsigned long long *nzero, uint32_t *err, hipStream_t st);
+                        const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
+                        float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st);
 // Pair forces and fluxes, cell-tiled kernel (one wavefront per home cell).
 void launch_pair_tiled(const PairConst &pc, State s, const uint32_t *cell_start, int64_t ncell,
-                       int64_t n, uint32_t k, float *F, float *Q, unsigned long long *nzero,
-                       uint32_t *err, hipStream_t st);
+                       int64_t n, const uint32_t *kdev, float *F, float *Q,
+                       unsigned long long *nzero, uint32_t *err, hipStream_t st);
 // Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
 void launch_pair_emit(const PairConst &pc, State s, const uint32_t *cell_keys,
                       const uint32_t *cell_start, int64_t n, float rcut2, int32_t *out,
@@ -79,11 +101,14 @@ struct MembraneConst {
 // totals A^t, V^t and centroid (the K-Gather), then per bond the spring,
 // viscous and random forces, then per vertex the sum of its bond forces, the
 // area/volume constraint forces (K-Apply) and bending, added into F (sorted
-// order).  lds_bytes = membrane_lds_bytes(max nv, max nbond).
+// order) written to Fm[rbc_voff[r] + v] (overwritten, not accumulated), so
+// the kernel can run beside the pair kernel.  lds_bytes =
+// membrane_lds_bytes(max nv, max nbond).
 size_t membrane_lds_bytes(int max_nv, int max_nbond);
 void launch_membrane(const MembraneConst &mc, const MeshDev *meshes, const int32_t *rbc_mesh,
-                     const int64_t *rbc_first, int nrbc, State s, const uint32_t *slot_of_gid,
-                     double *av, double *centroid, uint32_t k, float *F, uint32_t *err,
-                     size_t lds_bytes, hipStream_t st);
+                     const int64_t *rbc_first, const int64_t *rbc_voff, int nrbc, State s,
+                     const uint32_t *slot_of_gid, double *av, double *centroid,
+                     const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
+                     hipStream_t st);
 
 }  // namespace tdpd

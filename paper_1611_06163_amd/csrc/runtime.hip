@@ -97,6 +97,16 @@ struct tdpd_sys {
   int64_t nvert = 0;
   size_t mem_lds = 0;  // dynamic LDS of the membrane kernel
   int pair_kernel = 1;  // 0: one thread per particle, 1: cell-tiled
+  int bin_mode = 0;     // 0: counting (one-digit stable) sort, 1: LSD radix sort
+  bool use_graph = true;
+  uint32_t *kdev = nullptr;       // device step counter read by the kernels
+  uint32_t kdev_val = 0;          // host mirror of *kdev
+  uint32_t *cell_count = nullptr, *bin_tmp = nullptr;
+  float *Fm = nullptr;            // membrane forces by global vertex [nvert][3]
+  hipStream_t st2 = nullptr, gst = nullptr;  // membrane stream, capture stream
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
   // event timing per phase (index = log2 of TDPD_PHASE_*)
   int timing_mask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[4];
@@ -121,6 +131,22 @@ struct tdpd_sys {
     if (p) blocks.push_back(p);
     return p;
   }
+  void destroy_graphs() {
+    for (int q = 0; q < 2; ++q) {
+      if (gexec[q]) (void)hipGraphExecDestroy(gexec[q]);
+      if (graph[q]) (void)hipGraphDestroy(graph[q]);
+      gexec[q] = nullptr;
+      graph[q] = nullptr;
+    }
+  }
+  void destroy_streams() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (st2) (void)hipStreamDestroy(st2);
+    if (gst) (void)hipStreamDestroy(gst);
+    ev_fork = ev_join = nullptr;
+    st2 = gst = nullptr;
+  }
   void destroy_events() {
     for (int q = 0; q < 4; ++q) {
       for (auto &e : ev_pool[q]) {
@@ -132,19 +158,19 @@ struct tdpd_sys {
     }
   }
   // start/stop a timed phase; returns false if timing is off for it
-  bool phase_begin(int q) {
+  bool phase_begin(int q, hipStream_t on) {
     if (!(timing_mask & (1 << q))) return false;
     if (ev_used[q] == ev_pool[q].size()) {
       hipEvent_t a, b;
       if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return false;
       ev_pool[q].push_back({a, b});
     }
-    (void)hipEventRecord(ev_pool[q][ev_used[q]].first, st);
+    (void)hipEventRecord(ev_pool[q][ev_used[q]].first, on);
     return true;
   }
-  void phase_end(int q, bool on) {
-    if (!on) return;
-    (void)hipEventRecord(ev_pool[q][ev_used[q]].second, st);
+  void phase_end(int q, bool enabled, hipStream_t on) {
+    if (!enabled) return;
+    (void)hipEventRecord(ev_pool[q][ev_used[q]].second, on);
     ++ev_used[q];
   }
   void release_all() {
@@ -266,6 +292,8 @@ extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn
   mc.ctr3 = pc.ctr3;
   mc.terms = p->terms;
   if (const char *e = std::getenv("TDPD_PAIR_KERNEL")) s->pair_kernel = std::atoi(e);
+  if (const char *e = std::getenv("TDPD_BIN")) s->bin_mode = std::atoi(e);
+  if (const char *e = std::getenv("TDPD_GRAPH")) s->use_graph = std::atoi(e) != 0;
   *out = s;
   return TDPD_OK;
 }
@@ -273,6 +301,9 @@ extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn
 extern "C" void tdpd_destroy(tdpd_sys *s) {
   if (!s) return;
   if (s->uploaded) (void)hipStreamSynchronize(s->st);
+  if (s->st2) (void)hipStreamSynchronize(s->st2);
+  s->destroy_graphs();
+  s->destroy_streams();
   s->destroy_events();
   s->release_all();
   delete s;
@@ -298,6 +329,8 @@ extern "C" int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const fl
       if (!is_finite_f(conc[S * i + sp])) return s->fail(TDPD_ERR_NONFINITE, "set_state: non-finite concentration");
   }
   if (s->uploaded) (void)hipStreamSynchronize(s->st);
+  if (s->st2) (void)hipStreamSynchronize(s->st2);
+  s->destroy_graphs();
   s->release_all();
   s->uploaded = false;
   s->forces_valid = false;
@@ -538,6 +571,13 @@ static int prepare(tdpd_sys *s) {
   s->nzero = dallocT<unsigned long long>(s, 2);
   s->pair_count = s->nzero + 1;
   s->errw = dallocT<uint32_t>(s, 1);
+  s->kdev = dallocT<uint32_t>(s, 1);
+  s->cell_count = dallocT<uint32_t>(s, size_t(s->ncell));
+  s->bin_tmp = dallocT<uint32_t>(s, n);
+  if (!s->kdev || !s->cell_count || !s->bin_tmp) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  HIPCHK(hipMemsetAsync(s->kdev, 0, sizeof(uint32_t), s->st));
+  HIPCHK(hipMemsetAsync(s->cell_count, 0, sizeof(uint32_t) * s->ncell, s->st));
+  s->kdev_val = 0;
   s->diag_partial = dallocT<double>(s, size_t((n + 1023) / 1024 + 1) * (5 + kMaxS));
   s->diag_out = dallocT<double>(s, 5 + kMaxS);
   if (!s->F || !s->Q || !s->keys || !s->vals || !s->keys_tmp || !s->vals_tmp || !s->keys_s ||
@@ -654,7 +694,13 @@ static int prepare(tdpd_sys *s) {
         (rc = upload(s, &s->d_centroid, cen)))
       return rc;
     s->d_av = dallocT<double>(s, 2 * size_t(nrbc));
-    if (!s->d_av) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+    s->Fm = dallocT<float>(s, 3 * size_t(s->nvert));
+    if (!s->d_av || !s->Fm) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+    if (!s->st2) {
+      HIPCHK(hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming));
+    }
     HIPCHK(hipMemsetAsync(s->d_av, 0, sizeof(double) * 2 * nrbc, s->st));
   }
   HIPCHK(hipStreamSynchronize(s->st));  // host vectors may be released after this
@@ -662,48 +708,94 @@ static int prepare(tdpd_sys *s) {
   return TDPD_OK;
 }
 
-// One force evaluation at step counter k, optionally wrapped in the two
-// velocity-Verlet half kicks.
-static int evaluate(tdpd_sys *s, uint32_t k, bool integrate) {
+// Enqueue one force evaluation on stream `st`, optionally wrapped in the two
+// velocity-Verlet half kicks.  The random-number counter is *kdev (set by the
+// caller, or incremented by the first kick).  Host-side only swaps A/B.
+static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   const int64_t n = s->n;
+  const bool tb = s->phase_begin(1, st);
+  launch_prekick(s->pc, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate,
+                 s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, st);
   if (n == 0) {
-    s->forces_valid = true;
+    s->phase_end(1, tb, st);
     return TDPD_OK;
   }
-  hipStream_t st = s->st;
-  const bool tb = s->phase_begin(1);
-  launch_prekick(s->pc, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate, st);
-  radix_sort(s->keys, s->vals, s->keys_tmp, s->vals_tmp, s->keys_s, s->perm, s->hist, n,
-             s->key_bits, st);
-  launch_cell_bounds(s->keys_s, n, s->ncell, s->cell_start, st);
-  launch_reorder(s->cur(), s->nxt(), s->perm, n, s->S, s->slot_of_gid, st);
-  s->phase_end(1, tb);
-  s->cur_A = !s->cur_A;
-  const bool tp = s->phase_begin(0);
-  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
-  // one-thread-per-particle kernel
-  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
-  // it also packs a particle slot into 26 bits of a ring entry
-  if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26))
-    launch_pair_simple(s->pc, s->cur(), s->keys_s, s->cell_start, n, k, s->F, s->Q, s->nzero,
-                       s->errw, st);
-  else
-    launch_pair_tiled(s->pc, s->cur(), s->cell_start, s->ncell, n, k, s->F, s->Q, s->nzero,
-                      s->errw, st);
-  s->phase_end(0, tp);
-  const int nrbc = int(s->rbc_mesh.size());
-  const bool tm = nrbc > 0 && s->phase_begin(2);
-  if (nrbc > 0) {
-    launch_membrane(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, nrbc, s->cur(),
-                    s->slot_of_gid, s->d_av, s->d_centroid, k, s->F, s->errw, s->mem_lds, st);
+  if (s->bin_mode == 0) {
+    launch_bin_counting(s->cur(), s->nxt(), s->keys, s->vals, s->cell_count, s->ncell,
+                        s->cell_start, s->bin_tmp, n, s->S, s->slot_of_gid, s->keys_s, st);
+  } else {
+    radix_sort(s->keys, s->vals, s->keys_tmp, s->vals_tmp, s->keys_s, s->perm, s->hist, n,
+               s->key_bits, st);
+    launch_cell_bounds(s->keys_s, n, s->ncell, s->cell_start, st);
+    launch_reorder(s->cur(), s->nxt(), s->perm, n, s->S, s->slot_of_gid, st);
   }
-  s->phase_end(2, tm);
-  const bool tk = integrate && s->phase_begin(3);
-  if (integrate) launch_postkick(s->pc, s->cur(), s->F, s->Q, n, st);
-  s->phase_end(3, tk);
+  s->phase_end(1, tb, st);
+  s->cur_A = !s->cur_A;
+  const int nrbc = int(s->rbc_mesh.size());
+  // membrane terms on the second stream, beside the pair kernel
+  if (nrbc > 0) {
+    (void)hipEventRecord(s->ev_fork, st);
+    (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
+    const bool tm = s->phase_begin(2, s->st2);
+    launch_membrane(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, s->d_rbc_voff, nrbc,
+                    s->cur(), s->slot_of_gid, s->d_av, s->d_centroid, s->kdev, s->Fm, s->errw,
+                    s->mem_lds, s->st2);
+    s->phase_end(2, tm, s->st2);
+    (void)hipEventRecord(s->ev_join, s->st2);
+  }
+  const bool tp = s->phase_begin(0, st);
+  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
+  // one-thread-per-particle kernel; it also packs a slot into 26 bits
+  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
+  if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26))
+    launch_pair_simple(s->pc, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F, s->Q,
+                       s->nzero, s->errw, st);
+  else
+    launch_pair_tiled(s->pc, s->cur(), s->cell_start, s->ncell, n, s->kdev, s->F, s->Q,
+                      s->nzero, s->errw, st);
+  s->phase_end(0, tp, st);
+  if (nrbc > 0) (void)hipStreamWaitEvent(st, s->ev_join, 0);
+  if (integrate || nrbc > 0) {
+    const bool tk = s->phase_begin(3, st);
+    VertexMap vm{nrbc > 0 ? s->Fm : nullptr, s->d_rbc_first, s->d_rbc_voff};
+    launch_postkick(s->pc, s->cur(), s->F, s->Q, n, vm, integrate, st);
+    s->phase_end(3, tk, st);
+  }
+  return TDPD_OK;
+}
+
+static int check_launch(tdpd_sys *s) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return s->fail(TDPD_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return TDPD_OK;
+}
+
+// Force evaluation at counter k without integration.
+static int evaluate_at(tdpd_sys *s, uint32_t k) {
+  launch_set_counter(s->kdev, k, s->st);
+  s->kdev_val = k;
+  int rc = enqueue_evaluation(s, false, s->st);
+  if (rc) return rc;
   s->forces_valid = true;
+  return check_launch(s);
+}
+
+// Capture one integrated step for each A/B parity on a private stream.
+static int capture_graphs(tdpd_sys *s) {
+  if (!s->gst) HIPCHK(hipStreamCreateWithFlags(&s->gst, hipStreamNonBlocking));
+  const bool start_A = s->cur_A;
+  for (int q = 0; q < 2; ++q) {
+    const int slot = s->cur_A ? 0 : 1;
+    HIPCHK(hipStreamBeginCapture(s->gst, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_evaluation(s, true, s->gst);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->gst, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return s->fail(TDPD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    s->graph[slot] = g;
+    HIPCHK(hipGraphInstantiate(&s->gexec[slot], g, nullptr, nullptr, 0));
+  }
+  if (s->cur_A != start_A) return s->fail(TDPD_ERR_HIP, "graph capture: parity mismatch");
   return TDPD_OK;
 }
 
@@ -711,7 +803,7 @@ extern "C" int tdpd_compute_forces(tdpd_sys *s, uint32_t k) {
   if (!s) return TDPD_ERR_INVALID_ARG;
   int rc = prepare(s);
   if (rc) return rc;
-  return evaluate(s, k, false);
+  return evaluate_at(s, k);
 }
 
 extern "C" int tdpd_step(tdpd_sys *s, int32_t n_steps) {
@@ -719,13 +811,27 @@ extern "C" int tdpd_step(tdpd_sys *s, int32_t n_steps) {
   if (n_steps < 0) return s->fail(TDPD_ERR_INVALID_ARG, "step: negative count");
   int rc = prepare(s);
   if (rc) return rc;
-  if (!s->forces_valid && (rc = evaluate(s, 0, false))) return rc;
-  for (int i = 0; i < n_steps; ++i) {
-    if (s->step >= 0xffffffffLL) return s->fail(TDPD_ERR_UNSUPPORTED, "step counter exhausted");
-    ++s->step;
-    if ((rc = evaluate(s, uint32_t(s->step), true))) return rc;
+  if (!s->forces_valid && (rc = evaluate_at(s, 0))) return rc;
+  if (s->step + n_steps > 0xffffffffLL) return s->fail(TDPD_ERR_UNSUPPORTED, "step counter exhausted");
+  if (n_steps == 0) return TDPD_OK;
+  // the first kick of step n increments the device counter to n
+  if (s->kdev_val != uint32_t(s->step)) {
+    launch_set_counter(s->kdev, uint32_t(s->step), s->st);
+    s->kdev_val = uint32_t(s->step);
   }
-  return TDPD_OK;
+  const bool graphs = s->use_graph && s->timing_mask == 0 && s->n > 0;
+  if (graphs && !s->gexec[0] && (rc = capture_graphs(s))) return rc;
+  for (int i = 0; i < n_steps; ++i) {
+    ++s->step;
+    if (graphs) {
+      HIPCHK(hipGraphLaunch(s->gexec[s->cur_A ? 0 : 1], s->st));
+      s->cur_A = !s->cur_A;
+    } else if ((rc = enqueue_evaluation(s, true, s->st))) {
+      return rc;
+    }
+    ++s->kdev_val;
+  }
+  return check_launch(s);
 }
 
 extern "C" int tdpd_sync(tdpd_sys *s) {
@@ -745,7 +851,7 @@ extern "C" int tdpd_sync(tdpd_sys *s) {
 static int ensure_forces(tdpd_sys *s) {
   int rc = prepare(s);
   if (rc) return rc;
-  if (!s->forces_valid && (rc = evaluate(s, 0, false))) return rc;
+  if (!s->forces_valid && (rc = evaluate_at(s, 0))) return rc;
   return tdpd_sync(s);
 }
 

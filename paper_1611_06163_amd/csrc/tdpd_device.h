@@ -90,6 +90,14 @@ __device__ __forceinline__ float gauss(uint32_t w0, uint32_t w1) {
   return __builtin_amdgcn_sqrtf(r2) * __builtin_amdgcn_cosf(u1);
 }
 
+// Both Box-Muller normals of a word pair: r cos(2 pi u1), r sin(2 pi u1).
+__device__ __forceinline__ void gauss2(uint32_t w0, uint32_t w1, float &c, float &s) {
+  const float u0 = u01(w0), u1 = u01(w1);
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+  c = r * __builtin_amdgcn_cosf(u1);
+  s = r * __builtin_amdgcn_sinf(u1);
+}
+
 // ------------------------------------------------------------ predicate
 // FP32 displacement component x_j + s - x_i, rounded exactly as specified
 // (no contraction), s the periodic image shift.

@@ -9,18 +9,22 @@ from paper_1611_06163_amd import tdpd
 TOL = 1e-5          # per-particle force / flux tolerance, relative to sum_j |term_ij|
 
 
-def gpu_system(cfg, kernel=None, terms=tdpd.TERMS_ALL):
-    old = os.environ.get("TDPD_PAIR_KERNEL")
+def gpu_system(cfg, kernel=None, terms=tdpd.TERMS_ALL, env=None):
+    """Create a GPU system; `kernel` picks the pair kernel (0 simple, 1 tiled)
+    and `env` sets other library switches (TDPD_BIN, TDPD_GRAPH) for it."""
+    env = dict(env or {})
     if kernel is not None:
-        os.environ["TDPD_PAIR_KERNEL"] = str(kernel)
+        env["TDPD_PAIR_KERNEL"] = str(kernel)
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
     try:
         return tdpd.System(cfg, terms=terms)
     finally:
-        if kernel is not None:
-            if old is None:
-                os.environ.pop("TDPD_PAIR_KERNEL", None)
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
             else:
-                os.environ["TDPD_PAIR_KERNEL"] = old
+                os.environ[k] = v
 
 
 def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL, du=2e-7):

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 from scipy import stats
 
-from oracle import philox4x32, u01, pair_normals, pair_normals_batch
+from oracle import philox4x32, u01, pair_normals, pair_normals4, pair_normals_batch
 from paper_1611_06163_amd import inputs as I
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
@@ -73,3 +73,20 @@ def test_draws_decorrelated_across_steps_and_streams():
     d = pair_normals_batch(cfg, 1, gi, gj, 0)[:, 1]
     for x in (b, c, d):
         assert abs(np.corrcoef(a, x)[0, 1]) < 5.0 / np.sqrt(n)
+
+
+def test_four_normals_per_draw():
+    """The cos and sin Box-Muller partners are independent standard normals,
+    and the cos ones equal the single-normal draws."""
+    cfg = I.c1()
+    z = np.array([pair_normals4(cfg, 5, i, i + 3, 64 + (i % 3)) for i in range(20000)])
+    one = np.array([pair_normals(cfg, 5, i, i + 3, 64 + (i % 3)) for i in range(20000)])
+    # (the compiler may evaluate cos and sin together, so allow last-ulp changes)
+    assert np.allclose(z[:, 0], one[:, 0], rtol=1e-14, atol=1e-15)
+    assert np.allclose(z[:, 2], one[:, 1], rtol=1e-14, atol=1e-15)
+    for c in range(4):
+        assert abs(z[:, c].mean()) < 5.0 / np.sqrt(z.shape[0])
+        assert abs(z[:, c].var() - 1.0) < 5.0 * np.sqrt(2.0 / z.shape[0])
+    cc = np.corrcoef(z.T)
+    assert np.abs(cc - np.eye(4)).max() < 5.0 / np.sqrt(z.shape[0])
+    assert stats.kstest(z[:, 1], "norm").pvalue > 1e-4
