@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", type=int, default=None, help="pair kernel: 0 simple, 1 tiled")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device-to-device with torch (a plain "
+                         "copy of known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -152,6 +155,14 @@ def main():
         "diagnostics": {"kT": d["kT"], "P": [float(x) for x in d["P"]]},
     }
     sysg.close()
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)

@@ -106,6 +106,16 @@ typedef struct {
   float gamma_t, gamma_c; /* bond viscosities, Eqs. (15)-(16); 3 gamma_c >= gamma_t */
 } tdpd_mesh_params;
 
+/* One periodic box of a batched ensemble (tdpd_create_batch).  Each box has
+   its own geometry and noise key; the random-number counter uses box-local
+   gids, so a box gives the same trajectory alone and in a batch. */
+typedef struct {
+  float box[3];      /* box lengths */
+  uint64_t seed;     /* Philox key */
+  uint32_t box_id;   /* part of the Philox counter, < 2^24 */
+  float shear_rate;  /* must be 0 (sheared boxes are not supported) */
+} tdpd_box;
+
 typedef struct tdpd_sys tdpd_sys;
 typedef void *(*tdpd_alloc_fn)(size_t bytes, void *user); /* returns device memory or NULL */
 typedef void (*tdpd_free_fn)(void *ptr, void *user);
@@ -117,7 +127,21 @@ typedef void (*tdpd_free_fn)(void *ptr, void *user);
 int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn alloc,
                 tdpd_free_fn free_fn, void *user, tdpd_sys **out);
 
-/* Set the whole particle state: n particles, pos [n][3] (wrapped into the box
+/* Create a batch of n_boxes (1..1024) independent periodic boxes sharing
+   every parameter of p except box, seed and box_id, which come from boxes[].
+   Every phase of a step is one launch over all boxes (and one captured graph
+   per step).  Fills the state with tdpd_set_state_boxes. */
+int tdpd_create_batch(const tdpd_params *p, int32_t n_boxes, const tdpd_box *boxes,
+                      void *hip_stream, tdpd_alloc_fn alloc, tdpd_free_fn free_fn, void *user,
+                      tdpd_sys **out);
+
+/* Set the state of every box: box b owns the next box_count[b] particles of
+   the concatenated arrays (gids are global, box-major); positions are in
+   that box's coordinates.  Same layout and effects as tdpd_set_state. */
+int tdpd_set_state_boxes(tdpd_sys *s, const int64_t *box_count, const float *pos, const float *vel,
+                         const float *conc, const uint32_t *flags);
+
+/* Set the whole particle state of a one-box system: n particles, pos [n][3] (wrapped into the box
    by the library), vel [n][3], conc [n][n_species], flags [n].  All host
    pointers.  Resets the step counter to 0 and drops membranes added before. */
 int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const float *vel,
@@ -133,7 +157,8 @@ int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref_xyz, int32_t ntri,
                   const int32_t *tri, const tdpd_mesh_params *mp, int32_t *mesh_id);
 
 /* Bind particles [first_gid, first_gid + nv) to one cell of mesh mesh_id
-   (vertex v is particle first_gid + v).  Pair forces between vertices of the
+   (vertex v is particle first_gid + v; all in one box, whose half length
+   must exceed 1.25 times the cell's radius plus 1).  Pair forces between vertices of the
    same cell are left to the bonded terms; fluxes act between all pairs. */
 int tdpd_add_rbc(tdpd_sys *s, int32_t mesh_id, int64_t first_gid, int32_t *rbc_id);
 
@@ -179,6 +204,7 @@ int tdpd_set_timing(tdpd_sys *s, int32_t mask);
 int tdpd_get_timing(tdpd_sys *s, int32_t phase, double *total_ms, int64_t *launches);
 
 int64_t tdpd_num_particles(const tdpd_sys *s);
+int32_t tdpd_num_boxes(const tdpd_sys *s);
 int64_t tdpd_step_counter(const tdpd_sys *s);
 /* Number of coincident particle pairs (d^2 == 0) met since set_state. */
 int64_t tdpd_coincident_pairs(tdpd_sys *s);

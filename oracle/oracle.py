@@ -81,6 +81,8 @@ def _load():
                                              C.c_uint32, P]
         L.orc_pair_normals4.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32,
                                         C.c_uint32, C.c_uint32, P]
+        L.orc_disp.restype = C.c_float
+        L.orc_disp.argtypes = [P, P, P, P]
         L.orc_u01.restype = C.c_double
         L.orc_u01.argtypes = [C.c_uint32]
         L.orc_pair_normals.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32,
@@ -206,6 +208,13 @@ class Oracle:
         d = np.zeros((info["ndih"], 4), dtype=np.int32)
         self.L.orc_mesh_topology(self.h, mesh, _ptr(e), _ptr(d))
         return e, d
+
+    def disp(self, xi, xj):
+        a = np.ascontiguousarray(xi, dtype=np.float32)
+        b = np.ascontiguousarray(xj, dtype=np.float32)
+        d = np.zeros(3, dtype=np.float32)
+        d2 = self.L.orc_disp(self.h, _ptr(a), _ptr(b), _ptr(d))
+        return d, np.float32(d2)
 
     def pairs(self, pos_f32, which=0, brute=False, cap=None):
         x = np.ascontiguousarray(pos_f32, dtype=np.float32)

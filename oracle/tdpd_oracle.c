@@ -24,9 +24,11 @@
  *
  * The only FP32 arithmetic is the pair predicate (which particles are within
  * a cutoff), evaluated exactly as specified so that pair sets can be compared
- * bit for bit:  d = fl(fl(x_j + s) - x_i) per axis with s the periodic image
- * shift (0 or +-L) that brings x_j nearest x_i, d2 = fmaf(dz,dz,fmaf(dy,dy,
- * dx*dx)), pair iff 0 < d2 < fl(rcut*rcut).  Build with -ffp-contract=off.
+ * bit for bit:  per axis d = fl(x_j - x_i), except across the periodic
+ * boundary (|x_j - x_i| > L/2), where the coordinate nearer 0 is lifted by L
+ * first: d = fl(fl(x_j + L) - x_i) or fl(x_j - fl(x_i + L)); d2 =
+ * fmaf(dz,dz,fmaf(dy,dy,dx*dx)), pair iff 0 < d2 < fl(rcut*rcut).  The rule
+ * is symmetric: d_ji = -d_ij bit for bit.  Build with -ffp-contract=off.
  *
  * Random numbers: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
  * implemented here from its published definition.  Counter (k, min gid,
@@ -179,17 +181,26 @@ void orc_pair_normals4(const orc_params *p, uint32_t k, uint32_t gi, uint32_t gj
 /* ------------------------------------------------------------ predicate */
 
 /* FP32 displacement x_j - x_i under the nearest periodic image, and its
-   squared length; returns the image shifts through s (may be NULL). */
+   squared length; returns the image shifts of x_j through s (may be NULL).
+   For a pair across the boundary the coordinate nearer 0 is lifted by +L
+   (one rounding, the same from both sides), so d_ji = -d_ij exactly. */
 static float disp_f32(const float *xi, const float *xj, const float *L, float d[3],
                       float s[3]) {
   for (int a = 0; a < 3; ++a) {
     const float raw = xj[a] - xi[a];
     const float half = 0.5f * L[a];
     float sh = 0.0f;
-    if (raw > half) sh = -L[a];
-    else if (raw < -half) sh = L[a];
-    const float xs = xj[a] + sh;
-    d[a] = xs - xi[a];
+    if (raw > half) {          /* x_i near 0: lift x_i */
+      sh = -L[a];
+      const float xl = xi[a] + L[a];
+      d[a] = xj[a] - xl;
+    } else if (raw < -half) {  /* x_j near 0: lift x_j */
+      sh = L[a];
+      const float xl = xj[a] + L[a];
+      d[a] = xl - xi[a];
+    } else {
+      d[a] = raw;
+    }
     if (s) s[a] = sh;
   }
   return fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
@@ -935,4 +946,9 @@ void orc_diag(const orc_sys *s, int64_t n, const double *vel, const double *conc
 void orc_pair_normals_batch(const orc_params *p, uint32_t k, int64_t n, const uint32_t *gi,
                             const uint32_t *gj, uint32_t stream, double *out) {
   for (int64_t q = 0; q < n; ++q) orc_pair_normals(p, k, gi[q], gj[q], stream, out + 2 * q);
+}
+
+/* FP32 displacement of x_j seen from x_i (tests of the predicate rule) */
+float orc_disp(const orc_sys *s, const float *xi, const float *xj, float *d) {
+  return disp_f32(xi, xj, s->p.box, d, NULL);
 }

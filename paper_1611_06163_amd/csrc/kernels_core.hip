@@ -139,7 +139,8 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
 }
 
 // ------------------------------------------------------------- integrator
-__global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const float *__restrict__ F,
+__global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__restrict__ boxes,
+                                                 State s, const float *__restrict__ F,
                                                  const float *__restrict__ Q, int64_t n,
                                                  uint32_t *__restrict__ keys,
                                                  uint32_t *__restrict__ vals, int integrate,
@@ -148,8 +149,10 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const fl
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (integrate && kdev && i == 0) *kdev += 1u;  // step counter read by later kernels
   if (i >= n) return;
+  const uint32_t info = s.info[i];
+  const BoxDev &B = boxes[info_box(info)];
   float x = s.x[i], y = s.y[i], z = s.z[i];
-  if (integrate && !info_frozen(s.info[i])) {
+  if (integrate && !info_frozen(info)) {
     const float h = pc.half_dt;
     float vx = s.vx[i] + h * F[3 * i];
     float vy = s.vy[i] + h * F[3 * i + 1];
@@ -160,7 +163,7 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const fl
     z += pc.dt * vz;
     if (pc.wall_axis >= 0) {
       float *c = pc.wall_axis == 0 ? &x : (pc.wall_axis == 1 ? &y : &z);
-      const float L = pc.L[pc.wall_axis], w = pc.wall_w;
+      const float L = B.L[pc.wall_axis], w = pc.wall_w;
       bool hit = false;
       if (*c < w) {
         *c = 2.f * w - *c;
@@ -175,9 +178,9 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const fl
         vz = -vz;
       }
     }
-    x = wrap_coord(x, pc.L[0]);
-    y = wrap_coord(y, pc.L[1]);
-    z = wrap_coord(z, pc.L[2]);
+    x = wrap_coord(x, B.L[0]);
+    y = wrap_coord(y, B.L[1]);
+    z = wrap_coord(z, B.L[2]);
     s.x[i] = x;
     s.y[i] = y;
     s.z[i] = z;
@@ -185,21 +188,21 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, State s, const fl
     s.vy[i] = vy;
     s.vz[i] = vz;
   }
-  const int cx = cell_coord(x, pc.inv_h[0], pc.nc[0]);
-  const int cy = cell_coord(y, pc.inv_h[1], pc.nc[1]);
-  const int cz = cell_coord(z, pc.inv_h[2], pc.nc[2]);
-  const uint32_t key = uint32_t((cz * pc.nc[1] + cy) * pc.nc[0] + cx);
+  const int cx = cell_coord(x, B.inv_h[0], B.nc[0]);
+  const int cy = cell_coord(y, B.inv_h[1], B.nc[1]);
+  const int cz = cell_coord(z, B.inv_h[2], B.nc[2]);
+  const uint32_t key = B.cell_base + uint32_t((cz * B.nc[1] + cy) * B.nc[0] + cx);
   keys[i] = key;
   // counting binning: the value is this particle's (unordered) rank in its cell
   vals[i] = cell_count ? atomicAdd(&cell_count[key], 1u) : uint32_t(i);
 }
 
-void launch_prekick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
-                    uint32_t *keys, uint32_t *vals, bool integrate, uint32_t *cell_count,
-                    uint32_t *kdev, hipStream_t st) {
+void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
+                    const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
+                    uint32_t *cell_count, uint32_t *kdev, hipStream_t st) {
   const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
-  hipLaunchKernelGGL(k_prekick, dim3(unsigned(nb)), dim3(256), 0, st, pc, s, F, Q, n, keys, vals,
-                     int(integrate), cell_count, kdev);
+  hipLaunchKernelGGL(k_prekick, dim3(unsigned(nb)), dim3(256), 0, st, pc, boxes, s, F, Q, n, keys,
+                     vals, int(integrate), cell_count, kdev);
 }
 
 // ------------------------------------------------------------- counting binning

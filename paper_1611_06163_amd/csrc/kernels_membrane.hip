@@ -23,10 +23,10 @@ __device__ __forceinline__ float3 crs(float3 a, float3 b) {
   return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ float dt3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ float3 rel(const MembraneConst &mc, float3 a, float3 o) {
-  return make_float3(min_image(a.x - o.x, mc.L[0], mc.invL[0]),
-                     min_image(a.y - o.y, mc.L[1], mc.invL[1]),
-                     min_image(a.z - o.z, mc.L[2], mc.invL[2]));
+__device__ __forceinline__ float3 rel(const BoxDev &B, float3 a, float3 o) {
+  return make_float3(min_image(a.x - o.x, B.L[0], B.invL[0]),
+                     min_image(a.y - o.y, B.L[1], B.invL[1]),
+                     min_image(a.z - o.z, B.L[2], B.invL[2]));
 }
 
 // gradient of the signed normal angle of triangles (a,b,c), (d,c,b) with
@@ -60,7 +60,8 @@ size_t membrane_lds_bytes(int max_nv, int max_nbond) {
 }
 
 __global__ void __launch_bounds__(kMemThreads) k_membrane(
-    MembraneConst mc, const MeshDev *__restrict__ meshes, const int32_t *__restrict__ rbc_mesh,
+    MembraneConst mc, const BoxDev *__restrict__ boxes, const MeshDev *__restrict__ meshes,
+    const int32_t *__restrict__ rbc_mesh, const int32_t *__restrict__ rbc_box,
     const int64_t *__restrict__ rbc_first, const int64_t *__restrict__ rbc_voff, State s,
     const uint32_t *__restrict__ slot_of_gid, double *__restrict__ av,
     double *__restrict__ centroid, const uint32_t *__restrict__ kdev, float *__restrict__ Fm,
@@ -71,6 +72,7 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
   const int r = blockIdx.x, tid = threadIdx.x;
   const uint32_t k = *kdev;
   const MeshDev &M = meshes[rbc_mesh[r]];
+  const BoxDev &B = boxes[rbc_box[r]];
   const int nv = M.nv;
   float *px = lds, *py = px + nv, *pz = py + nv, *wx = pz + nv, *wy = wx + nv, *wz = wy + nv;
   uint32_t *sl = reinterpret_cast<uint32_t *>(wz + nv);
@@ -96,15 +98,15 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
                                   float(centroid[3 * r + 2]));
     double acc[5] = {0, 0, 0, 0, 0};
     for (int t = tid; t < M.ntri; t += kMemThreads) {
-      const float3 a = rel(mc, P(M.tri[3 * t]), cf);
-      const float3 b = rel(mc, P(M.tri[3 * t + 1]), cf);
-      const float3 c = rel(mc, P(M.tri[3 * t + 2]), cf);
+      const float3 a = rel(B, P(M.tri[3 * t]), cf);
+      const float3 b = rel(B, P(M.tri[3 * t + 1]), cf);
+      const float3 c = rel(B, P(M.tri[3 * t + 2]), cf);
       const float3 nn = crs(sub(b, a), sub(c, a));
       acc[0] += double(0.5f * sqrtf(dt3(nn, nn)));
       acc[1] += double(dt3(a, crs(b, c)) * (1.f / 6.f));
     }
     for (int v = tid; v < nv; v += kMemThreads) {
-      const float3 a = rel(mc, P(v), cf);
+      const float3 a = rel(B, P(v), cf);
       acc[2] += a.x;
       acc[3] += a.y;
       acc[4] += a.z;
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
     const float cc = sqrtf(fmaxf(3.f * M.gamma_c - M.gamma_t, 0.f)) * (1.f / 3.f);
     for (int bnd = tid; bnd < M.nbond; bnd += kMemThreads) {
       const int2 ab = M.bond_ab[bnd];
-      const float3 d = rel(mc, P(ab.y), P(ab.x));  // a -> b
+      const float3 d = rel(B, P(ab.y), P(ab.x));  // a -> b
       const float l = sqrtf(dt3(d, d));
       const float il = 1.f / l;
       float3 f = make_float3(0.f, 0.f, 0.f);
@@ -164,12 +166,13 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
         f.z += -M.gamma_t * vr.z - M.gamma_c * ve * e.z;
       }
       if (terms & TDPD_TERM_BOND_RANDOM) {
-        // a < b locally and gids are consecutive, so (g0+a, g0+b) is ordered
-        const uint32_t ga = uint32_t(g0 + ab.x), gb = uint32_t(g0 + ab.y);
+        // a < b locally and gids are consecutive, so (g0+a, g0+b) is ordered;
+        // the counter takes box-local gids
+        const uint32_t ga = uint32_t(g0 + ab.x) - B.gid_base, gb = uint32_t(g0 + ab.y) - B.gid_base;
         float W[12];  // streams 64..66: (cos, sin) of words (0,1) then (2,3); first 9 used
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          const u32x4 z = philox10(k, ga, gb, mc.ctr3 | uint32_t(64 + q), mc.seed_lo, mc.seed_hi);
+          const u32x4 z = philox10(k, ga, gb, B.ctr3 | uint32_t(64 + q), B.seed_lo, B.seed_hi);
           gauss2(z.a, z.b, W[4 * q], W[4 * q + 1]);
           gauss2(z.c, z.d, W[4 * q + 2], W[4 * q + 3]);
         }
@@ -218,8 +221,8 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
     if (terms & (TDPD_TERM_AREA | TDPD_TERM_VOLUME)) {
       for (int q = M.tri_off[v]; q < M.tri_off[v + 1]; ++q) {
         const int4 tr = M.tri_inc[q];  // (b, c, triangle, -), v first, counter-clockwise
-        const float3 rb = rel(mc, P(tr.x), pv);
-        const float3 rc = rel(mc, P(tr.y), pv);
+        const float3 rb = rel(B, P(tr.x), pv);
+        const float3 rc = rel(B, P(tr.y), pv);
         const float3 nn = crs(rb, rc);
         if (terms & TDPD_TERM_AREA) {
           const float nl = sqrtf(dt3(nn, nn));
@@ -244,10 +247,10 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
       for (int q = M.dih_off[v]; q < M.dih_off[v + 1]; ++q) {
         const int4 D = M.dih_inc[q];
         const int role = M.dih_role[q];
-        const float3 a = role == 0 ? zero3 : rel(mc, P(D.x), pv);
-        const float3 b = role == 1 ? zero3 : rel(mc, P(D.y), pv);
-        const float3 c = role == 2 ? zero3 : rel(mc, P(D.z), pv);
-        const float3 d = role == 3 ? zero3 : rel(mc, P(D.w), pv);
+        const float3 a = role == 0 ? zero3 : rel(B, P(D.x), pv);
+        const float3 b = role == 1 ? zero3 : rel(B, P(D.y), pv);
+        const float3 c = role == 2 ? zero3 : rel(B, P(D.z), pv);
+        const float3 d = role == 3 ? zero3 : rel(B, P(D.w), pv);
         float sn, cs;
         const float3 g = dihedral_grad(a, b, c, d, role, sn, cs);
         const float coef = -M.kb * (sn * c0 - cs * s0);  // -kb sin(theta - theta0)
@@ -264,14 +267,16 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
   }
 }
 
-void launch_membrane(const MembraneConst &mc, const MeshDev *meshes, const int32_t *rbc_mesh,
-                     const int64_t *rbc_first, const int64_t *rbc_voff, int nrbc, State s,
+void launch_membrane(const MembraneConst &mc, const BoxDev *boxes, const MeshDev *meshes,
+                     const int32_t *rbc_mesh, const int32_t *rbc_box, const int64_t *rbc_first,
+                     const int64_t *rbc_voff, int nrbc, State s,
                      const uint32_t *slot_of_gid, double *av, double *centroid,
                      const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
                      hipStream_t st) {
   if (nrbc <= 0) return;
-  hipLaunchKernelGGL(k_membrane, dim3(nrbc), dim3(kMemThreads), lds_bytes, st, mc, meshes, rbc_mesh,
-                     rbc_first, rbc_voff, s, slot_of_gid, av, centroid, kdev, Fm, err);
+  hipLaunchKernelGGL(k_membrane, dim3(nrbc), dim3(kMemThreads), lds_bytes, st, mc, boxes, meshes,
+                     rbc_mesh, rbc_box, rbc_first, rbc_voff, s, slot_of_gid, av, centroid, kdev, Fm,
+                     err);
 }
 
 }  // namespace tdpd

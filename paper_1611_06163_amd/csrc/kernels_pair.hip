@@ -17,7 +17,8 @@ struct PairAcc {
   float q[kMaxS];
 };
 
-__device__ __forceinline__ void pair_term(const PairConst &pc, float dx, float dy, float dz, float d2,
+__device__ __forceinline__ void pair_term(const PairConst &pc, const BoxDev &B, float dx, float dy,
+                                          float dz, float d2,
                                           float vxi, float vyi, float vzi, float vxj, float vyj,
                                           float vzj, const float *ci, const float *cj, int ti,
                                           int tj, bool same_body, uint32_t gi, uint32_t gj,
@@ -31,7 +32,7 @@ __device__ __forceinline__ void pair_term(const PairConst &pc, float dx, float d
       (d2 < pc.rc2 && !same_body && (pc.terms & TDPD_TERM_RANDOM)) ||
       (d2 < pc.rcc2 && pc.ms_rho > 0.f && (pc.terms & TDPD_TERM_FLUX_RANDOM));
   u32x4 w = {0, 0, 0, 0};
-  if (need_noise) w = philox10(k, lo, hi, pc.ctr3, pc.seed_lo, pc.seed_hi);
+  if (need_noise) w = philox10(k, lo, hi, B.ctr3, B.seed_lo, B.seed_hi);
   if (d2 < pc.rc2 && !same_body) {
     const int tt = ti * pc.n_types + tj;
     const float wc = fmaxf(1.f - r * pc.inv_rc, 0.f);
@@ -60,8 +61,8 @@ __device__ __forceinline__ void pair_term(const PairConst &pc, float dx, float d
         if (sp == 0) {
           z = gauss(w.c, w.d);
         } else {
-          const u32x4 w2 = philox10(k, lo, hi, pc.ctr3 | uint32_t((sp + 1) >> 1), pc.seed_lo,
-                                    pc.seed_hi);
+          const u32x4 w2 = philox10(k, lo, hi, B.ctr3 | uint32_t((sp + 1) >> 1), B.seed_lo,
+                                    B.seed_hi);
           z = (sp & 1) ? gauss(w2.a, w2.b) : gauss(w2.c, w2.d);
         }
         if (gi > gj) z = -z;  // zeta_ij = -zeta_ji
@@ -75,7 +76,8 @@ __device__ __forceinline__ void pair_term(const PairConst &pc, float dx, float d
 // ------------------------------------------------------------ simple kernel
 // One thread per home particle (sorted order), scanning the 27 neighbour
 // cells of its own cell in global memory.
-__global__ void __launch_bounds__(256) k_pair_simple(PairConst pc, State s,
+__global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
+                                                     const BoxDev *__restrict__ boxes, State s,
                                                      const uint32_t *__restrict__ cell_keys,
                                                      const uint32_t *__restrict__ cell_start,
                                                      int64_t n, const uint32_t *__restrict__ kdev,
@@ -94,29 +96,30 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc, State s,
     const float vxi = s.vx[i], vyi = s.vy[i], vzi = s.vz[i];
     float ci[kMaxS], cj[kMaxS];
     for (int sp = 0; sp < S; ++sp) ci[sp] = s.C[sp * n + i];
-    const uint32_t gi = s.gid[i];
+    const BoxDev &B = boxes[info_box(infoi)];
+    const uint32_t gi = s.gid[i] - B.gid_base;
     const int ti = info_type(infoi), bi = info_body(infoi);
-    const uint32_t key = cell_keys[i];
-    const int cx = int(key % uint32_t(pc.nc[0]));
-    const int cy = int((key / uint32_t(pc.nc[0])) % uint32_t(pc.nc[1]));
-    const int cz = int(key / uint32_t(pc.nc[0] * pc.nc[1]));
+    const uint32_t key = cell_keys[i] - B.cell_base;
+    const int cx = int(key % uint32_t(B.nc[0]));
+    const int cy = int((key / uint32_t(B.nc[0])) % uint32_t(B.nc[1]));
+    const int cz = int(key / uint32_t(B.nc[0] * B.nc[1]));
     unsigned zero = 0;
     for (int dz = -1; dz <= 1; ++dz) {
       int qz = cz + dz;
       float sz = 0.f;
-      if (qz < 0) { qz += pc.nc[2]; sz = -pc.L[2]; }
-      else if (qz >= pc.nc[2]) { qz -= pc.nc[2]; sz = pc.L[2]; }
+      if (qz < 0) { qz += B.nc[2]; sz = -B.L[2]; }
+      else if (qz >= B.nc[2]) { qz -= B.nc[2]; sz = B.L[2]; }
       for (int dy = -1; dy <= 1; ++dy) {
         int qy = cy + dy;
         float sy = 0.f;
-        if (qy < 0) { qy += pc.nc[1]; sy = -pc.L[1]; }
-        else if (qy >= pc.nc[1]) { qy -= pc.nc[1]; sy = pc.L[1]; }
+        if (qy < 0) { qy += B.nc[1]; sy = -B.L[1]; }
+        else if (qy >= B.nc[1]) { qy -= B.nc[1]; sy = B.L[1]; }
         for (int dx = -1; dx <= 1; ++dx) {
           int qx = cx + dx;
           float sx = 0.f;
-          if (qx < 0) { qx += pc.nc[0]; sx = -pc.L[0]; }
-          else if (qx >= pc.nc[0]) { qx -= pc.nc[0]; sx = pc.L[0]; }
-          const uint32_t c = uint32_t((qz * pc.nc[1] + qy) * pc.nc[0] + qx);
+          if (qx < 0) { qx += B.nc[0]; sx = -B.L[0]; }
+          else if (qx >= B.nc[0]) { qx -= B.nc[0]; sx = B.L[0]; }
+          const uint32_t c = B.cell_base + uint32_t((qz * B.nc[1] + qy) * B.nc[0] + qx);
           const uint32_t j0 = cell_start[c], j1 = cell_start[c + 1];
           for (uint32_t j = j0; j < j1; ++j) {
             const float ddx = disp(s.x[j], sx, xi);
@@ -131,8 +134,8 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc, State s,
             const uint32_t infoj = s.info[j];
             const int bj = info_body(infoj);
             for (int sp = 0; sp < S; ++sp) cj[sp] = s.C[sp * n + j];
-            pair_term(pc, ddx, ddy, ddz, d2, vxi, vyi, vzi, s.vx[j], s.vy[j], s.vz[j], ci, cj, ti,
-                      info_type(infoj), bi >= 0 && bi == bj, gi, s.gid[j], k, acc);
+            pair_term(pc, B, ddx, ddy, ddz, d2, vxi, vyi, vzi, s.vx[j], s.vy[j], s.vz[j], ci, cj, ti,
+                      info_type(infoj), bi >= 0 && bi == bj, gi, s.gid[j] - B.gid_base, k, acc);
           }
         }
       }
@@ -151,16 +154,18 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc, State s,
   for (int sp = 0; sp < S; ++sp) Q[S * i + sp] = acc.q[sp];
 }
 
-void launch_pair_simple(const PairConst &pc, State s, const uint32_t *cell_keys,
-                        const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
-                        float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st) {
+void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
+                        const uint32_t *cell_keys, const uint32_t *cell_start, int64_t n,
+                        const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
+                        uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_pair_simple, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s,
+  hipLaunchKernelGGL(k_pair_simple, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, boxes, s,
                      cell_keys, cell_start, n, kdev, F, Q, nzero, err);
 }
 
 // ------------------------------------------------------------ pair listing
-__global__ void __launch_bounds__(256) k_pair_emit(PairConst pc, State s,
+__global__ void __launch_bounds__(256) k_pair_emit(PairConst pc, const BoxDev *__restrict__ boxes,
+                                                   State s,
                                                    const uint32_t *__restrict__ cell_keys,
                                                    const uint32_t *__restrict__ cell_start,
                                                    int64_t n, float rcut2, int32_t *out,
@@ -169,26 +174,27 @@ __global__ void __launch_bounds__(256) k_pair_emit(PairConst pc, State s,
   if (i >= n) return;
   const float xi = s.x[i], yi = s.y[i], zi = s.z[i];
   const uint32_t gi = s.gid[i];
-  const uint32_t key = cell_keys[i];
-  const int cx = int(key % uint32_t(pc.nc[0]));
-  const int cy = int((key / uint32_t(pc.nc[0])) % uint32_t(pc.nc[1]));
-  const int cz = int(key / uint32_t(pc.nc[0] * pc.nc[1]));
+  const BoxDev &B = boxes[info_box(s.info[i])];
+  const uint32_t key = cell_keys[i] - B.cell_base;
+  const int cx = int(key % uint32_t(B.nc[0]));
+  const int cy = int((key / uint32_t(B.nc[0])) % uint32_t(B.nc[1]));
+  const int cz = int(key / uint32_t(B.nc[0] * B.nc[1]));
   for (int dz = -1; dz <= 1; ++dz) {
     int qz = cz + dz;
     float sz = 0.f;
-    if (qz < 0) { qz += pc.nc[2]; sz = -pc.L[2]; }
-    else if (qz >= pc.nc[2]) { qz -= pc.nc[2]; sz = pc.L[2]; }
+    if (qz < 0) { qz += B.nc[2]; sz = -B.L[2]; }
+    else if (qz >= B.nc[2]) { qz -= B.nc[2]; sz = B.L[2]; }
     for (int dy = -1; dy <= 1; ++dy) {
       int qy = cy + dy;
       float sy = 0.f;
-      if (qy < 0) { qy += pc.nc[1]; sy = -pc.L[1]; }
-      else if (qy >= pc.nc[1]) { qy -= pc.nc[1]; sy = pc.L[1]; }
+      if (qy < 0) { qy += B.nc[1]; sy = -B.L[1]; }
+      else if (qy >= B.nc[1]) { qy -= B.nc[1]; sy = B.L[1]; }
       for (int dx = -1; dx <= 1; ++dx) {
         int qx = cx + dx;
         float sx = 0.f;
-        if (qx < 0) { qx += pc.nc[0]; sx = -pc.L[0]; }
-        else if (qx >= pc.nc[0]) { qx -= pc.nc[0]; sx = pc.L[0]; }
-        const uint32_t c = uint32_t((qz * pc.nc[1] + qy) * pc.nc[0] + qx);
+        if (qx < 0) { qx += B.nc[0]; sx = -B.L[0]; }
+        else if (qx >= B.nc[0]) { qx -= B.nc[0]; sx = B.L[0]; }
+        const uint32_t c = B.cell_base + uint32_t((qz * B.nc[1] + qy) * B.nc[0] + qx);
         for (uint32_t j = cell_start[c]; j < cell_start[c + 1]; ++j) {
           const uint32_t gj = s.gid[j];
           if (gj <= gi) continue;
@@ -206,11 +212,12 @@ __global__ void __launch_bounds__(256) k_pair_emit(PairConst pc, State s,
   }
 }
 
-void launch_pair_emit(const PairConst &pc, State s, const uint32_t *cell_keys,
-                      const uint32_t *cell_start, int64_t n, float rcut2, int32_t *out,
-                      int64_t cap, unsigned long long *count, hipStream_t st) {
+void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
+                      const uint32_t *cell_keys, const uint32_t *cell_start, int64_t n,
+                      float rcut2, int32_t *out, int64_t cap, unsigned long long *count,
+                      hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_pair_emit, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s,
+  hipLaunchKernelGGL(k_pair_emit, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, boxes, s,
                      cell_keys, cell_start, n, rcut2, out, cap, count);
 }
 

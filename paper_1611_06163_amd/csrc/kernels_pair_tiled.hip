@@ -73,7 +73,7 @@ struct TiledShared {
 // window (entries are appended in home order and the ring is flushed at the
 // end of each register block), so run leaders never collide.
 template <int NS>
-__device__ __forceinline__ void flush_ring(const PairConst &pc, const State &s,
+__device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B, const State &s,
                                            TiledShared<NS> &sh, int w, uint32_t head, int m,
                                            uint32_t k) {
   const int lane = threadIdx.x & 63;
@@ -85,9 +85,10 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const State &s,
     hi_i = int(wd >> kJBits);
     const uint32_t j = wd & ((1u << kJBits) - 1);
     const float dx = sh.rd[w][0][e], dy = sh.rd[w][1][e], dz = sh.rd[w][2][e];
-    const float3 f = force_term(pc, dx, dy, dz, dist2(dx, dy, dz), sh.hvx[hi_i], sh.hvy[hi_i],
+    const float3 f = force_term(pc, B, dx, dy, dz, dist2(dx, dy, dz), sh.hvx[hi_i], sh.hvy[hi_i],
                                 sh.hvz[hi_i], s.vx[j], s.vy[j], s.vz[j], info_type(sh.hinfo[hi_i]),
-                                info_type(s.info[j]), sh.hgid[hi_i], s.gid[j], k);
+                                info_type(s.info[j]), sh.hgid[hi_i] - B.gid_base,
+                                s.gid[j] - B.gid_base, k);
     sh.rd[w][0][e] = f.x;
     sh.rd[w][1][e] = f.y;
     sh.rd[w][2][e] = f.z;
@@ -114,7 +115,9 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const State &s,
 }
 
 template <int NS>
-__global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State s,
+__global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
+                                                            const BoxDev *__restrict__ boxes,
+                                                            State s,
                                                             const uint32_t *__restrict__ cell_start,
                                                             int64_t ncell, int64_t per_xcd,
                                                             int64_t n,
@@ -132,16 +135,18 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
   const int64_t cell = (b & 7) * per_xcd + (b >> 3);
   if (cell >= ncell) return;
   const int S = pc.n_species, T = pc.n_types;
-  const int nx = pc.nc[0], ny = pc.nc[1], nz = pc.nc[2];
-  const int cx = int(cell % nx), cy = int((cell / nx) % ny), cz = int(cell / (int64_t(nx) * ny));
+  const BoxDev &B = boxes[box_of_cell(boxes, pc.n_boxes, uint32_t(cell))];
+  const int nx = B.nc[0], ny = B.nc[1], nz = B.nc[2];
+  const int64_t lc = cell - B.cell_base;  // cell index inside its box
+  const int cx = int(lc % nx), cy = int((lc / nx) % ny), cz = int(lc / (int64_t(nx) * ny));
   if (tid < 27) {
     const int dz = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dx = tid % 3 - 1;
     int qx = cx + dx, qy = cy + dy, qz = cz + dz;
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    if (qx < 0) { qx += nx; sx = -pc.L[0]; } else if (qx >= nx) { qx -= nx; sx = pc.L[0]; }
-    if (qy < 0) { qy += ny; sy = -pc.L[1]; } else if (qy >= ny) { qy -= ny; sy = pc.L[1]; }
-    if (qz < 0) { qz += nz; sz = -pc.L[2]; } else if (qz >= nz) { qz -= nz; sz = pc.L[2]; }
-    const int64_t q = (int64_t(qz) * ny + qy) * nx + qx;
+    if (qx < 0) { qx += nx; sx = -B.L[0]; } else if (qx >= nx) { qx -= nx; sx = B.L[0]; }
+    if (qy < 0) { qy += ny; sy = -B.L[1]; } else if (qy >= ny) { qy -= ny; sy = B.L[1]; }
+    if (qz < 0) { qz += nz; sz = -B.L[2]; } else if (qz >= nz) { qz -= nz; sz = B.L[2]; }
+    const int64_t q = B.cell_base + (int64_t(qz) * ny + qy) * nx + qx;
     const uint32_t a0 = cell_start[q], a1 = cell_start[q + 1];
     sh.seg_start[tid] = int(a0);
     sh.seg_pref[tid + 1] = int(a1 - a0);  // counts, prefixed below
@@ -183,8 +188,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
     uint32_t head = 0, tail = 0;  // this wave's ring cursors (wave-uniform)
 
     for (int cb = 0; cb < my_chunks; cb += kChunks) {
+      // candidate coordinates, lifted by +L where the candidate sits across
+      // the low boundary; lift[kk] bit a says the home coordinate is lifted
+      // instead (candidate across the high boundary)
       float cxs[kChunks], cys[kChunks], czs[kChunks], cc[kChunks][NS];
-      uint32_t cj[kChunks];
+      uint32_t cj[kChunks], lift[kChunks];
       int ct[kChunks], cbody[kChunks];
       bool cv[kChunks];
 #pragma unroll
@@ -194,6 +202,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
         cv[kk] = (cb + kk) < my_chunks && t < ncand;
         cxs[kk] = cys[kk] = czs[kk] = 0.f;
         cj[kk] = 0;
+        lift[kk] = 0;
         ct[kk] = 0;
         cbody[kk] = -2;
 #pragma unroll
@@ -207,9 +216,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
           }
           const uint32_t j = uint32_t(sh.seg_start[lo] + (t - sh.seg_pref[lo]));
           cj[kk] = j;
-          cxs[kk] = __fadd_rn(s.x[j], sh.seg_sh[lo][0]);
-          cys[kk] = __fadd_rn(s.y[j], sh.seg_sh[lo][1]);
-          czs[kk] = __fadd_rn(s.z[j], sh.seg_sh[lo][2]);
+          const float sx = sh.seg_sh[lo][0], sy = sh.seg_sh[lo][1], sz = sh.seg_sh[lo][2];
+          cxs[kk] = sx > 0.f ? __fadd_rn(s.x[j], sx) : s.x[j];
+          cys[kk] = sy > 0.f ? __fadd_rn(s.y[j], sy) : s.y[j];
+          czs[kk] = sz > 0.f ? __fadd_rn(s.z[j], sz) : s.z[j];
+          lift[kk] = (sx < 0.f ? 1u : 0u) | (sy < 0.f ? 2u : 0u) | (sz < 0.f ? 4u : 0u);
           const uint32_t inf = s.info[j];
           ct[kk] = info_type(inf);
           cbody[kk] = info_body(inf);
@@ -223,6 +234,8 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
         const uint32_t infoi = sh.hinfo[i];
         if (info_frozen(infoi)) continue;
         const float xi = sh.hx[i], yi = sh.hy[i], zi = sh.hz[i];
+        const float xil = __fadd_rn(xi, B.L[0]), yil = __fadd_rn(yi, B.L[1]),
+                    zil = __fadd_rn(zi, B.L[2]);
         const int ti = info_type(infoi), bi = info_body(infoi);
         const uint32_t self = uint32_t(hb + i);
         float qp[NS], ci[NS], kr[NS][kMaxT];
@@ -237,9 +250,9 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
 #pragma unroll
         for (int kk = 0; kk < kChunks; ++kk) {
           if (cb + kk >= my_chunks) break;  // wave-uniform
-          const float dx = __fsub_rn(cxs[kk], xi);
-          const float dy = __fsub_rn(cys[kk], yi);
-          const float dz = __fsub_rn(czs[kk], zi);
+          const float dx = __fsub_rn(cxs[kk], (lift[kk] & 1u) ? xil : xi);
+          const float dy = __fsub_rn(cys[kk], (lift[kk] & 2u) ? yil : yi);
+          const float dz = __fsub_rn(czs[kk], (lift[kk] & 4u) ? zil : zi);
           const float d2 = dist2(dx, dy, dz);
           const bool live = cv[kk] && d2 > 0.f;
           zero += (cv[kk] && d2 == 0.f && cj[kk] != self) ? 1u : 0u;
@@ -262,7 +275,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
             }
             tail += uint32_t(__popcll(fm));
             if (tail - head >= 64) {
-              flush_ring<NS>(pc, s, sh, w, head, 64, k);
+              flush_ring<NS>(pc, B, s, sh, w, head, 64, k);
               head += 64;
             }
           }
@@ -277,7 +290,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
       // ever mixes entries of two blocks (which would repeat home indices)
       while (tail != head) {
         const int m = int(min(tail - head, 64u));
-        flush_ring<NS>(pc, s, sh, w, head, m, k);
+        flush_ring<NS>(pc, B, s, sh, w, head, m, k);
         head += uint32_t(m);
       }
     }
@@ -318,23 +331,24 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc, State 
   if (zero) atomicAdd(nzero, (unsigned long long)zero);
 }
 
-void launch_pair_tiled(const PairConst &pc, State s, const uint32_t *cell_start, int64_t ncell,
+void launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
+                       const uint32_t *cell_start, int64_t ncell,
                        int64_t n, const uint32_t *kdev, float *F, float *Q,
                        unsigned long long *nzero, uint32_t *err, hipStream_t st) {
   if (n <= 0 || ncell <= 0) return;
   const int64_t per_xcd = (ncell + 7) / 8;
   const dim3 grid(unsigned(per_xcd * 8)), block(64 * kWaves);
   if (pc.n_species <= 1)
-    hipLaunchKernelGGL(k_pair_tiled<1>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
+    hipLaunchKernelGGL(k_pair_tiled<1>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
                        kdev, F, Q, nzero, err);
   else if (pc.n_species == 2)
-    hipLaunchKernelGGL(k_pair_tiled<2>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
+    hipLaunchKernelGGL(k_pair_tiled<2>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
                        kdev, F, Q, nzero, err);
   else if (pc.n_species <= 4)
-    hipLaunchKernelGGL(k_pair_tiled<4>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
+    hipLaunchKernelGGL(k_pair_tiled<4>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
                        kdev, F, Q, nzero, err);
   else
-    hipLaunchKernelGGL(k_pair_tiled<8>, grid, block, 0, st, pc, s, cell_start, ncell, per_xcd, n,
+    hipLaunchKernelGGL(k_pair_tiled<8>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
                        kdev, F, Q, nzero, err);
 }
 

@@ -20,9 +20,9 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
 // With cell_count, vals gets the particle's unordered rank in its cell (the
 // counting binning); else vals = index (the radix binning).  With integrate
 // and kdev, the device step counter *kdev is incremented.
-void launch_prekick(const PairConst &pc, State s, const float *F, const float *Q, int64_t n,
-                    uint32_t *keys, uint32_t *vals, bool integrate, uint32_t *cell_count,
-                    uint32_t *kdev, hipStream_t st);
+void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
+                    const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
+                    uint32_t *cell_count, uint32_t *kdev, hipStream_t st);
 // Counting binning after launch_prekick: scan of the cell counts into
 // cell_start (counts zeroed for the next step), scatter, and the rank fix-up
 // fused with the reorder of every state plane into dst (slot_of_gid and the
@@ -52,15 +52,18 @@ void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st);
 // Pair forces and fluxes, one thread per particle (sorted order).
 // The random-number step counter k is read from device memory (*kdev) so a
 // captured graph of a step stays valid from step to step.
-void launch_pair_simple(const PairConst &pc, State s, const uint32_t *cell_keys,
+void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
+                        const uint32_t *cell_keys,
                         const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
                         float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st);
 // Pair forces and fluxes, cell-tiled kernel (one wavefront per home cell).
-void launch_pair_tiled(const PairConst &pc, State s, const uint32_t *cell_start, int64_t ncell,
+void launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
+                       const uint32_t *cell_start, int64_t ncell,
                        int64_t n, const uint32_t *kdev, float *F, float *Q,
                        unsigned long long *nzero, uint32_t *err, hipStream_t st);
 // Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
-void launch_pair_emit(const PairConst &pc, State s, const uint32_t *cell_keys,
+void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
+                      const uint32_t *cell_keys,
                       const uint32_t *cell_start, int64_t n, float rcut2, int32_t *out,
                       int64_t cap, unsigned long long *count, hipStream_t st);
 
@@ -91,9 +94,7 @@ struct MeshDev {
 };
 
 struct MembraneConst {
-  float L[3], invL[3];
   float kT, dt;
-  uint32_t seed_lo, seed_hi, ctr3;
   int terms;
 };
 
@@ -105,8 +106,9 @@ struct MembraneConst {
 // the kernel can run beside the pair kernel.  lds_bytes =
 // membrane_lds_bytes(max nv, max nbond).
 size_t membrane_lds_bytes(int max_nv, int max_nbond);
-void launch_membrane(const MembraneConst &mc, const MeshDev *meshes, const int32_t *rbc_mesh,
-                     const int64_t *rbc_first, const int64_t *rbc_voff, int nrbc, State s,
+void launch_membrane(const MembraneConst &mc, const BoxDev *boxes, const MeshDev *meshes,
+                     const int32_t *rbc_mesh, const int32_t *rbc_box, const int64_t *rbc_first,
+                     const int64_t *rbc_voff, int nrbc, State s,
                      const uint32_t *slot_of_gid, double *av, double *centroid,
                      const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
                      hipStream_t st);

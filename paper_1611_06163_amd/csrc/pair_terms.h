@@ -6,12 +6,13 @@
 
 namespace tdpd {
 
-// Force of pair (i,j) on i at FP32 displacement d = x_j + s - x_i with
-// d2 = |d|^2, 0 < d2 < rc2, i and j not in the same cell body.
+// Force of pair (i,j) on i at FP32 displacement d (of x_j seen from x_i)
+// with d2 = |d|^2, 0 < d2 < rc2, i and j not in the same cell body.
 // e_ij = -d/r points from j to i; v_ij = v_i - v_j; the noise xi is the
-// Box-Muller normal of Philox stream 0, words (0,1), for the unordered gid
-// pair at step k, so F_ij = -F_ji exactly.
-__device__ __forceinline__ float3 force_term(const PairConst &pc, float dx, float dy, float dz,
+// Box-Muller normal of Philox stream 0, words (0,1), for the unordered pair
+// of box-local gids at step k under the box's key, so F_ij = -F_ji exactly.
+__device__ __forceinline__ float3 force_term(const PairConst &pc, const BoxDev &B, float dx,
+                                             float dy, float dz,
                                              float d2, float vxi, float vyi, float vzi, float vxj,
                                              float vyj, float vzj, int ti, int tj, uint32_t gi,
                                              uint32_t gj, uint32_t k) {
@@ -29,7 +30,7 @@ __device__ __forceinline__ float3 force_term(const PairConst &pc, float dx, floa
   }
   if (pc.terms & TDPD_TERM_RANDOM) {
     const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
-    const u32x4 w = philox10(k, lo, hi, pc.ctr3, pc.seed_lo, pc.seed_hi);
+    const u32x4 w = philox10(k, lo, hi, B.ctr3, B.seed_lo, B.seed_hi);
     fs += pc.sigma[tt] * wr * gauss(w.a, w.b) * pc.isdt;
   }
   return make_float3(fs * ex, fs * ey, fs * ez);

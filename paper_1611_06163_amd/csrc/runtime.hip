@@ -55,8 +55,19 @@ static double d_theta(const double *a, const double *b, const double *c, const d
 
 }  // namespace
 
+struct HostBox {
+  float L[3] = {0, 0, 0};
+  int nc[3] = {0, 0, 0};
+  int64_t ncell = 0, cell_base = 0;
+  int64_t gid_base = 0, n = 0;
+  uint64_t seed = 0;
+  uint32_t box_id = 0;
+};
+
 struct tdpd_sys {
   tdpd_params prm{};
+  std::vector<HostBox> boxes;
+  BoxDev *d_boxes = nullptr;
   PairConst pc{};
   MembraneConst mc{};
   hipStream_t st = nullptr;
@@ -76,6 +87,7 @@ struct tdpd_sys {
   // host copies kept until upload
   std::vector<float> h_pos, h_vel, h_conc;
   std::vector<uint32_t> h_flags;
+  std::vector<int32_t> h_box, h_body;
 
   State A{}, B{};
   bool cur_A = true;
@@ -88,10 +100,10 @@ struct tdpd_sys {
   double *diag_partial = nullptr, *diag_out = nullptr;
 
   std::vector<HostMesh> meshes;
-  std::vector<int32_t> rbc_mesh;
+  std::vector<int32_t> rbc_mesh, rbc_box;
   std::vector<int64_t> rbc_first, rbc_voff;
   MeshDev *d_meshes = nullptr;
-  int32_t *d_rbc_mesh = nullptr;
+  int32_t *d_rbc_mesh = nullptr, *d_rbc_box = nullptr;
   int64_t *d_rbc_first = nullptr, *d_rbc_voff = nullptr;
   double *d_av = nullptr, *d_centroid = nullptr;
   int64_t nvert = 0;
@@ -198,18 +210,14 @@ static float wrap_host(float x, float L) {
   return x;
 }
 
-extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn alloc,
-                           tdpd_free_fn free_fn, void *user, tdpd_sys **out) {
-  if (!p || !out) return TDPD_ERR_INVALID_ARG;
-  *out = nullptr;
-  if ((alloc == nullptr) != (free_fn == nullptr)) return TDPD_ERR_INVALID_ARG;
+// Checks of the parameters shared by every box.
+static int check_common(const tdpd_params *p) {
   if (p->n_types < 1 || p->n_types > TDPD_MAX_TYPES || p->n_species < 1 ||
       p->n_species > TDPD_MAX_SPECIES)
     return TDPD_ERR_INVALID_ARG;
   if (!(p->rc > 0.f) || !(p->rcc > 0.f) || !(p->dt > 0.f) || !(p->kT >= 0.f) ||
       !(p->s_exp >= 0.f) || !(p->sc_exp >= 0.f) || !(p->m_s >= 0.f) || !(p->rho >= 0.f))
     return TDPD_ERR_INVALID_ARG;
-  if (p->box_id >= (1u << 24)) return TDPD_ERR_INVALID_ARG;
   if (p->wall_axis < -1 || p->wall_axis > 2) return TDPD_ERR_INVALID_ARG;
   const int T = p->n_types;
   for (int i = 0; i < T; ++i)
@@ -226,15 +234,31 @@ extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn
         if (k1 != k2 || k1 < 0.f) return TDPD_ERR_INVALID_ARG;
       }
     }
+  return TDPD_OK;
+}
+
+// Geometry of one box; fails if it holds fewer than 3 cells of edge
+// > max(rc, rcc) per axis.
+static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
+  if (in.box_id >= (1u << 24)) return TDPD_ERR_INVALID_ARG;
+  if (in.shear_rate != 0.f) return TDPD_ERR_UNSUPPORTED;
   const float rmax = std::max(p->rc, p->rcc);
-  int nc[3];
   for (int a = 0; a < 3; ++a) {
-    if (!(p->box[a] > 0.f)) return TDPD_ERR_INVALID_ARG;
-    nc[a] = int(std::floor(double(p->box[a]) / (double(rmax) * (1.0 + 1e-4))));
-    if (nc[a] < 3) return TDPD_ERR_BOX_TOO_SMALL;
+    if (!(in.box[a] > 0.f)) return TDPD_ERR_INVALID_ARG;
+    b.L[a] = in.box[a];
+    b.nc[a] = int(std::floor(double(in.box[a]) / (double(rmax) * (1.0 + 1e-4))));
+    if (b.nc[a] < 3) return TDPD_ERR_BOX_TOO_SMALL;
   }
-  if (p->wall_axis >= 0 && !(p->wall_w > 0.f && 2.f * p->wall_w < p->box[p->wall_axis]))
+  if (p->wall_axis >= 0 && !(p->wall_w > 0.f && 2.f * p->wall_w < in.box[p->wall_axis]))
     return TDPD_ERR_INVALID_ARG;
+  b.ncell = int64_t(b.nc[0]) * b.nc[1] * b.nc[2];
+  b.seed = in.seed;
+  b.box_id = in.box_id;
+  return TDPD_OK;
+}
+
+static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void *hip_stream,
+                         tdpd_alloc_fn alloc, tdpd_free_fn free_fn, void *user, tdpd_sys **out) {
   tdpd_sys *s = new tdpd_sys();
   s->prm = *p;
   s->st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -242,18 +266,16 @@ extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn
   s->free_fn = free_fn;
   s->user = user;
   s->S = p->n_species;
-  PairConst &pc = s->pc;
-  for (int a = 0; a < 3; ++a) {
-    pc.L[a] = p->box[a];
-    pc.invL[a] = 1.f / p->box[a];
-    pc.halfL[a] = 0.5f * p->box[a];
-    pc.nc[a] = nc[a];
-    pc.inv_h[a] = float(nc[a]) / p->box[a];
-    pc.body_force[a] = p->body_force[a];
+  s->boxes = std::move(boxes);
+  s->ncell = 0;
+  for (auto &b : s->boxes) {
+    b.cell_base = s->ncell;
+    s->ncell += b.ncell;
   }
-  s->ncell = int64_t(nc[0]) * nc[1] * nc[2];
   s->key_bits = 1;
   while ((int64_t(1) << s->key_bits) < s->ncell) ++s->key_bits;
+  PairConst &pc = s->pc;
+  for (int a = 0; a < 3; ++a) pc.body_force[a] = p->body_force[a];
   pc.rc = p->rc;
   pc.rcc = p->rcc;
   pc.rc2 = p->rc * p->rc;
@@ -268,7 +290,7 @@ extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn
   pc.half_dt = 0.5f * p->dt;
   pc.isdt = float(1.0 / std::sqrt(double(p->dt)));
   pc.ms_rho = p->m_s * p->m_s * p->rho;
-  pc.n_types = T;
+  pc.n_types = p->n_types;
   pc.n_species = p->n_species;
   std::memcpy(pc.alpha, p->alpha, sizeof(pc.alpha));
   std::memcpy(pc.gamma, p->gamma, sizeof(pc.gamma));
@@ -276,26 +298,46 @@ extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn
   std::memcpy(pc.kappa, p->kappa, sizeof(pc.kappa));
   pc.wall_axis = p->wall_axis;
   pc.wall_w = p->wall_w;
-  pc.seed_lo = uint32_t(p->seed & 0xffffffffu);
-  pc.seed_hi = uint32_t(p->seed >> 32);
-  pc.ctr3 = p->box_id << 8;
   pc.terms = p->terms;
-  MembraneConst &mc = s->mc;
-  for (int a = 0; a < 3; ++a) {
-    mc.L[a] = pc.L[a];
-    mc.invL[a] = pc.invL[a];
-  }
-  mc.kT = p->kT;
-  mc.dt = p->dt;
-  mc.seed_lo = pc.seed_lo;
-  mc.seed_hi = pc.seed_hi;
-  mc.ctr3 = pc.ctr3;
-  mc.terms = p->terms;
+  pc.n_boxes = int(s->boxes.size());
+  s->mc.kT = p->kT;
+  s->mc.dt = p->dt;
+  s->mc.terms = p->terms;
   if (const char *e = std::getenv("TDPD_PAIR_KERNEL")) s->pair_kernel = std::atoi(e);
   if (const char *e = std::getenv("TDPD_BIN")) s->bin_mode = std::atoi(e);
   if (const char *e = std::getenv("TDPD_GRAPH")) s->use_graph = std::atoi(e) != 0;
   *out = s;
   return TDPD_OK;
+}
+
+extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn alloc,
+                           tdpd_free_fn free_fn, void *user, tdpd_sys **out) {
+  if (!p || !out) return TDPD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return TDPD_ERR_INVALID_ARG;
+  int rc = check_common(p);
+  if (rc) return rc;
+  tdpd_box in{};
+  for (int a = 0; a < 3; ++a) in.box[a] = p->box[a];
+  in.seed = p->seed;
+  in.box_id = p->box_id;
+  std::vector<HostBox> boxes(1);
+  if ((rc = make_box(p, in, boxes[0]))) return rc;
+  return create_common(p, std::move(boxes), hip_stream, alloc, free_fn, user, out);
+}
+
+extern "C" int tdpd_create_batch(const tdpd_params *p, int32_t n_boxes, const tdpd_box *in,
+                                 void *hip_stream, tdpd_alloc_fn alloc, tdpd_free_fn free_fn,
+                                 void *user, tdpd_sys **out) {
+  if (!p || !out || !in || n_boxes < 1 || n_boxes > kMaxBoxes) return TDPD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return TDPD_ERR_INVALID_ARG;
+  int rc = check_common(p);
+  if (rc) return rc;
+  std::vector<HostBox> boxes(n_boxes);
+  for (int b = 0; b < n_boxes; ++b)
+    if ((rc = make_box(p, in[b], boxes[b]))) return rc;
+  return create_common(p, std::move(boxes), hip_stream, alloc, free_fn, user, out);
 }
 
 extern "C" void tdpd_destroy(tdpd_sys *s) {
@@ -313,10 +355,15 @@ extern "C" const char *tdpd_last_error(const tdpd_sys *s) { return s ? s->err.c_
 extern "C" int64_t tdpd_num_particles(const tdpd_sys *s) { return s ? s->n : 0; }
 extern "C" int64_t tdpd_step_counter(const tdpd_sys *s) { return s ? s->step : 0; }
 
-extern "C" int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const float *vel,
-                              const float *conc, const uint32_t *flags) {
-  if (!s) return TDPD_ERR_INVALID_ARG;
-  if (n < 0 || n >= (int64_t(1) << 31) || (n > 0 && (!pos || !vel || !conc || !flags)))
+extern "C" int tdpd_set_state_boxes(tdpd_sys *s, const int64_t *box_count, const float *pos,
+                                    const float *vel, const float *conc, const uint32_t *flags) {
+  if (!s || !box_count) return TDPD_ERR_INVALID_ARG;
+  int64_t n = 0;
+  for (size_t b = 0; b < s->boxes.size(); ++b) {
+    if (box_count[b] < 0) return s->fail(TDPD_ERR_INVALID_ARG, "set_state: negative box count");
+    n += box_count[b];
+  }
+  if (n >= (int64_t(1) << 31) || (n > 0 && (!pos || !vel || !conc || !flags)))
     return s->fail(TDPD_ERR_INVALID_ARG, "set_state: bad size or null pointer");
   const int S = s->S;
   for (int64_t i = 0; i < n; ++i) {
@@ -337,26 +384,48 @@ extern "C" int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const fl
   s->meshes.clear();
   s->rbc_mesh.clear();
   s->rbc_first.clear();
+  s->rbc_box.clear();
   s->n = n;
   s->step = 0;
   s->mem_lds = 0;
   s->h_pos.assign(pos, pos + 3 * n);
-  for (int64_t i = 0; i < n; ++i)
-    for (int a = 0; a < 3; ++a) {
-      float x = s->h_pos[3 * i + a];
-      const float L = s->prm.box[a];
-      if (x < -L || x >= 2.f * L) x = x - L * std::floor(x / L);  // far outside: fold first
-      s->h_pos[3 * i + a] = wrap_host(x, L);
+  s->h_box.assign(n, 0);
+  int64_t g = 0;
+  for (size_t b = 0; b < s->boxes.size(); ++b) {
+    HostBox &B = s->boxes[b];
+    B.gid_base = g;
+    B.n = box_count[b];
+    for (int64_t i = g; i < g + B.n; ++i) {
+      s->h_box[i] = int32_t(b);
+      for (int a = 0; a < 3; ++a) {
+        float x = s->h_pos[3 * i + a];
+        const float L = B.L[a];
+        if (x < -L || x >= 2.f * L) x = x - L * std::floor(x / L);  // far outside: fold first
+        s->h_pos[3 * i + a] = wrap_host(x, L);
+      }
     }
+    g += B.n;
+  }
   s->h_vel.assign(vel, vel + 3 * n);
   s->h_conc.assign(conc, conc + int64_t(S) * n);
   s->h_flags.assign(flags, flags + n);
+  s->h_body.assign(n, -1);
   for (int64_t i = 0; i < n; ++i)
     if (s->h_flags[i] & TDPD_FLAG_FROZEN)
       for (int a = 0; a < 3; ++a) s->h_vel[3 * i + a] = 0.f;
   s->have_state = true;
   return TDPD_OK;
 }
+
+extern "C" int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const float *vel,
+                              const float *conc, const uint32_t *flags) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (s->boxes.size() != 1) return s->fail(TDPD_ERR_STATE, "set_state: a batch takes tdpd_set_state_boxes");
+  if (n < 0) return s->fail(TDPD_ERR_INVALID_ARG, "set_state: negative count");
+  return tdpd_set_state_boxes(s, &n, pos, vel, conc, flags);
+}
+
+extern "C" int32_t tdpd_num_boxes(const tdpd_sys *s) { return s ? int32_t(s->boxes.size()) : 0; }
 
 extern "C" int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref, int32_t ntri,
                              const int32_t *tri, const tdpd_mesh_params *mp, int32_t *mesh_id) {
@@ -490,9 +559,6 @@ extern "C" int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref, int32_t
     for (int q = 0; q < 3; ++q) r2 += (ref[3 * v + q] - cen[q]) * (ref[3 * v + q] - cen[q]);
     M.max_radius = std::max(M.max_radius, std::sqrt(r2));
   }
-  for (int a = 0; a < 3; ++a)
-    if (1.25 * M.max_radius + 1.0 > 0.5 * s->prm.box[a])
-      return s->fail(TDPD_ERR_UNSUPPORTED, "add_mesh: cell too large for the periodic box");
   if (membrane_lds_bytes(M.nv, int(M.bond_ab.size())) > 60 * 1024)
     return s->fail(TDPD_ERR_UNSUPPORTED, "add_mesh: mesh too large for one workgroup's LDS");
   s->meshes.push_back(std::move(M));
@@ -506,14 +572,22 @@ extern "C" int tdpd_add_rbc(tdpd_sys *s, int32_t mesh_id, int64_t first_gid, int
   if (mesh_id < 0 || mesh_id >= int(s->meshes.size())) return s->fail(TDPD_ERR_INVALID_ARG, "add_rbc: bad mesh id");
   const int nv = s->meshes[mesh_id].nv;
   if (first_gid < 0 || first_gid + nv > s->n) return s->fail(TDPD_ERR_INVALID_ARG, "add_rbc: gid range outside the state");
-  if (s->rbc_mesh.size() >= 65534) return s->fail(TDPD_ERR_UNSUPPORTED, "add_rbc: too many cells");
+  if (s->rbc_mesh.size() >= size_t(kMaxBodies)) return s->fail(TDPD_ERR_UNSUPPORTED, "add_rbc: too many cells");
+  const int32_t box = s->h_box[first_gid];
+  if (s->h_box[first_gid + nv - 1] != box)
+    return s->fail(TDPD_ERR_INVALID_ARG, "add_rbc: cell spans two boxes");
+  const double rad = s->meshes[mesh_id].max_radius;
+  for (int a = 0; a < 3; ++a)
+    if (1.25 * rad + 1.0 > 0.5 * s->boxes[box].L[a])
+      return s->fail(TDPD_ERR_UNSUPPORTED, "add_rbc: cell too large for its periodic box");
   for (int64_t g = first_gid; g < first_gid + nv; ++g)
-    if ((s->h_flags[g] >> 16) != 0 || (s->h_flags[g] & TDPD_FLAG_FROZEN))
+    if (s->h_body[g] >= 0 || (s->h_flags[g] & TDPD_FLAG_FROZEN))
       return s->fail(TDPD_ERR_INVALID_ARG, "add_rbc: particle already bound or frozen");
-  const uint32_t body = uint32_t(s->rbc_mesh.size()) + 1;
-  for (int64_t g = first_gid; g < first_gid + nv; ++g) s->h_flags[g] |= body << 16;
+  const int32_t body = int32_t(s->rbc_mesh.size());
+  for (int64_t g = first_gid; g < first_gid + nv; ++g) s->h_body[g] = body;
   s->rbc_mesh.push_back(mesh_id);
   s->rbc_first.push_back(first_gid);
+  s->rbc_box.push_back(box);
   if (rbc_id) *rbc_id = int32_t(s->rbc_mesh.size() - 1);
   return TDPD_OK;
 }
@@ -594,7 +668,8 @@ static int prepare(tdpd_sys *s) {
     }
     for (int sp = 0; sp < S; ++sp) planes[(6 + sp) * n + i] = s->h_conc[S * i + sp];
     ints[i] = uint32_t(i);
-    ints[n + i] = s->h_flags[i];
+    ints[n + i] = make_info(int(s->h_flags[i] & 0xffu), (s->h_flags[i] & TDPD_FLAG_FROZEN) != 0,
+                            s->h_box[i], s->h_body[i]);
   }
   if (n > 0) {
     HIPCHK(hipMemcpyAsync(s->A.x, planes.data(), sizeof(float) * planes.size(), hipMemcpyHostToDevice, s->st));
@@ -669,7 +744,7 @@ static int prepare(tdpd_sys *s) {
           if (par < 0) {
             u[3 * v + a] = x;
           } else {
-            const double L = s->prm.box[a];
+            const double L = s->boxes[s->rbc_box[r]].L[a];
             double d = x - s->h_pos[3 * (g0 + par) + a];
             d -= L * std::nearbyint(d / L);
             u[3 * v + a] = u[3 * par + a] + d;
@@ -680,7 +755,7 @@ static int prepare(tdpd_sys *s) {
         double c = 0;
         for (int v = 0; v < M.nv; ++v) c += u[3 * v + a];
         c /= M.nv;
-        const double L = s->prm.box[a];
+        const double L = s->boxes[s->rbc_box[r]].L[a];
         c -= L * std::floor(c / L);
         cen[3 * r + a] = c;
         for (int v = 0; v < M.nv; ++v)
@@ -690,6 +765,7 @@ static int prepare(tdpd_sys *s) {
     }
     s->nvert = s->rbc_voff[nrbc];
     if ((rc = upload(s, &s->d_meshes, md)) || (rc = upload(s, &s->d_rbc_mesh, s->rbc_mesh)) ||
+        (rc = upload(s, &s->d_rbc_box, s->rbc_box)) ||
         (rc = upload(s, &s->d_rbc_first, s->rbc_first)) || (rc = upload(s, &s->d_rbc_voff, s->rbc_voff)) ||
         (rc = upload(s, &s->d_centroid, cen)))
       return rc;
@@ -703,6 +779,27 @@ static int prepare(tdpd_sys *s) {
     }
     HIPCHK(hipMemsetAsync(s->d_av, 0, sizeof(double) * 2 * nrbc, s->st));
   }
+  // box table
+  {
+    std::vector<BoxDev> bd(s->boxes.size());
+    for (size_t b = 0; b < s->boxes.size(); ++b) {
+      const HostBox &H = s->boxes[b];
+      BoxDev &D = bd[b];
+      for (int a = 0; a < 3; ++a) {
+        D.L[a] = H.L[a];
+        D.invL[a] = 1.f / H.L[a];
+        D.inv_h[a] = float(H.nc[a]) / H.L[a];
+        D.nc[a] = H.nc[a];
+      }
+      D.cell_base = uint32_t(H.cell_base);
+      D.ncell = uint32_t(H.ncell);
+      D.gid_base = uint32_t(H.gid_base);
+      D.seed_lo = uint32_t(H.seed & 0xffffffffu);
+      D.seed_hi = uint32_t(H.seed >> 32);
+      D.ctr3 = H.box_id << 8;
+    }
+    if ((rc = upload(s, &s->d_boxes, bd))) return rc;
+  }
   HIPCHK(hipStreamSynchronize(s->st));  // host vectors may be released after this
   s->uploaded = true;
   return TDPD_OK;
@@ -714,7 +811,7 @@ static int prepare(tdpd_sys *s) {
 static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   const int64_t n = s->n;
   const bool tb = s->phase_begin(1, st);
-  launch_prekick(s->pc, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate,
+  launch_prekick(s->pc, s->d_boxes, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate,
                  s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, st);
   if (n == 0) {
     s->phase_end(1, tb, st);
@@ -737,7 +834,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
     (void)hipEventRecord(s->ev_fork, st);
     (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
     const bool tm = s->phase_begin(2, s->st2);
-    launch_membrane(s->mc, s->d_meshes, s->d_rbc_mesh, s->d_rbc_first, s->d_rbc_voff, nrbc,
+    launch_membrane(s->mc, s->d_boxes, s->d_meshes, s->d_rbc_mesh, s->d_rbc_box, s->d_rbc_first,
+                    s->d_rbc_voff, nrbc,
                     s->cur(), s->slot_of_gid, s->d_av, s->d_centroid, s->kdev, s->Fm, s->errw,
                     s->mem_lds, s->st2);
     s->phase_end(2, tm, s->st2);
@@ -748,10 +846,12 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   // one-thread-per-particle kernel; it also packs a slot into 26 bits
   const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
   if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26))
-    launch_pair_simple(s->pc, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F, s->Q,
+    launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
+                       s->Q,
                        s->nzero, s->errw, st);
   else
-    launch_pair_tiled(s->pc, s->cur(), s->cell_start, s->ncell, n, s->kdev, s->F, s->Q,
+    launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, n, s->kdev, s->F,
+                      s->Q,
                       s->nzero, s->errw, st);
   s->phase_end(0, tp, st);
   if (nrbc > 0) (void)hipStreamWaitEvent(st, s->ev_join, 0);
@@ -902,7 +1002,7 @@ extern "C" int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *
   int32_t *dout = dallocT<int32_t>(s, 2 * size_t(cap > 0 ? cap : 1));
   if (!dout) return s->fail(TDPD_ERR_OOM, "device allocation failed");
   HIPCHK(hipMemsetAsync(s->pair_count, 0, sizeof(unsigned long long), s->st));
-  launch_pair_emit(s->pc, s->cur(), s->keys_s, s->cell_start, s->n, which ? s->pc.rcc2 : s->pc.rc2,
+  launch_pair_emit(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, s->n, which ? s->pc.rcc2 : s->pc.rc2,
                    dout, cap, s->pair_count, s->st);
   unsigned long long cnt = 0;
   hipError_t e = hipMemcpyAsync(&cnt, s->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, s->st);

@@ -9,24 +9,40 @@
 
 namespace tdpd {
 
-constexpr uint32_t kFrozen = 1u << 8;
 constexpr int kMaxT = TDPD_MAX_TYPES;
 constexpr int kMaxS = TDPD_MAX_SPECIES;
 
-// info word of a particle: type (bits 0-7) | frozen (bit 8) | (body + 1) << 16
-__host__ __device__ inline int info_type(uint32_t w) { return int(w & 0xffu); }
+// Internal info word of a particle (the public flags word is converted at
+// upload): type bits 0-2 | frozen bit 3 | box bits 4-13 | (body + 1) bits 14-31.
+constexpr uint32_t kFrozen = 1u << 3;
+constexpr int kMaxBoxes = 1024;
+constexpr int kMaxBodies = (1 << 18) - 2;
+__host__ __device__ inline int info_type(uint32_t w) { return int(w & 7u); }
 __host__ __device__ inline bool info_frozen(uint32_t w) { return (w & kFrozen) != 0; }
-__host__ __device__ inline int info_body(uint32_t w) { return int(w >> 16) - 1; }
+__host__ __device__ inline int info_box(uint32_t w) { return int((w >> 4) & 1023u); }
+__host__ __device__ inline int info_body(uint32_t w) { return int(w >> 14) - 1; }
+__host__ __device__ inline uint32_t make_info(int type, bool frozen, int box, int body) {
+  return uint32_t(type) | (frozen ? kFrozen : 0u) | (uint32_t(box) << 4) | (uint32_t(body + 1) << 14);
+}
 
 // Error bits written by kernels (sticky until the host reads them).
 constexpr uint32_t kErrOverext = 1u;
 constexpr uint32_t kErrNonfinite = 2u;
 
-// Parameters of the pair kernel and integrator, passed by value.
+// One periodic box of a (possibly batched) system: geometry, its slice of
+// the global cell list and of the gid range, and its noise key and counter
+// word (the counter uses box-local gids, so a box behaves the same alone and
+// in a batch).
+struct BoxDev {
+  float L[3], invL[3], inv_h[3];
+  int nc[3];
+  uint32_t cell_base, ncell;
+  uint32_t gid_base;
+  uint32_t seed_lo, seed_hi, ctr3;  // ctr3 = box_id << 8
+};
+
+// Parameters shared by every box, passed by value.
 struct PairConst {
-  float L[3], invL[3], halfL[3];
-  int nc[3];          // cells per axis
-  float inv_h[3];     // cells per unit length
   float rc, rcc, rc2, rcc2, rmax2;
   float inv_rc, inv_rcc;
   float s_half;       // w_R = w^(s/2)
@@ -40,8 +56,8 @@ struct PairConst {
   float body_force[3];
   int wall_axis;
   float wall_w;
-  uint32_t seed_lo, seed_hi, ctr3;  // ctr3 = box_id << 8
   int terms;
+  int n_boxes;
 };
 
 // State planes of one particle ordering.
@@ -50,6 +66,17 @@ struct State {
   float *C;            // [S][N]
   uint32_t *gid, *info;
 };
+
+// Box owning global cell c (boxes hold ascending cell ranges).
+__device__ __forceinline__ int box_of_cell(const BoxDev *boxes, int nbox, uint32_t c) {
+  int lo = 0, hi = nbox - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boxes[mid].cell_base <= c) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 // ------------------------------------------------------------------ Philox
 // Philox-4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
@@ -99,10 +126,14 @@ __device__ __forceinline__ void gauss2(uint32_t w0, uint32_t w1, float &c, float
 }
 
 // ------------------------------------------------------------ predicate
-// FP32 displacement component x_j + s - x_i, rounded exactly as specified
-// (no contraction), s the periodic image shift.
+// FP32 displacement component of x_j seen from x_i at periodic image shift
+// s in {0, +L, -L} of x_j, rounded exactly as specified (no contraction).
+// Across the boundary the coordinate nearer 0 is lifted by L, so both
+// orientations of a pair round the same value and d_ji = -d_ij exactly.
 __device__ __forceinline__ float disp(float xj, float s, float xi) {
-  return __fsub_rn(__fadd_rn(xj, s), xi);
+  if (s > 0.f) return __fsub_rn(__fadd_rn(xj, s), xi);
+  if (s < 0.f) return __fsub_rn(xj, __fadd_rn(xi, -s));
+  return __fsub_rn(xj, xi);
 }
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {
   return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));

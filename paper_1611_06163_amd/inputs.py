@@ -64,6 +64,7 @@ class Config:
     body_force: tuple = (0.0, 0.0, 0.0)
     wall_axis: int = -1
     wall_w: float = 0.0
+    shear_rate: float = 0.0
     seed: int = 1
     box_id: int = 0
     steps: int = 100
@@ -360,3 +361,27 @@ def c5(seed=5, n_cells=1000):
 def ensemble_sizes(n_boxes=256, lo=2000, hi=60000, seed=4):
     rng = np.random.default_rng(seed)
     return np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), n_boxes))).astype(int)
+
+
+def ensemble(n_boxes=256, seed=4, lo=2000, hi=60000, rho=3.0, max_cells=4, shear_max=0.5):
+    """Batched-ensemble workload: n_boxes independent periodic cubic boxes of
+    log-uniform particle count in [lo, hi] at density rho, each with its own
+    seed (1000 + b), box id b, shear rate U[0, shear_max] and U{0..max_cells}
+    cells (none where the box is narrower than 12, at most 20 % of the box
+    volume).  One species.  Returns a list of Config, one per box."""
+    rng = np.random.default_rng(seed)
+    sizes = np.round(np.exp(rng.uniform(math.log(lo), math.log(hi), n_boxes))).astype(int)
+    shears = rng.uniform(0.0, shear_max, n_boxes)
+    ncells = rng.integers(0, max_cells + 1, n_boxes)
+    boxes = []
+    for b in range(n_boxes):
+        L = float((sizes[b] / rho) ** (1.0 / 3.0))
+        nc = int(ncells[b]) if L >= 12.0 else 0
+        nc = min(nc, int(0.2 * L ** 3 / 95.0))
+        cfg = _suspension(f"ensemble_{b}", (L, L, L), rho, nc, 1000 + b, n_species=1,
+                          permeability=(1.0,))
+        cfg.seed = 1000 + b
+        cfg.box_id = b
+        cfg.shear_rate = float(shears[b])
+        boxes.append(cfg)
+    return boxes

@@ -49,6 +49,11 @@ class tdpd_params(C.Structure):
     ]
 
 
+class tdpd_box(C.Structure):
+    _fields_ = [("box", C.c_float * 3), ("seed", C.c_uint64), ("box_id", C.c_uint32),
+                ("shear_rate", C.c_float)]
+
+
 class tdpd_mesh_params(C.Structure):
     _fields_ = [(f, C.c_float) for f in
                 ("p", "x0", "m_pow", "kb", "theta0", "kg", "kl", "kv", "gamma_t", "gamma_c")]
@@ -78,7 +83,11 @@ def lib():
         sig = {
             "tdpd_create": (C.c_int, [C.POINTER(tdpd_params), P, ALLOC_FN, FREE_FN, P,
                                       C.POINTER(P)]),
+            "tdpd_create_batch": (C.c_int, [C.POINTER(tdpd_params), I32, P, P, ALLOC_FN,
+                                            FREE_FN, P, C.POINTER(P)]),
             "tdpd_set_state": (C.c_int, [P, I64, P, P, P, P]),
+            "tdpd_set_state_boxes": (C.c_int, [P, P, P, P, P, P]),
+            "tdpd_num_boxes": (I32, [P]),
             "tdpd_add_mesh": (C.c_int, [P, I32, P, I32, P, C.POINTER(tdpd_mesh_params),
                                         C.POINTER(I32)]),
             "tdpd_add_rbc": (C.c_int, [P, I32, I64, C.POINTER(I32)]),
@@ -158,12 +167,18 @@ class _TorchAllocator:
 
 
 class System:
-    """One tDPD system on the GPU (a thin owner of a tdpd_sys handle)."""
+    """One tDPD system on the GPU (a thin owner of a tdpd_sys handle).
+
+    `cfg` is one inputs.Config (one periodic box) or a list of them (a
+    batched ensemble: one box per config, sharing the common parameters of
+    the first; particles concatenated box-major)."""
 
     def __init__(self, cfg, terms=TERMS_ALL, stream=None, torch_alloc=True):
         L = lib()
-        self.cfg = cfg
-        self.S = cfg.n_species
+        cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg]
+        self.cfgs = cfgs
+        self.cfg = cfgs[0]
+        self.S = self.cfg.n_species
         self._alloc = None
         alloc_cb, free_cb = ALLOC_FN(), FREE_FN()
         if torch_alloc:
@@ -172,31 +187,57 @@ class System:
         if stream is None and torch_alloc:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
-        self._p = params_from_config(cfg, terms)
+        self._p = params_from_config(self.cfg, terms)
         h = C.c_void_p()
-        rc = L.tdpd_create(C.byref(self._p), C.c_void_p(stream) if stream else None,
-                           alloc_cb, free_cb, None, C.byref(h))
+        strm = C.c_void_p(stream) if stream else None
+        batched = isinstance(cfg, (list, tuple))
+        if batched:
+            boxes = (tdpd_box * len(cfgs))()
+            for b, c in enumerate(cfgs):
+                for a in range(3):
+                    boxes[b].box[a] = c.box[a]
+                boxes[b].seed, boxes[b].box_id = c.seed, c.box_id
+                boxes[b].shear_rate = getattr(c, "shear_rate", 0.0)
+            rc = L.tdpd_create_batch(C.byref(self._p), len(cfgs), C.cast(boxes, C.c_void_p), strm,
+                                     alloc_cb, free_cb, None, C.byref(h))
+        else:
+            rc = L.tdpd_create(C.byref(self._p), strm, alloc_cb, free_cb, None, C.byref(h))
         if rc:
             raise TdpdError(rc, "tdpd_create rejected the parameters")
         self.h = h
-        self._check(L.tdpd_set_state(self.h, cfg.n, _ptr(np.ascontiguousarray(cfg.pos, np.float32)),
-                                     _ptr(np.ascontiguousarray(cfg.vel, np.float32)),
-                                     _ptr(np.ascontiguousarray(cfg.conc, np.float32)),
-                                     _ptr(np.ascontiguousarray(cfg.flags, np.uint32))))
-        if cfg.mesh_xyz is not None and len(cfg.rbc_first_gid):
-            mp = cfg.mesh_params
+        counts = np.array([c.n for c in cfgs], dtype=np.int64)
+        self.box_offset = np.concatenate([[0], np.cumsum(counts)])
+        cat = lambda f, dt: np.ascontiguousarray(
+            np.concatenate([getattr(c, f) for c in cfgs]) if cfgs else np.zeros(0), dt)
+        self._check(L.tdpd_set_state_boxes(self.h, _ptr(counts), _ptr(cat("pos", np.float32)),
+                                           _ptr(cat("vel", np.float32)),
+                                           _ptr(cat("conc", np.float32)),
+                                           _ptr(cat("flags", np.uint32))))
+        self.n = int(counts.sum())
+        self.rbc_first = []
+        mesh_cfg = next((c for c in cfgs if c.mesh_xyz is not None and len(c.rbc_first_gid)), None)
+        if mesh_cfg is not None:
+            mp = mesh_cfg.mesh_params
             m = tdpd_mesh_params(p=mp.p, x0=mp.x0, m_pow=mp.m_pow, kb=mp.kb,
                                  theta0=mp.theta0, kg=mp.kg, kl=mp.kl, kv=mp.kv,
                                  gamma_t=mp.gamma_t, gamma_c=mp.gamma_c)
-            ref = np.ascontiguousarray(cfg.mesh_xyz, np.float64)
-            tri = np.ascontiguousarray(cfg.mesh_tri, np.int32)
+            ref = np.ascontiguousarray(mesh_cfg.mesh_xyz, np.float64)
+            tri = np.ascontiguousarray(mesh_cfg.mesh_tri, np.int32)
             mid = C.c_int32()
             self._check(L.tdpd_add_mesh(self.h, ref.shape[0], _ptr(ref), tri.shape[0], _ptr(tri),
                                         C.byref(m), C.byref(mid)))
-            for g0 in cfg.rbc_first_gid:
-                rid = C.c_int32()
-                self._check(L.tdpd_add_rbc(self.h, mid.value, int(g0), C.byref(rid)))
-        self.n = cfg.n
+            for b, c in enumerate(cfgs):
+                if not len(c.rbc_first_gid):
+                    continue
+                if c.mesh_xyz is not mesh_cfg.mesh_xyz and not (
+                        np.array_equal(c.mesh_xyz, mesh_cfg.mesh_xyz)
+                        and np.array_equal(c.mesh_tri, mesh_cfg.mesh_tri)):
+                    raise ValueError("all boxes of a batch must share one cell mesh")
+                for g0 in c.rbc_first_gid:
+                    rid = C.c_int32()
+                    g = int(self.box_offset[b] + g0)
+                    self._check(L.tdpd_add_rbc(self.h, mid.value, g, C.byref(rid)))
+                    self.rbc_first.append(g)
 
     def _check(self, rc):
         if rc:
@@ -247,7 +288,7 @@ class System:
         return out[:cnt.value].copy()
 
     def diagnostics(self):
-        nrbc = len(self.cfg.rbc_first_gid) if self.cfg.mesh_xyz is not None else 0
+        nrbc = len(self.rbc_first)
         out = np.zeros(4 + self.S + 2 * nrbc)
         self._check(lib().tdpd_diagnostics(self.h, _ptr(out), out.size))
         return dict(P=out[:3], kT=out[3], C=out[4:4 + self.S],

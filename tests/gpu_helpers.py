@@ -27,21 +27,36 @@ def gpu_system(cfg, kernel=None, terms=tdpd.TERMS_ALL, env=None):
                 os.environ[k] = v
 
 
-def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL, du=2e-7):
+def _ulp32(x):
+    x = np.abs(np.asarray(x, dtype=np.float32))
+    return (np.nextafter(x, np.float32(np.inf)) - x).astype(np.float64)
+
+
+def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL):
     """Particles whose force cannot be resolved to `tol` in FP32.
 
     Near r_c the weights w_R = w^(s/2) and w_D = w^s (w = 1 - r/r_c) have
     derivatives (s/2) w^(s/2-1) and s w^(s-1) that amplify the FP32 rounding
-    of r (du in w, about two ulps) without bound.  For each force pair the
-    induced error is sigma |xi| w_R' du / sqrt(dt) + gamma |v_ij| w_D' du with
-    the pair's own noise draw xi (same generator and counter as the step); a
-    particle is excluded when the sum over its pairs exceeds half of its
-    tolerance tol * sum_j |F_ij| (ref = the oracle's evaluation)."""
+    of r without bound.  That rounding is bounded per pair from the specified
+    arithmetic: the shifted coordinate x_j + s and the difference are each
+    rounded to half an ulp (a whole ulp of the box length for a pair across
+    the periodic boundary), plus three ulps of r for d^2, rsqrt and r.  The
+    induced error is sigma |xi| w_R' dr / (r_c sqrt(dt)) + gamma |v_ij| w_D'
+    dr / r_c with the pair's own noise draw xi; a particle is excluded when
+    the sum over its pairs exceeds half of its tolerance tol * sum_j |F_ij|
+    (ref = the oracle's evaluation)."""
     p, _ = o.pairs(pos.astype(np.float32), 0)
-    d = pos[p[:, 1]].astype(np.float64) - pos[p[:, 0]]
+    xi_ = pos[p[:, 0]].astype(np.float64)
+    xj = pos[p[:, 1]].astype(np.float64)
+    d = xj - xi_
     L = np.asarray(cfg.box)
-    d -= L * np.round(d / L)
+    shift = -L * np.round(d / L)
+    d += shift
     r = np.linalg.norm(d, axis=1)
+    m = np.maximum(np.abs(xj + shift), np.abs(xi_))
+    # x_j + s is exact when s = 0; the difference rounds to half an ulp of d
+    dd = np.where(shift != 0.0, 0.5 * _ulp32(m), 0.0) + 0.5 * _ulp32(d)
+    dr = (np.abs(d) / r[:, None] * dd).sum(axis=1) + 3.0 * _ulp32(r)
     w = np.maximum(1.0 - r / cfg.rc, 1e-12)
     s = cfg.s_exp
     xi = np.abs(pair_normals_batch(cfg, k, p[:, 0], p[:, 1], 0)[:, 0])
@@ -49,7 +64,7 @@ def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL, du=2e-7):
     sig = float(np.max(cfg.sigma))
     gam = float(np.max(cfg.gamma))
     sens = (sig * xi * (0.5 * s) * w ** (0.5 * s - 1.0) / np.sqrt(cfg.dt)
-            + gam * vij * s * w ** (s - 1.0)) * du
+            + gam * vij * s * w ** (s - 1.0)) * dr / cfg.rc
     tot = np.zeros(pos.shape[0])
     np.add.at(tot, p[:, 0], sens)
     np.add.at(tot, p[:, 1], sens)

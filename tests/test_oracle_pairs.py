@@ -81,3 +81,24 @@ def test_hand_checked_cutoff_and_wrap():
     got = {tuple(x) for x in _sorted(a).tolist()}
     # (1,3): |(0.5, 0, 1-ulp)| > 1, absent; (0,4): 1.2 through the boundary
     assert got == {(0, 1), (0, 3), (5, 6)}
+
+
+def test_displacement_antisymmetric_across_boundaries():
+    """The FP32 displacement rule lifts the coordinate nearer 0 of a pair
+    across the periodic boundary, so both orientations round the same value:
+    d_ji = -d_ij and d2_ji = d2_ij bit for bit."""
+    rng = np.random.default_rng(5)
+    L = np.float32(17.3)
+    cfg = _tiny((float(L), float(L), float(L)), 2, 0)
+    o = Oracle(cfg)
+    n_wrapped = 0
+    for _ in range(4000):
+        a = (rng.random(3) * L).astype(np.float32)
+        b = (a + rng.normal(scale=1.0, size=3)).astype(np.float32)
+        b = np.where(b < 0, b + L, np.where(b >= L, b - L, b)).astype(np.float32)
+        b[b >= L] = 0
+        dab, qab = o.disp(a, b)
+        dba, qba = o.disp(b, a)
+        assert np.array_equal(dab, -dba) and qab == qba
+        n_wrapped += int(np.any(np.abs(b - a) > L / 2))
+    assert n_wrapped > 200
