@@ -13,23 +13,17 @@ pytestmark = pytest.mark.gpu
 
 
 def _boxes():
+    """Five ensemble boxes of 2500-9000 particles plus a 14^3 box with one
+    red cell, so that membrane work is batched too."""
     boxes = I.ensemble(n_boxes=5, seed=11, lo=2500, hi=9000, shear_max=0.0)
-    assert any(len(b.rbc_first_gid) for b in boxes) or True
-    return boxes
-
-
-def _with_cell(boxes):
-    """Guarantee at least one box with a red cell (a 14^3 box)."""
-    c = I.small_suspension(seed=21, box=(14.0, 14.0, 14.0), n_cells=1)
-    c.n_species = 1
-    c.conc = c.conc[:, :1].copy()
-    c.kappa = c.kappa[:1]
-    c.seed, c.box_id = 1099, len(boxes)
+    c = I._suspension("batch_cell", (14.0, 14.0, 14.0), 3.0, 1, 1099, n_species=1,
+                      permeability=(1.0,))
+    c.box_id = len(boxes)
     return boxes + [c]
 
 
 def test_batch_box_equals_solo_bitwise():
-    boxes = _with_cell(_boxes())
+    boxes = _boxes()
     bs = gpu_system(boxes)
     bs.step(10)
     pos, vel, conc = bs.get_state()
@@ -48,7 +42,7 @@ def test_batch_box_equals_solo_bitwise():
 
 
 def test_batch_forces_match_oracle_per_box():
-    boxes = _with_cell(_boxes())
+    boxes = _boxes()
     bs = gpu_system(boxes)
     bs.compute_forces(5)
     pos, vel, conc = bs.get_state()
