@@ -18,12 +18,43 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # VALU issue slots per unit of pair-kernel work (non-packed FP32; quarter-rate
-# transcendentals and 32-bit multiplies count 4).  Derivation in the design doc.
+# transcendentals and 32-bit multiplies count 4).  A candidate test is 3 sub,
+# 1 mul, 2 fma, 1 compare; a flux pair and species is rsqrt (4), r, weight
+# fma, max, square, C difference, two multiplies and the accumulate; a force
+# pair is rsqrt, e, weights incl. exp2/log2, e.v, three terms, the
+# accumulate, Philox-4x32-10 (10 rounds of two 32x32->64 products, xors
+# and key adds = 140) and Box-Muller (about 21).
 OPS_CANDIDATE = 7
 OPS_FLUX_PER_SPECIES = 12
 OPS_FORCE = 200
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol"
+
+# HBM bytes per launch of the pair kernel from two rocprofv3 counter runs
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the factors a 256 MiB copy gives;
+# profiles/pair_tiled_single_rbc_20cube_hbm.md).  Valid only for the kernel
+# sources they were taken with: reported when the hash still matches.
+PAIR_SOURCES = ("kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h", "launch.h")
+PAIR_TRAFFIC = {
+    "c2": {"sha256": "c578969bedbfc4bfe393e6c9e0a92551604d111b9efcac0c738c4f254c1c8db5", "read_bytes": 2.648e6, "write_bytes": 0.490e6},
+}
+
+
+def pair_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_1611_06163_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pair_traffic(name):
+    t = PAIR_TRAFFIC.get(name)
+    if t is None or t["sha256"] != pair_source_hash():
+        return None
+    return t["read_bytes"] + t["write_bytes"]
 
 
 def workload(name):
@@ -130,7 +161,7 @@ def main():
     achieved = ops / pair_avg_s / 1e12
     d = sysg.diagnostics()
     out = {
-        "metric": "tDPD particle-steps/s on 1 MI355X",
+        "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -147,7 +178,8 @@ def main():
                    "dt": cfg.dt, "pair_kernel": os.environ.get("TDPD_PAIR_KERNEL", "1")},
         "roofline": {"bound": "alu", "kernel": "pair (forces + fluxes)",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": pair_traffic(args.workload),
+                     "traffic_unit": "bytes per launch",
                      "avg_launch_us": pair_avg_s * 1e6, "launches": pair_n,
                      "ops_per_launch": ops,
                      "units_per_launch": {"candidate_tests": n_cand, "flux_pairs": n_flux,

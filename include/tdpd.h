@@ -46,7 +46,8 @@ typedef enum {
   TDPD_ERR_BOND_OVEREXTENDED = -6, /* a WLC bond reached its maximum length */
   TDPD_ERR_STATE = -7,         /* call out of order (e.g. step before set_state) */
   TDPD_ERR_UNSUPPORTED = -8,   /* valid request outside what the library handles */
-  TDPD_ERR_CAPACITY = -9       /* an output buffer was too small */
+  TDPD_ERR_CAPACITY = -9,      /* an output buffer was too small */
+  TDPD_ERR_IO = -10            /* a checkpoint file could not be read or written, or does not match */
 } tdpd_status;
 
 #define TDPD_MAX_TYPES 4
@@ -202,6 +203,22 @@ int tdpd_diagnostics(tdpd_sys *s, double *out, int64_t cap);
 #define TDPD_PHASE_KICK 8      /* second half kick */
 int tdpd_set_timing(tdpd_sys *s, int32_t mask);
 int tdpd_get_timing(tdpd_sys *s, int32_t phase, double *total_ms, int64_t *launches);
+
+/* Checkpoint and resume.  The paper's method is an explicit time
+   integration (Eqs. 1-2 and 7 advanced by velocity Verlet), so the whole
+   state of a run is the particle state in the library's internal (cell)
+   order, the last forces and rates, the step counter that keys the random
+   numbers, and the per-cell centroids of the volume sums (Eq. 18).
+   tdpd_save waits for the stream and writes these to `path` (binary,
+   little-endian, with a fingerprint of parameters, boxes, particle count,
+   meshes and cells).  tdpd_load reads such a file into a system built the
+   same way (same params, boxes, set_state sizes, meshes and cells; the
+   particle values given to set_state are replaced).  A run resumed from a
+   checkpoint continues bit for bit as the uninterrupted run.
+   Errors: TDPD_ERR_IO if the file cannot be opened, is truncated or its
+   fingerprint differs; TDPD_ERR_STATE before set_state. */
+int tdpd_save(tdpd_sys *s, const char *path);
+int tdpd_load(tdpd_sys *s, const char *path);
 
 int64_t tdpd_num_particles(const tdpd_sys *s);
 int32_t tdpd_num_boxes(const tdpd_sys *s);

@@ -19,8 +19,8 @@
  *     Eqs. (17)-(18), bending, Eq. (19);
  *   - time integration: velocity Verlet (the paper gives only the ODEs,
  *     Eqs. (1)-(2)).
- * Readings of points the paper leaves open are listed with the code that
- * takes them and collected in the design doc.
+ * Readings of points the paper leaves open are stated with the code that
+ * takes them.
  *
  * The only FP32 arithmetic is the pair predicate (which particles are within
  * a cutoff), evaluated exactly as specified so that pair sets can be compared

@@ -1073,3 +1073,140 @@ extern "C" int tdpd_get_timing(tdpd_sys *s, int32_t phase, double *total_ms, int
   s->ev_used[q] = 0;
   return TDPD_OK;
 }
+
+// ------------------------------------------------------------ checkpoints
+namespace {
+
+constexpr char kCkptMagic[8] = {'T', 'D', 'P', 'D', 'C', 'K', 'P', '1'};
+
+struct Fnv {
+  uint64_t h = 1469598103934665603ull;
+  void bytes(const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  }
+  template <class T>
+  void val(const T &v) { bytes(&v, sizeof(T)); }
+  template <class T>
+  void vec(const std::vector<T> &v) {
+    val(uint64_t(v.size()));
+    if (!v.empty()) bytes(v.data(), sizeof(T) * v.size());
+  }
+};
+
+// Fingerprint of everything a checkpoint must match: parameters field by
+// field (no struct padding), boxes, sizes, meshes and cells.
+uint64_t fingerprint(const tdpd_sys *s) {
+  Fnv f;
+  const tdpd_params &p = s->prm;
+  f.val(p.rc); f.val(p.rcc); f.val(p.dt); f.val(p.kT); f.val(p.rho); f.val(p.m_s);
+  f.val(p.s_exp); f.val(p.sc_exp); f.val(p.n_types); f.val(p.n_species);
+  f.bytes(p.alpha, sizeof(p.alpha)); f.bytes(p.gamma, sizeof(p.gamma));
+  f.bytes(p.sigma, sizeof(p.sigma)); f.bytes(p.kappa, sizeof(p.kappa));
+  f.bytes(p.body_force, sizeof(p.body_force)); f.val(p.wall_axis); f.val(p.wall_w);
+  f.val(p.terms);
+  f.val(s->n); f.val(s->S); f.val(uint64_t(s->boxes.size()));
+  for (const HostBox &b : s->boxes) {
+    f.bytes(b.L, sizeof(b.L)); f.val(b.n); f.val(b.seed); f.val(b.box_id);
+  }
+  for (const HostMesh &m : s->meshes) {
+    f.val(m.nv); f.val(m.ntri); f.vec(m.tri); f.vec(m.A0t);
+    const tdpd_mesh_params &q = m.mp;
+    f.val(q.p); f.val(q.x0); f.val(q.m_pow); f.val(q.kb); f.val(q.kg); f.val(q.kl);
+    f.val(q.kv); f.val(q.gamma_t); f.val(q.gamma_c); f.val(float(m.theta0));
+  }
+  f.vec(s->rbc_mesh); f.vec(s->rbc_first);
+  return f.h;
+}
+
+struct CkptHeader {
+  char magic[8];
+  uint64_t fingerprint;
+  int64_t n, step;
+  int32_t S, nrbc;
+  uint32_t kdev, forces_valid;
+};
+
+// The device regions of a checkpoint, in file order.
+std::vector<std::pair<void *, size_t>> ckpt_regions(tdpd_sys *s) {
+  const size_t n = size_t(s->n), S = size_t(s->S), nrbc = s->rbc_mesh.size();
+  State &c = s->cur();
+  std::vector<std::pair<void *, size_t>> r = {
+      {c.x, sizeof(float) * (6 + S) * n},   // x, y, z, vx, vy, vz, C planes (one block)
+      {c.gid, sizeof(uint32_t) * 2 * n},    // gid, info
+      {s->slot_of_gid, sizeof(uint32_t) * n},
+      {s->F, sizeof(float) * 3 * n},
+      {s->Q, sizeof(float) * S * n}};
+  if (nrbc) r.push_back({s->d_centroid, sizeof(double) * 3 * nrbc});
+  return r;
+}
+
+}  // namespace
+
+extern "C" int tdpd_save(tdpd_sys *s, const char *path) {
+  if (!s || !path) return TDPD_ERR_INVALID_ARG;
+  int rc = ensure_forces(s);
+  if (rc) return rc;
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.fingerprint = fingerprint(s);
+  h.n = s->n;
+  h.step = s->step;
+  h.S = s->S;
+  h.nrbc = int32_t(s->rbc_mesh.size());
+  h.kdev = s->kdev_val;
+  h.forces_valid = s->forces_valid ? 1u : 0u;
+  FILE *fp = std::fopen(path, "wb");
+  if (!fp) return s->fail(TDPD_ERR_IO, std::string("save: cannot open ") + path);
+  bool ok = std::fwrite(&h, sizeof(h), 1, fp) == 1;
+  std::vector<char> buf;
+  for (auto &reg : ckpt_regions(s)) {
+    if (!ok || reg.second == 0) continue;
+    buf.resize(reg.second);
+    if (hipMemcpy(buf.data(), reg.first, reg.second, hipMemcpyDeviceToHost) != hipSuccess) {
+      std::fclose(fp);
+      return s->fail(TDPD_ERR_HIP, "save: device copy failed");
+    }
+    ok = std::fwrite(buf.data(), 1, reg.second, fp) == reg.second;
+  }
+  ok = (std::fclose(fp) == 0) && ok;
+  if (!ok) return s->fail(TDPD_ERR_IO, std::string("save: write failed: ") + path);
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_load(tdpd_sys *s, const char *path) {
+  if (!s || !path) return TDPD_ERR_INVALID_ARG;
+  int rc = prepare(s);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s->st));
+  FILE *fp = std::fopen(path, "rb");
+  if (!fp) return s->fail(TDPD_ERR_IO, std::string("load: cannot open ") + path);
+  CkptHeader h{};
+  bool ok = std::fread(&h, sizeof(h), 1, fp) == 1 && std::memcmp(h.magic, kCkptMagic, 8) == 0;
+  if (!ok || h.fingerprint != fingerprint(s) || h.n != s->n || h.S != s->S ||
+      h.nrbc != int32_t(s->rbc_mesh.size()) || h.step < 0 || h.step > 0xffffffffLL) {
+    std::fclose(fp);
+    return s->fail(TDPD_ERR_IO, "load: not a checkpoint of this system");
+  }
+  // read everything before touching the device, so a short file changes nothing
+  s->cur_A = true;
+  auto regs = ckpt_regions(s);
+  std::vector<std::vector<char>> data(regs.size());
+  for (size_t i = 0; i < regs.size() && ok; ++i) {
+    data[i].resize(regs[i].second);
+    ok = std::fread(data[i].data(), 1, regs[i].second, fp) == regs[i].second;
+  }
+  std::fclose(fp);
+  if (!ok) return s->fail(TDPD_ERR_IO, "load: truncated checkpoint");
+  for (size_t i = 0; i < regs.size(); ++i)
+    if (regs[i].second)
+      HIPCHK(hipMemcpy(regs[i].first, data[i].data(), regs[i].second, hipMemcpyHostToDevice));
+  launch_set_counter(s->kdev, h.kdev, s->st);
+  HIPCHK(hipStreamSynchronize(s->st));
+  s->kdev_val = h.kdev;
+  s->step = h.step;
+  s->forces_valid = h.forces_valid != 0;
+  // captured graphs hold the A/B parity they were recorded at; A is current now
+  s->destroy_graphs();
+  return check_launch(s);
+}

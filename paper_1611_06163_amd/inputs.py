@@ -8,8 +8,9 @@ and the CPU oracle can both be fed from it without sharing any of the
 computation they are compared on.
 
 Workload shapes follow the paper's benchmark systems (pure tDPD fluid and RBC
-suspensions with 500 membrane particles per cell, Section 5, Table 1) and the
-synthetic configurations listed in the design doc (C1..C5).
+suspensions with 500 membrane particles per cell, Section 5, Table 1): a plain
+fluid (c1), one cell in a periodic box (c2), a wall-bounded suspension (c3),
+batched ensembles of uneven boxes (ensemble) and a large suspension (c5).
 """
 from __future__ import annotations
 

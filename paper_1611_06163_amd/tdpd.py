@@ -26,7 +26,7 @@ FLAG_FROZEN = 1 << 8
 PHASE = dict(pair=1, bin=2, membrane=4, kick=8)
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BOX_TOO_SMALL", -3: "OOM", -4: "HIP",
           -5: "NONFINITE", -6: "BOND_OVEREXTENDED", -7: "STATE", -8: "UNSUPPORTED",
-          -9: "CAPACITY"}
+          -9: "CAPACITY", -10: "IO"}
 
 
 class TdpdError(RuntimeError):
@@ -100,6 +100,8 @@ def lib():
             "tdpd_diagnostics": (C.c_int, [P, P, I64]),
             "tdpd_set_timing": (C.c_int, [P, I32]),
             "tdpd_get_timing": (C.c_int, [P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
+            "tdpd_save": (C.c_int, [P, C.c_char_p]),
+            "tdpd_load": (C.c_int, [P, C.c_char_p]),
             "tdpd_num_particles": (I64, [P]),
             "tdpd_step_counter": (I64, [P]),
             "tdpd_coincident_pairs": (I64, [P]),
@@ -293,6 +295,12 @@ class System:
         self._check(lib().tdpd_diagnostics(self.h, _ptr(out), out.size))
         return dict(P=out[:3], kT=out[3], C=out[4:4 + self.S],
                     av=out[4 + self.S:].reshape(nrbc, 2))
+
+    def save(self, path):
+        self._check(lib().tdpd_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self._check(lib().tdpd_load(self.h, os.fsencode(path)))
 
     def set_timing(self, mask):
         self._check(lib().tdpd_set_timing(self.h, int(mask)))

@@ -38,9 +38,11 @@ def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL):
     Near r_c the weights w_R = w^(s/2) and w_D = w^s (w = 1 - r/r_c) have
     derivatives (s/2) w^(s/2-1) and s w^(s-1) that amplify the FP32 rounding
     of r without bound.  That rounding is bounded per pair from the specified
-    arithmetic: the shifted coordinate x_j + s and the difference are each
-    rounded to half an ulp (a whole ulp of the box length for a pair across
-    the periodic boundary), plus three ulps of r for d^2, rsqrt and r.  The
+    arithmetic: for a pair across the periodic boundary the coordinate
+    nearer 0 is lifted by +L, which rounds to half an ulp of the lifted value,
+    and the difference with the other coordinate is exact; otherwise the
+    difference rounds to half an ulp of d.  Three more ulps of r cover d^2,
+    rsqrt and r.  The
     induced error is sigma |xi| w_R' dr / (r_c sqrt(dt)) + gamma |v_ij| w_D'
     dr / r_c with the pair's own noise draw xi; a particle is excluded when
     the sum over its pairs exceeds half of its tolerance tol * sum_j |F_ij|
@@ -53,9 +55,12 @@ def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL):
     shift = -L * np.round(d / L)
     d += shift
     r = np.linalg.norm(d, axis=1)
-    m = np.maximum(np.abs(xj + shift), np.abs(xi_))
-    # x_j + s is exact when s = 0; the difference rounds to half an ulp of d
-    dd = np.where(shift != 0.0, 0.5 * _ulp32(m), 0.0) + 0.5 * _ulp32(d)
+    # across the boundary the coordinate nearer 0 is lifted by +L in FP32,
+    # rounding to half an ulp of the lifted value (>= L); the difference of
+    # the lifted coordinate and the other is then exact (Sterbenz), else the
+    # plain difference rounds to half an ulp of d
+    lifted = np.minimum(xi_, xj) + L
+    dd = np.where(shift != 0.0, 0.5 * _ulp32(lifted), 0.5 * _ulp32(d))
     dr = (np.abs(d) / r[:, None] * dd).sum(axis=1) + 3.0 * _ulp32(r)
     w = np.maximum(1.0 - r / cfg.rc, 1e-12)
     s = cfg.s_exp

@@ -237,3 +237,25 @@ def test_full_size_sampled_c3():
         rep = compare_forces(F, Q, ref, exclude=excl, which=which, label=f"c3-full/k{kernel}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         sysg.close()
+
+
+def test_checkpoint_resume_bitwise(tmp_path):
+    """A run resumed from a checkpoint equals the uninterrupted run bit for
+    bit (same cell order, step counter and centroids)."""
+    cfg = I.small_suspension(seed=31, box=(14.0, 14.0, 14.0), n_cells=1)
+    a = gpu_system(cfg)
+    a.step(7)
+    path = str(tmp_path / "ck.bin")
+    a.save(path)
+    a.step(8)
+    ref = a.get_state() + a.get_forces()
+    b = gpu_system(cfg)
+    b.load(path)
+    assert b.step_counter == 7
+    b.step(8)
+    got = b.get_state() + b.get_forces()
+    for name, x, y in zip(("pos", "vel", "conc", "F", "Q"), got, ref):
+        assert np.array_equal(x, y), name
+    # a checkpoint of another system is refused
+    with pytest.raises(tdpd.TdpdError):
+        gpu_system(I.c1()).load(path)
