@@ -139,6 +139,11 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
 }
 
 // ------------------------------------------------------------- integrator
+// First half kick, drift, wall reflection, wrap and cell key of every
+// particle.  In counting mode the value is the particle's unordered rank in
+// its cell: lanes of a wave holding the same key in a run (slots are in the
+// previous step's cell order, so most runs are whole cells) take one atomic
+// for the run, and each lane adds its offset in the run.
 __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__restrict__ boxes,
                                                  State s, const float *__restrict__ F,
                                                  const float *__restrict__ Q, int64_t n,
@@ -148,53 +153,72 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
                                                  uint32_t *__restrict__ kdev) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (integrate && kdev && i == 0) *kdev += 1u;  // step counter read by later kernels
-  if (i >= n) return;
-  const uint32_t info = s.info[i];
-  const BoxDev &B = boxes[info_box(info)];
-  float x = s.x[i], y = s.y[i], z = s.z[i];
-  if (integrate && !info_frozen(info)) {
-    const float h = pc.half_dt;
-    float vx = s.vx[i] + h * F[3 * i];
-    float vy = s.vy[i] + h * F[3 * i + 1];
-    float vz = s.vz[i] + h * F[3 * i + 2];
-    for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
-    x += pc.dt * vx;
-    y += pc.dt * vy;
-    z += pc.dt * vz;
-    if (pc.wall_axis >= 0) {
-      float *c = pc.wall_axis == 0 ? &x : (pc.wall_axis == 1 ? &y : &z);
-      const float L = B.L[pc.wall_axis], w = pc.wall_w;
-      bool hit = false;
-      if (*c < w) {
-        *c = 2.f * w - *c;
-        hit = true;
-      } else if (*c > L - w) {
-        *c = 2.f * (L - w) - *c;
-        hit = true;
+  const bool active = i < n;
+  uint32_t key = 0xffffffffu;
+  if (active) {
+    const uint32_t info = s.info[i];
+    const BoxDev &B = boxes[info_box(info)];
+    float x = s.x[i], y = s.y[i], z = s.z[i];
+    if (integrate && !info_frozen(info)) {
+      const float h = pc.half_dt;
+      float vx = s.vx[i] + h * F[3 * i];
+      float vy = s.vy[i] + h * F[3 * i + 1];
+      float vz = s.vz[i] + h * F[3 * i + 2];
+      for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+      x += pc.dt * vx;
+      y += pc.dt * vy;
+      z += pc.dt * vz;
+      if (pc.wall_axis >= 0) {
+        float *c = pc.wall_axis == 0 ? &x : (pc.wall_axis == 1 ? &y : &z);
+        const float L = B.L[pc.wall_axis], w = pc.wall_w;
+        bool hit = false;
+        if (*c < w) {
+          *c = 2.f * w - *c;
+          hit = true;
+        } else if (*c > L - w) {
+          *c = 2.f * (L - w) - *c;
+          hit = true;
+        }
+        if (hit) {
+          vx = -vx;
+          vy = -vy;
+          vz = -vz;
+        }
       }
-      if (hit) {
-        vx = -vx;
-        vy = -vy;
-        vz = -vz;
-      }
+      x = wrap_coord(x, B.L[0]);
+      y = wrap_coord(y, B.L[1]);
+      z = wrap_coord(z, B.L[2]);
+      s.x[i] = x;
+      s.y[i] = y;
+      s.z[i] = z;
+      s.vx[i] = vx;
+      s.vy[i] = vy;
+      s.vz[i] = vz;
     }
-    x = wrap_coord(x, B.L[0]);
-    y = wrap_coord(y, B.L[1]);
-    z = wrap_coord(z, B.L[2]);
-    s.x[i] = x;
-    s.y[i] = y;
-    s.z[i] = z;
-    s.vx[i] = vx;
-    s.vy[i] = vy;
-    s.vz[i] = vz;
+    const int cx = cell_coord(x, B.inv_h[0], B.nc[0]);
+    const int cy = cell_coord(y, B.inv_h[1], B.nc[1]);
+    const int cz = cell_coord(z, B.inv_h[2], B.nc[2]);
+    key = B.cell_base + uint32_t((cz * B.nc[1] + cy) * B.nc[0] + cx);
+    keys[i] = key;
   }
-  const int cx = cell_coord(x, B.inv_h[0], B.nc[0]);
-  const int cy = cell_coord(y, B.inv_h[1], B.nc[1]);
-  const int cz = cell_coord(z, B.inv_h[2], B.nc[2]);
-  const uint32_t key = B.cell_base + uint32_t((cz * B.nc[1] + cy) * B.nc[0] + cx);
-  keys[i] = key;
-  // counting binning: the value is this particle's (unordered) rank in its cell
-  vals[i] = cell_count ? atomicAdd(&cell_count[key], 1u) : uint32_t(i);
+  if (!cell_count) {
+    if (active) vals[i] = uint32_t(i);
+    return;
+  }
+  // runs of equal keys inside the wave (every lane takes part)
+  const int lane = int(threadIdx.x & 63u);
+  const uint32_t prev = uint32_t(__shfl_up(int(key), 1));
+  const bool start = lane == 0 || prev != key;
+  const uint64_t starts = __ballot(start);
+  uint32_t base = 0;
+  if (start && active) {
+    const uint64_t above = starts & ~((2ull << lane) - 1ull);
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    base = atomicAdd(&cell_count[key], uint32_t(next - lane));
+  }
+  const int leader = 63 - __clzll((long long)(starts & ((2ull << lane) - 1ull)));
+  const uint32_t b0 = uint32_t(__shfl(int(base), leader));
+  if (active) vals[i] = b0 + uint32_t(lane - leader);
 }
 
 void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
@@ -212,32 +236,84 @@ void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const flo
 // and k_rank_gather replaces that rank by the particle's rank in previous
 // order among its cell (a count over the cell), so the final order is the
 // same as a stable sort's and does not depend on atomic ordering.
-__global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restrict__ count,
-                                                             int64_t ncell,
-                                                             uint32_t *__restrict__ start) {
-  __shared__ uint32_t part[kScanThreads];
-  const int64_t chunk = (ncell + kScanThreads - 1) / kScanThreads;
-  const int64_t b = int64_t(threadIdx.x) * chunk;
-  const int64_t e = b + chunk < ncell ? b + chunk : ncell;
-  uint32_t sum = 0;
-  for (int64_t c = b; c < e; ++c) sum += count[c];
-  part[threadIdx.x] = sum;
+constexpr int kCellTile = 4 * kScanThreads;  // cells per scan tile
+
+// Inclusive scan of one value per thread over the block (1024 threads).
+__device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
   __syncthreads();
   for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    const uint32_t u = t >= off ? sh[t - off] : 0u;
     __syncthreads();
-    part[threadIdx.x] += v;
+    sh[t] += u;
     __syncthreads();
   }
-  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-  for (int64_t c = b; c < e; ++c) {
-    const uint32_t v = count[c];
-    start[c] = run;
-    count[c] = 0u;  // ready for the next step
-    run += v;
-  }
-  if (threadIdx.x == kScanThreads - 1) start[ncell] = part[kScanThreads - 1];
+  return sh[t];
 }
+
+// Sum of the cell counts of each tile of kCellTile cells.
+__global__ void __launch_bounds__(kScanThreads) k_count_tiles(const uint32_t *__restrict__ count,
+                                                              int64_t ncell,
+                                                              uint32_t *__restrict__ tile_sum) {
+  __shared__ uint32_t sh[kScanThreads];
+  const int64_t c0 = int64_t(blockIdx.x) * kCellTile;
+  uint32_t v = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t c = c0 + q * kScanThreads + threadIdx.x;
+    if (c < ncell) v += count[c];
+  }
+  const uint32_t tot = block_scan_incl(v, sh);
+  if (threadIdx.x == kScanThreads - 1) tile_sum[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the cell counts into cell_start (tile prefix from the
+// tile sums, then a block scan of the tile); clears the counts.
+__global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restrict__ count,
+                                                             int64_t ncell,
+                                                             const uint32_t *__restrict__ tile_sum,
+                                                             uint32_t *__restrict__ start) {
+  __shared__ uint32_t sh[kScanThreads];
+  __shared__ uint32_t tile[kCellTile];
+  const int t = threadIdx.x;
+  const int64_t c0 = int64_t(blockIdx.x) * kCellTile;
+  // prefix of the earlier tiles
+  uint32_t pre = 0;
+  for (int64_t q = t; q < int64_t(blockIdx.x); q += kScanThreads) pre += tile_sum[q];
+  (void)block_scan_incl(pre, sh);
+  const uint32_t base = sh[kScanThreads - 1];
+  __syncthreads();
+  // coalesced load of the tile, then four consecutive cells per thread
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t c = c0 + q * kScanThreads + t;
+    uint32_t v = 0;
+    if (c < ncell) {
+      v = count[c];
+      count[c] = 0u;  // ready for the next step
+    }
+    tile[q * kScanThreads + t] = v;
+  }
+  __syncthreads();
+  const uint32_t a0 = tile[4 * t], a1 = tile[4 * t + 1], a2 = tile[4 * t + 2], a3 = tile[4 * t + 3];
+  const uint32_t incl = block_scan_incl(a0 + a1 + a2 + a3, sh);
+  const uint32_t ex = base + incl - (a0 + a1 + a2 + a3);
+  __syncthreads();
+  tile[4 * t] = ex;
+  tile[4 * t + 1] = ex + a0;
+  tile[4 * t + 2] = ex + a0 + a1;
+  tile[4 * t + 3] = ex + a0 + a1 + a2;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t c = c0 + q * kScanThreads + t;
+    if (c < ncell) start[c] = tile[q * kScanThreads + t];
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == kScanThreads - 1) start[ncell] = ex + a0 + a1 + a2 + a3;
+}
+
+int64_t count_scan_tiles(int64_t ncell) { return ncell > 0 ? (ncell + kCellTile - 1) / kCellTile : 1; }
 
 __global__ void __launch_bounds__(256) k_scatter_rank(const uint32_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ rank,
@@ -277,9 +353,13 @@ __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uin
 
 void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
                          uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
-                         int64_t n, int nspec, uint32_t *slot_of_gid, uint32_t *keys_sorted,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_count_scan, dim3(1), dim3(kScanThreads), 0, st, cell_count, ncell, cell_start);
+                         uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
+                         uint32_t *keys_sorted, hipStream_t st) {
+  const int64_t nt = count_scan_tiles(ncell);
+  hipLaunchKernelGGL(k_count_tiles, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count, ncell,
+                     tile_sum);
+  hipLaunchKernelGGL(k_count_scan, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count, ncell,
+                     tile_sum, cell_start);
   if (n <= 0) return;
   const dim3 g(unsigned((n + 255) / 256));
   hipLaunchKernelGGL(k_scatter_rank, g, dim3(256), 0, st, keys, rank, cell_start, n, tmp);

@@ -44,14 +44,23 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
-__device__ __forceinline__ float sel4(int t, float a0, float a1, float a2, float a3) {
-  return t == 0 ? a0 : (t == 1 ? a1 : (t == 2 ? a2 : a3));
-}
-
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// a value every lane holds equally, kept in a scalar register
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_readfirstlane(int(v)));
+}
+
+// ring slot of this lane among the set lanes of mask m, after `tail`
+__device__ __forceinline__ uint32_t lane_slot(uint64_t m, uint32_t tail) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), tail)) &
+         uint32_t(kRing - 1);
 }
 
 template <int NS>
@@ -61,6 +70,7 @@ struct TiledShared {
   uint32_t hgid[kHome], hinfo[kHome];
   float fa[kWaves][3][kHome];
   float qa[kWaves][NS][kHome];
+  float kap[NS][kMaxT * kMaxT];
   int seg_start[27];
   int seg_pref[28];
   float seg_sh[27][3];
@@ -164,7 +174,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
   const int nchunk = (ncand + 63) / 64;
   const int my_chunks = nchunk > w ? (nchunk - w + kWaves - 1) / kWaves : 0;
   const int h0 = int(cell_start[cell]), h1 = int(cell_start[cell + 1]);
-  uint32_t zero = 0;  // coincident pairs seen by this lane
+  uint32_t zero = 0;  // coincident (home, candidate) tests of this wave (wave-uniform)
+  if (tid < NS * kMaxT * kMaxT) {
+    const int sp = tid / (kMaxT * kMaxT), tt = tid % (kMaxT * kMaxT);
+    sh.kap[sp][tt] = (sp < S && tt < T * T) ? pc.kappa[sp * T * T + tt] : 0.f;
+  }
 
   for (int hb = h0; hb < h1; hb += kHome) {
     const int nh = min(kHome, h1 - hb);
@@ -186,28 +200,29 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
     for (int sp = 0; sp < NS; ++sp) sh.qa[w][sp][lane] = 0.f;
     __syncthreads();
     uint32_t head = 0, tail = 0;  // this wave's ring cursors (wave-uniform)
+    const float Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
+    const bool fick = (pc.terms & TDPD_TERM_FLUX_FICK) != 0;
 
     for (int cb = 0; cb < my_chunks; cb += kChunks) {
       // candidate coordinates, lifted by +L where the candidate sits across
-      // the low boundary; lift[kk] bit a says the home coordinate is lifted
-      // instead (candidate across the high boundary)
+      // the high boundary; lift[kk] bit a says the home coordinate is lifted
+      // instead (candidate across the low boundary).  Empty lanes hold NaN,
+      // which fails every distance test.
       float cxs[kChunks], cys[kChunks], czs[kChunks], cc[kChunks][NS];
       uint32_t cj[kChunks], lift[kChunks];
       int ct[kChunks], cbody[kChunks];
-      bool cv[kChunks];
 #pragma unroll
       for (int kk = 0; kk < kChunks; ++kk) {
         const int chunk = w + kWaves * (cb + kk);
         const int t = chunk * 64 + lane;
-        cv[kk] = (cb + kk) < my_chunks && t < ncand;
-        cxs[kk] = cys[kk] = czs[kk] = 0.f;
+        cxs[kk] = cys[kk] = czs[kk] = __builtin_nanf("");
         cj[kk] = 0;
         lift[kk] = 0;
         ct[kk] = 0;
         cbody[kk] = -2;
 #pragma unroll
         for (int sp = 0; sp < NS; ++sp) cc[kk][sp] = 0.f;
-        if (cv[kk]) {
+        if ((cb + kk) < my_chunks && t < ncand) {
           int lo = 0, hi = 26;  // largest segment whose prefix is <= t
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -232,20 +247,19 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
 
       for (int i = 0; i < nh; ++i) {
         const uint32_t infoi = sh.hinfo[i];
-        if (info_frozen(infoi)) continue;
+        if (info_frozen(infoi)) continue;  // frozen particles get F = Q = 0
         const float xi = sh.hx[i], yi = sh.hy[i], zi = sh.hz[i];
-        const float xil = __fadd_rn(xi, B.L[0]), yil = __fadd_rn(yi, B.L[1]),
-                    zil = __fadd_rn(zi, B.L[2]);
-        const int ti = info_type(infoi), bi = info_body(infoi);
-        const uint32_t self = uint32_t(hb + i);
-        float qp[NS], ci[NS], kr[NS][kMaxT];
+        const float xil = __fadd_rn(xi, Lx), yil = __fadd_rn(yi, Ly), zil = __fadd_rn(zi, Lz);
+        // pair forces skip partners of the home's own cell body; body ids
+        // are >= -2 (-1 none, -2 empty lane), so -3 matches nothing
+        const int bq = info_body(infoi) >= 0 ? info_body(infoi) : -3;
+        const int trow = info_type(infoi) * T;
+        const uint32_t hbits = uint32_t(i) << kJBits;
+        float qp[NS], ci[NS];
 #pragma unroll
         for (int sp = 0; sp < NS; ++sp) {
           qp[sp] = 0.f;
           ci[sp] = sh.hc[sp][i];
-#pragma unroll
-          for (int tj = 0; tj < kMaxT; ++tj)
-            kr[sp][tj] = (sp < S && tj < T) ? pc.kappa[(sp * T + ti) * T + tj] : 0.f;
         }
 #pragma unroll
         for (int kk = 0; kk < kChunks; ++kk) {
@@ -254,36 +268,39 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
           const float dy = __fsub_rn(cys[kk], (lift[kk] & 2u) ? yil : yi);
           const float dz = __fsub_rn(czs[kk], (lift[kk] & 4u) ? zil : zi);
           const float d2 = dist2(dx, dy, dz);
-          const bool live = cv[kk] && d2 > 0.f;
-          zero += (cv[kk] && d2 == 0.f && cj[kk] != self) ? 1u : 0u;
-          if ((pc.terms & TDPD_TERM_FLUX_FICK) && live && d2 < pc.rcc2) {
-            const float wdc = flux_weight(pc, d2);
-#pragma unroll
-            for (int sp = 0; sp < NS; ++sp)
-              qp[sp] -= sel4(ct[kk], kr[sp][0], kr[sp][1], kr[sp][2], kr[sp][3]) * wdc *
-                        (ci[sp] - cc[kk][sp]);
+          if (ballot(d2 == 0.f)) {  // the home itself, or a coincident particle
+            const uint32_t self = uint32_t(hb + i);
+            zero += uint32_t(__popcll(ballot((d2 == 0.f) & (cj[kk] != self))));
           }
-          const bool hitf = live && d2 < pc.rc2 && !(bi >= 0 && bi == cbody[kk]);
-          const uint64_t fm = __ballot(hitf);
+          if (fick && ((d2 > 0.f) & (d2 < pc.rcc2))) {
+            const float wdc = flux_weight(pc, d2);
+            const int tt = trow + ct[kk];
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) qp[sp] -= sh.kap[sp][tt] * wdc * (ci[sp] - cc[kk][sp]);
+          }
+          const bool hitf = (d2 > 0.f) & (d2 < pc.rc2) & (cbody[kk] != bq);
+          const uint64_t fm = ballot(hitf);
           if (fm) {
             if (hitf) {
-              const uint32_t e = (tail + uint32_t(__popcll(fm & __lanemask_lt()))) & (kRing - 1);
+              const uint32_t e = lane_slot(fm, tail);
               sh.rd[w][0][e] = dx;
               sh.rd[w][1][e] = dy;
               sh.rd[w][2][e] = dz;
-              sh.rij[w][e] = (uint32_t(i) << kJBits) | cj[kk];
+              sh.rij[w][e] = hbits | cj[kk];
             }
-            tail += uint32_t(__popcll(fm));
+            tail = uniform(tail + uint32_t(__popcll(fm)));
             if (tail - head >= 64) {
               flush_ring<NS>(pc, B, s, sh, w, head, 64, k);
-              head += 64;
+              head = uniform(head + 64u);
             }
           }
         }
+        if (fick) {
 #pragma unroll
-        for (int sp = 0; sp < NS; ++sp) {
-          const float t = wave_sum(qp[sp]);
-          if (lane == 0) sh.qa[w][sp][i] += t;
+          for (int sp = 0; sp < NS; ++sp) {
+            const float t = wave_sum(qp[sp]);
+            if (lane == 0) sh.qa[w][sp][i] += t;
+          }
         }
       }
       // end of the register block: empty the ring so that no flush window
@@ -291,7 +308,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
       while (tail != head) {
         const int m = int(min(tail - head, 64u));
         flush_ring<NS>(pc, B, s, sh, w, head, m, k);
-        head += uint32_t(m);
+        head = uniform(head + uint32_t(m));
       }
     }
     __syncthreads();
@@ -328,7 +345,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
     }
     __syncthreads();
   }
-  if (zero) atomicAdd(nzero, (unsigned long long)zero);
+  if (zero && lane == 0) atomicAdd(nzero, (unsigned long long)zero);
 }
 
 void launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,

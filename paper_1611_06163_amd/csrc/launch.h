@@ -24,13 +24,15 @@ void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const flo
                     const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
                     uint32_t *cell_count, uint32_t *kdev, hipStream_t st);
 // Counting binning after launch_prekick: scan of the cell counts into
-// cell_start (counts zeroed for the next step), scatter, and the rank fix-up
-// fused with the reorder of every state plane into dst (slot_of_gid and the
-// sorted keys updated).  Same permutation as the stable radix sort.
+// cell_start (counts zeroed for the next step; tile_sum holds
+// count_scan_tiles(ncell) words), scatter, and the rank fix-up fused with
+// the reorder of every state plane into dst (slot_of_gid and the sorted keys
+// updated).  Same permutation as the stable radix sort.
+int64_t count_scan_tiles(int64_t ncell);
 void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
                          uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
-                         int64_t n, int nspec, uint32_t *slot_of_gid, uint32_t *keys_sorted,
-                         hipStream_t st);
+                         uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
+                         uint32_t *keys_sorted, hipStream_t st);
 // cell_start[c] = first sorted index of cell c, cell_start[ncell] = n.
 void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
                         uint32_t *cell_start, hipStream_t st);

@@ -113,7 +113,7 @@ struct tdpd_sys {
   bool use_graph = true;
   uint32_t *kdev = nullptr;       // device step counter read by the kernels
   uint32_t kdev_val = 0;          // host mirror of *kdev
-  uint32_t *cell_count = nullptr, *bin_tmp = nullptr;
+  uint32_t *cell_count = nullptr, *bin_tmp = nullptr, *tile_sum = nullptr;
   float *Fm = nullptr;            // membrane forces by global vertex [nvert][3]
   hipStream_t st2 = nullptr, gst = nullptr;  // membrane stream, capture stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -648,7 +648,9 @@ static int prepare(tdpd_sys *s) {
   s->kdev = dallocT<uint32_t>(s, 1);
   s->cell_count = dallocT<uint32_t>(s, size_t(s->ncell));
   s->bin_tmp = dallocT<uint32_t>(s, n);
-  if (!s->kdev || !s->cell_count || !s->bin_tmp) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  s->tile_sum = dallocT<uint32_t>(s, size_t(count_scan_tiles(s->ncell)));
+  if (!s->kdev || !s->cell_count || !s->bin_tmp || !s->tile_sum)
+    return s->fail(TDPD_ERR_OOM, "device allocation failed");
   HIPCHK(hipMemsetAsync(s->kdev, 0, sizeof(uint32_t), s->st));
   HIPCHK(hipMemsetAsync(s->cell_count, 0, sizeof(uint32_t) * s->ncell, s->st));
   s->kdev_val = 0;
@@ -819,7 +821,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   }
   if (s->bin_mode == 0) {
     launch_bin_counting(s->cur(), s->nxt(), s->keys, s->vals, s->cell_count, s->ncell,
-                        s->cell_start, s->bin_tmp, n, s->S, s->slot_of_gid, s->keys_s, st);
+                        s->cell_start, s->bin_tmp, s->tile_sum, n, s->S, s->slot_of_gid, s->keys_s,
+                        st);
   } else {
     radix_sort(s->keys, s->vals, s->keys_tmp, s->vals_tmp, s->keys_s, s->perm, s->hist, n,
                s->key_bits, st);
