@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", type=int, default=None, help="pair kernel: 0 simple, 1 tiled")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shape of the pair kernel")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device with torch (a plain "
                          "copy of known size, to scale hardware byte counters)")
@@ -142,6 +144,8 @@ def main():
     cfg, desc = workload(args.workload)
     sysg = tdpd.System(cfg)
     sysg.compute_forces(0)
+    if not args.no_autotune:
+        sysg.autotune(reps=5)  # before the warm-up: untimed
     n_cand, n_flux, n_force = pair_work(sysg, cfg)
     sysg.step(args.warmup)
     sysg.sync()
@@ -175,7 +179,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "particles": cfg.n, "box": list(cfg.box),
                    "n_species": cfg.n_species, "rbcs": len(cfg.rbc_first_gid),
-                   "dt": cfg.dt, "pair_kernel": os.environ.get("TDPD_PAIR_KERNEL", "1")},
+                   "dt": cfg.dt, "pair_kernel": os.environ.get("TDPD_PAIR_KERNEL", "1"),
+                   "tile": list(sysg.tile)},
         "roofline": {"bound": "alu", "kernel": "pair (forces + fluxes)",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": pair_traffic(args.workload),

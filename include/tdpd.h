@@ -220,6 +220,25 @@ int tdpd_get_timing(tdpd_sys *s, int32_t phase, double *total_ms, int64_t *launc
 int tdpd_save(tdpd_sys *s, const char *path);
 int tdpd_load(tdpd_sys *s, const char *path);
 
+/* Tile shape of the cell-tiled pair kernel: wavefronts per workgroup (2 or
+   4), 64-candidate chunks per wavefront held in registers (1-4), workgroups
+   per cell (1-4).  Every shape gives a valid result; summation order, and
+   so the last bits, depend on the shape, and results are bit-for-bit
+   reproducible for a fixed shape.  tdpd_autotune times every built shape on
+   the system's current state (reps launches each, HIP events on the
+   system's stream), keeps the fastest and re-evaluates the forces with it.
+   With cache_path (may be NULL) it first looks for a line written for the
+   same device and workload signature (particle, species, box, cell and RBC
+   counts, term mask) and uses it without timing; otherwise it appends the
+   result.  *best_ms (may be NULL) gets the chosen shape's time, 0 when the
+   tiled kernel is not used (m_s > 0, or the simple kernel selected).
+   tdpd_set_tile returns TDPD_ERR_UNSUPPORTED for a shape that is not built.
+   These calls are not part of the paper's method: they choose among
+   equivalent evaluation orders of Eqs. (2)-(10). */
+int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps, double *best_ms);
+int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split);
+int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split);
+
 int64_t tdpd_num_particles(const tdpd_sys *s);
 int32_t tdpd_num_boxes(const tdpd_sys *s);
 int64_t tdpd_step_counter(const tdpd_sys *s);

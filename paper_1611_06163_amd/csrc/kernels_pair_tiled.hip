@@ -1,9 +1,12 @@
 // kernels_pair_tiled.hip -- cell-tiled tDPD pair kernel (Eqs. 2-10).
 //
-// One workgroup of kWaves wavefronts per home cell of the cell list.  The 27
-// neighbour cells form one candidate list cut into 64-candidate chunks; wave w
-// takes chunks w, w + kWaves, ... and holds up to kChunks of them in
-// registers (one lane per candidate).  Home particles are walked one at a
+// One workgroup of W wavefronts per home cell of the cell list (or per part
+// of its home particles when a cell is split over several workgroups).  The
+// 27 neighbour cells form one candidate list cut into 64-candidate chunks;
+// wave w takes chunks w, w + W, ... and holds up to KC of them in registers
+// (one lane per candidate).  (W, KC, split) is the tile shape; every shape
+// gives a valid result, and the fastest one for a workload is chosen by
+// timing them (tdpd_autotune).  Home particles are walked one at a
 // time as wave-uniform broadcasts.  For every (home, candidate) test:
 //   - the Fickian flux is accumulated in place per lane and summed across
 //     the wave with DPP adds (registers only) once per home particle and
@@ -18,8 +21,6 @@
 
 namespace tdpd {
 
-constexpr int kWaves = 4;      // wavefronts per home cell
-constexpr int kChunks = 2;     // 64-candidate chunks per wave held in registers
 constexpr int kRing = 128;     // per-wave force-pair ring (>= 63 + 64)
 constexpr int kHome = 64;      // home particles per pass
 constexpr uint32_t kJBits = 26;
@@ -63,28 +64,28 @@ __device__ __forceinline__ uint32_t lane_slot(uint64_t m, uint32_t tail) {
          uint32_t(kRing - 1);
 }
 
-template <int NS>
+template <int NS, int W>
 struct TiledShared {
   float hx[kHome], hy[kHome], hz[kHome], hvx[kHome], hvy[kHome], hvz[kHome];
   float hc[NS][kHome];
   uint32_t hgid[kHome], hinfo[kHome];
-  float fa[kWaves][3][kHome];
-  float qa[kWaves][NS][kHome];
+  float fa[W][3][kHome];
+  float qa[W][NS][kHome];
   float kap[NS][kMaxT * kMaxT];
   int seg_start[27];
   int seg_pref[28];
   float seg_sh[27][3];
-  float rd[kWaves][3][kRing];   // ring: displacement, overwritten by the force
-  uint32_t rij[kWaves][kRing];  // ring: home index << kJBits | candidate slot
+  float rd[W][3][kRing];   // ring: displacement, overwritten by the force
+  uint32_t rij[W][kRing];  // ring: home index << kJBits | candidate slot
 };
 
 // Evaluate ring entries [head, head+m) of wave w (m <= 64) and add them to
 // that wave's home accumulators; every home index forms one run in the
 // window (entries are appended in home order and the ring is flushed at the
 // end of each register block), so run leaders never collide.
-template <int NS>
+template <int NS, int W>
 __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B, const State &s,
-                                           TiledShared<NS> &sh, int w, uint32_t head, int m,
+                                           TiledShared<NS, W> &sh, int w, uint32_t head, int m,
                                            uint32_t k) {
   const int lane = threadIdx.x & 63;
   const uint32_t e = (head + lane) & (kRing - 1);
@@ -124,26 +125,28 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
   wave_sync();
 }
 
-template <int NS>
-__global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
+template <int NS, int W, int KC>
+__global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
                                                             const BoxDev *__restrict__ boxes,
                                                             State s,
                                                             const uint32_t *__restrict__ cell_start,
-                                                            int64_t ncell, int64_t per_xcd,
-                                                            int64_t n,
+                                                            int64_t ncell, int split,
+                                                            int64_t per_xcd, int64_t n,
                                                             const uint32_t *__restrict__ kdev,
                                                             float *__restrict__ F,
                                                             float *__restrict__ Q,
                                                             unsigned long long *nzero,
                                                             uint32_t *err) {
-  __shared__ TiledShared<NS> sh;
+  __shared__ TiledShared<NS, W> sh;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t k = *kdev;  // random-number step counter
   // consecutive workgroups go to different XCDs; give each XCD a contiguous
   // slab of cells so neighbouring cells share that XCD's L2
   const int64_t b = blockIdx.x;
-  const int64_t cell = (b & 7) * per_xcd + (b >> 3);
-  if (cell >= ncell) return;
+  const int64_t item = (b & 7) * per_xcd + (b >> 3);
+  if (item >= ncell * split) return;
+  const int64_t cell = item / split;
+  const int part = int(item - cell * split);
   const int S = pc.n_species, T = pc.n_types;
   const BoxDev &B = boxes[box_of_cell(boxes, pc.n_boxes, uint32_t(cell))];
   const int nx = B.nc[0], ny = B.nc[1], nz = B.nc[2];
@@ -172,8 +175,11 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
   __syncthreads();
   const int ncand = sh.seg_pref[27];
   const int nchunk = (ncand + 63) / 64;
-  const int my_chunks = nchunk > w ? (nchunk - w + kWaves - 1) / kWaves : 0;
-  const int h0 = int(cell_start[cell]), h1 = int(cell_start[cell + 1]);
+  const int my_chunks = nchunk > w ? (nchunk - w + W - 1) / W : 0;
+  // this workgroup's share of the cell's home particles
+  const int c0 = int(cell_start[cell]), cnt = int(cell_start[cell + 1]) - c0;
+  const int h0 = c0 + int(int64_t(cnt) * part / split);
+  const int h1 = c0 + int(int64_t(cnt) * (part + 1) / split);
   uint32_t zero = 0;  // coincident (home, candidate) tests of this wave (wave-uniform)
   if (tid < NS * kMaxT * kMaxT) {
     const int sp = tid / (kMaxT * kMaxT), tt = tid % (kMaxT * kMaxT);
@@ -203,17 +209,17 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
     const float Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
     const bool fick = (pc.terms & TDPD_TERM_FLUX_FICK) != 0;
 
-    for (int cb = 0; cb < my_chunks; cb += kChunks) {
+    for (int cb = 0; cb < my_chunks; cb += KC) {
       // candidate coordinates, lifted by +L where the candidate sits across
       // the high boundary; lift[kk] bit a says the home coordinate is lifted
       // instead (candidate across the low boundary).  Empty lanes hold NaN,
       // which fails every distance test.
-      float cxs[kChunks], cys[kChunks], czs[kChunks], cc[kChunks][NS];
-      uint32_t cj[kChunks], lift[kChunks];
-      int ct[kChunks], cbody[kChunks];
+      float cxs[KC], cys[KC], czs[KC], cc[KC][NS];
+      uint32_t cj[KC], lift[KC];
+      int ct[KC], cbody[KC];
 #pragma unroll
-      for (int kk = 0; kk < kChunks; ++kk) {
-        const int chunk = w + kWaves * (cb + kk);
+      for (int kk = 0; kk < KC; ++kk) {
+        const int chunk = w + W * (cb + kk);
         const int t = chunk * 64 + lane;
         cxs[kk] = cys[kk] = czs[kk] = __builtin_nanf("");
         cj[kk] = 0;
@@ -262,7 +268,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
           ci[sp] = sh.hc[sp][i];
         }
 #pragma unroll
-        for (int kk = 0; kk < kChunks; ++kk) {
+        for (int kk = 0; kk < KC; ++kk) {
           if (cb + kk >= my_chunks) break;  // wave-uniform
           const float dx = __fsub_rn(cxs[kk], (lift[kk] & 1u) ? xil : xi);
           const float dy = __fsub_rn(cys[kk], (lift[kk] & 2u) ? yil : yi);
@@ -290,7 +296,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
             }
             tail = uniform(tail + uint32_t(__popcll(fm)));
             if (tail - head >= 64) {
-              flush_ring<NS>(pc, B, s, sh, w, head, 64, k);
+              flush_ring<NS, W>(pc, B, s, sh, w, head, 64, k);
               head = uniform(head + 64u);
             }
           }
@@ -307,7 +313,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
       // ever mixes entries of two blocks (which would repeat home indices)
       while (tail != head) {
         const int m = int(min(tail - head, 64u));
-        flush_ring<NS>(pc, B, s, sh, w, head, m, k);
+        flush_ring<NS, W>(pc, B, s, sh, w, head, m, k);
         head = uniform(head + uint32_t(m));
       }
     }
@@ -318,7 +324,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
       const bool frozen = info_frozen(sh.hinfo[tid]);
       if (!frozen) {
 #pragma unroll
-        for (int v = 0; v < kWaves; ++v) {
+        for (int v = 0; v < W; ++v) {
           fx += sh.fa[v][0][tid];
           fy += sh.fa[v][1][tid];
           fz += sh.fa[v][2][tid];
@@ -339,7 +345,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
         float q = 0.f;
         if (!frozen)
 #pragma unroll
-          for (int v = 0; v < kWaves; ++v) q += sh.qa[v][sp][tid];
+          for (int v = 0; v < W; ++v) q += sh.qa[v][sp][tid];
         Q[S * p + sp] = q;
       }
     }
@@ -348,25 +354,54 @@ __global__ void __launch_bounds__(64 * kWaves) k_pair_tiled(PairConst pc,
   if (zero && lane == 0) atomicAdd(nzero, (unsigned long long)zero);
 }
 
-void launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
+template <int NS, int W, int KC>
+static void launch_shape(const PairConst &pc, const BoxDev *boxes, State s,
+                         const uint32_t *cell_start, int64_t ncell, int split, int64_t n,
+                         const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
+                         uint32_t *err, hipStream_t st) {
+  const int64_t per_xcd = (ncell * split + 7) / 8;
+  hipLaunchKernelGGL((k_pair_tiled<NS, W, KC>), dim3(unsigned(per_xcd * 8)), dim3(64 * W), 0, st, pc,
+                     boxes, s, cell_start, ncell, split, per_xcd, n, kdev, F, Q, nzero, err);
+}
+
+template <int NS>
+static bool launch_ns(const PairConst &pc, const BoxDev *boxes, State s, const uint32_t *cell_start,
+                      int64_t ncell, int64_t n, const uint32_t *kdev, float *F, float *Q,
+                      unsigned long long *nzero, uint32_t *err, const PairTile &t, hipStream_t st) {
+#define TDPD_SHAPE(W, KC)                                                                    \
+  if (t.waves == W && t.chunks == KC) {                                                      \
+    launch_shape<NS, W, KC>(pc, boxes, s, cell_start, ncell, t.split, n, kdev, F, Q, nzero, err, \
+                            st);                                                             \
+    return true;                                                                             \
+  }
+  TDPD_SHAPE(4, 2)
+  TDPD_SHAPE(4, 1)
+  TDPD_SHAPE(4, 3)
+  TDPD_SHAPE(2, 2)
+  TDPD_SHAPE(2, 3)
+  TDPD_SHAPE(2, 4)
+#undef TDPD_SHAPE
+  return false;
+}
+
+const PairTile kPairTiles[] = {{4, 2, 1}, {4, 1, 1}, {4, 3, 1}, {2, 2, 1}, {2, 3, 1}, {2, 4, 1},
+                               {4, 2, 2}, {4, 1, 2}, {2, 2, 2}, {2, 3, 2}, {2, 2, 4}, {4, 1, 4}};
+const int kNumPairTiles = int(sizeof(kPairTiles) / sizeof(kPairTiles[0]));
+
+bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
                        const uint32_t *cell_start, int64_t ncell,
                        int64_t n, const uint32_t *kdev, float *F, float *Q,
-                       unsigned long long *nzero, uint32_t *err, hipStream_t st) {
-  if (n <= 0 || ncell <= 0) return;
-  const int64_t per_xcd = (ncell + 7) / 8;
-  const dim3 grid(unsigned(per_xcd * 8)), block(64 * kWaves);
+                       unsigned long long *nzero, uint32_t *err, const PairTile &tile,
+                       hipStream_t st) {
+  if (n <= 0 || ncell <= 0) return true;
+  if (tile.split < 1 || tile.split > 8) return false;
   if (pc.n_species <= 1)
-    hipLaunchKernelGGL(k_pair_tiled<1>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
-                       kdev, F, Q, nzero, err);
-  else if (pc.n_species == 2)
-    hipLaunchKernelGGL(k_pair_tiled<2>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
-                       kdev, F, Q, nzero, err);
-  else if (pc.n_species <= 4)
-    hipLaunchKernelGGL(k_pair_tiled<4>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
-                       kdev, F, Q, nzero, err);
-  else
-    hipLaunchKernelGGL(k_pair_tiled<8>, grid, block, 0, st, pc, boxes, s, cell_start, ncell, per_xcd, n,
-                       kdev, F, Q, nzero, err);
+    return launch_ns<1>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
+  if (pc.n_species == 2)
+    return launch_ns<2>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
+  if (pc.n_species <= 4)
+    return launch_ns<4>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
+  return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
 }
 
 }  // namespace tdpd

@@ -109,6 +109,7 @@ struct tdpd_sys {
   int64_t nvert = 0;
   size_t mem_lds = 0;  // dynamic LDS of the membrane kernel
   int pair_kernel = 1;  // 0: one thread per particle, 1: cell-tiled
+  PairTile tile{4, 2, 1};  // shape of the cell-tiled kernel
   int bin_mode = 0;     // 0: counting (one-digit stable) sort, 1: LSD radix sort
   bool use_graph = true;
   uint32_t *kdev = nullptr;       // device step counter read by the kernels
@@ -257,6 +258,14 @@ static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
   return TDPD_OK;
 }
 
+static bool tile_built(const PairTile &t) {
+  for (int i = 0; i < kNumPairTiles; ++i)
+    if (kPairTiles[i].waves == t.waves && kPairTiles[i].chunks == t.chunks &&
+        kPairTiles[i].split == t.split)
+      return true;
+  return false;
+}
+
 static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void *hip_stream,
                          tdpd_alloc_fn alloc, tdpd_free_fn free_fn, void *user, tdpd_sys **out) {
   tdpd_sys *s = new tdpd_sys();
@@ -306,6 +315,10 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
   if (const char *e = std::getenv("TDPD_PAIR_KERNEL")) s->pair_kernel = std::atoi(e);
   if (const char *e = std::getenv("TDPD_BIN")) s->bin_mode = std::atoi(e);
   if (const char *e = std::getenv("TDPD_GRAPH")) s->use_graph = std::atoi(e) != 0;
+  if (const char *e = std::getenv("TDPD_TILE")) {  // "waves,chunks,split"
+    PairTile t{};
+    if (std::sscanf(e, "%d,%d,%d", &t.waves, &t.chunks, &t.split) == 3 && tile_built(t)) s->tile = t;
+  }
   *out = s;
   return TDPD_OK;
 }
@@ -853,9 +866,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
                        s->Q,
                        s->nzero, s->errw, st);
   else
-    launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, n, s->kdev, s->F,
-                      s->Q,
-                      s->nzero, s->errw, st);
+    (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, n, s->kdev,
+                            s->F, s->Q, s->nzero, s->errw, s->tile, st);
   s->phase_end(0, tp, st);
   if (nrbc > 0) (void)hipStreamWaitEvent(st, s->ev_join, 0);
   if (integrate || nrbc > 0) {
@@ -1212,4 +1224,120 @@ extern "C" int tdpd_load(tdpd_sys *s, const char *path) {
   // captured graphs hold the A/B parity they were recorded at; A is current now
   s->destroy_graphs();
   return check_launch(s);
+}
+
+// ------------------------------------------------------------- autotuning
+namespace {
+
+std::string tune_signature(const tdpd_sys *s) {
+  hipDeviceProp_t prop{};
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&prop, dev);
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s n=%lld S=%d boxes=%zu cells=%lld rbcs=%zu terms=%d",
+                prop.gcnArchName, (long long)s->n, s->S, s->boxes.size(), (long long)s->ncell,
+                s->rbc_mesh.size(), s->prm.terms);
+  for (char *c = buf; *c; ++c)
+    if (*c == ':' || *c == '\n') *c = '_';
+  return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &sig, PairTile *t) {
+  FILE *fp = path ? std::fopen(path, "r") : nullptr;
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), fp)) {
+    const char *bar = std::strchr(line, '|');
+    if (!bar || std::string(line, bar - line) != sig) continue;
+    PairTile c{};
+    if (std::sscanf(bar + 1, "%d %d %d", &c.waves, &c.chunks, &c.split) == 3 && tile_built(c)) {
+      *t = c;
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+}  // namespace
+
+extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
+                             double *best_ms) {
+  if (!s || reps < 1) return TDPD_ERR_INVALID_ARG;
+  int rc = ensure_forces(s);
+  if (rc) return rc;
+  const std::string sig = tune_signature(s);
+  PairTile best = s->tile;
+  double best_t = -1.0;
+  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
+  if (s->n == 0 || s->pair_kernel == 0 || random_flux || s->n >= (int64_t(1) << 26)) {
+    if (best_ms) *best_ms = 0.0;
+    return TDPD_OK;  // the tiled kernel is not used for this system
+  }
+  if (!cache_lookup(cache_path, sig, &best)) {
+    // the pair kernel is a pure function of the binned state: time every
+    // shape on the current state, keeping the coincident-pair counters
+    unsigned long long saved[2] = {0, 0};
+    HIPCHK(hipMemcpy(saved, s->nzero, sizeof(saved), hipMemcpyDeviceToHost));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int i = 0; i < kNumPairTiles; ++i) {
+      const PairTile &t = kPairTiles[i];
+      auto launch = [&]() {
+        (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, s->n,
+                                s->kdev, s->F, s->Q, s->nzero, s->errw, t, s->st);
+      };
+      launch();  // warm-up
+      (void)hipEventRecord(e0, s->st);
+      for (int r = 0; r < reps; ++r) launch();
+      (void)hipEventRecord(e1, s->st);
+      if (hipEventSynchronize(e1) != hipSuccess) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double avg = double(ms) / reps;
+      if (best_t < 0.0 || avg < best_t) {
+        best_t = avg;
+        best = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    rc = check_launch(s);
+    if (rc) return rc;
+    HIPCHK(hipMemcpy(s->nzero, saved, sizeof(saved), hipMemcpyHostToDevice));
+    if (cache_path) {
+      FILE *fp = std::fopen(cache_path, "a");
+      if (!fp) return s->fail(TDPD_ERR_IO, std::string("autotune: cannot write ") + cache_path);
+      std::fprintf(fp, "%s|%d %d %d %.6f\n", sig.c_str(), best.waves, best.chunks, best.split,
+                   best_t);
+      std::fclose(fp);
+    }
+  }
+  s->tile = best;
+  if (best_ms) *best_ms = best_t;
+  // graphs hold the previous shape; forces are re-evaluated with the chosen one
+  s->destroy_graphs();
+  rc = evaluate_at(s, s->kdev_val);
+  if (rc) return rc;
+  return tdpd_sync(s);
+}
+
+extern "C" int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  const PairTile t{waves, chunks, split};
+  if (!tile_built(t)) return s->fail(TDPD_ERR_UNSUPPORTED, "set_tile: shape not built");
+  s->tile = t;
+  s->destroy_graphs();
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split) {
+  if (!s || !waves || !chunks || !split) return TDPD_ERR_INVALID_ARG;
+  *waves = s->tile.waves;
+  *chunks = s->tile.chunks;
+  *split = s->tile.split;
+  return TDPD_OK;
 }

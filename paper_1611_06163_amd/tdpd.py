@@ -100,6 +100,9 @@ def lib():
             "tdpd_diagnostics": (C.c_int, [P, P, I64]),
             "tdpd_set_timing": (C.c_int, [P, I32]),
             "tdpd_get_timing": (C.c_int, [P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
+            "tdpd_autotune": (C.c_int, [P, C.c_char_p, I32, C.POINTER(C.c_double)]),
+            "tdpd_set_tile": (C.c_int, [P, I32, I32, I32]),
+            "tdpd_get_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
             "tdpd_save": (C.c_int, [P, C.c_char_p]),
             "tdpd_load": (C.c_int, [P, C.c_char_p]),
             "tdpd_num_particles": (I64, [P]),
@@ -295,6 +298,23 @@ class System:
         self._check(lib().tdpd_diagnostics(self.h, _ptr(out), out.size))
         return dict(P=out[:3], kT=out[3], C=out[4:4 + self.S],
                     av=out[4 + self.S:].reshape(nrbc, 2))
+
+    def autotune(self, cache_path=None, reps=5):
+        """Pick the fastest tile shape of the pair kernel (returns its ms)."""
+        ms = C.c_double()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        self._check(lib().tdpd_autotune(self.h, path, int(reps), C.byref(ms)))
+        return ms.value
+
+    @property
+    def tile(self):
+        w, c, sp = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(lib().tdpd_get_tile(self.h, C.byref(w), C.byref(c), C.byref(sp)))
+        return (w.value, c.value, sp.value)
+
+    @tile.setter
+    def tile(self, t):
+        self._check(lib().tdpd_set_tile(self.h, int(t[0]), int(t[1]), int(t[2])))
 
     def save(self, path):
         self._check(lib().tdpd_save(self.h, os.fsencode(path)))

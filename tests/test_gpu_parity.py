@@ -259,3 +259,51 @@ def test_checkpoint_resume_bitwise(tmp_path):
     # a checkpoint of another system is refused
     with pytest.raises(tdpd.TdpdError):
         gpu_system(I.c1()).load(path)
+
+
+@pytest.mark.parametrize("tile", [(4, 1, 1), (4, 3, 1), (2, 2, 1), (2, 4, 1), (4, 2, 2), (2, 2, 4)])
+@pytest.mark.parametrize("name", ["cluster", "c2"])
+def test_tile_shapes_match_oracle(tile, name):
+    """Every tile shape of the cell-tiled kernel gives forces and fluxes
+    within tolerance of the oracle (cluster: cells above 64 particles and
+    stencils above 256 candidates; c2: one cell body in solvent)."""
+    cfg = _cluster_cfg() if name == "cluster" else I.c2()
+    sysg = gpu_system(cfg, kernel=1)
+    sysg.tile = tile
+    assert sysg.tile == tile
+    k = 3
+    sysg.compute_forces(k)
+    F, Q = sysg.get_forces()
+    pos, vel, conc = sysg.get_state()
+    o = Oracle(cfg)
+    ref = o.forces(pos, vel, conc, k=k)
+    excl = near_cutoff_mask(o, cfg, pos, vel, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/tile{tile}")
+    assert rep["badF"] == 0 and rep["badQ"] == 0
+    assert rep["excluded"] <= 5 + cfg.n // 20
+
+
+def test_autotune_picks_a_built_shape_and_caches(tmp_path):
+    cfg = I.c2()
+    a = gpu_system(cfg, kernel=1)
+    a.step(3)
+    path = str(tmp_path / "tiles.txt")
+    ms = a.autotune(path, reps=3)
+    assert ms > 0.0
+    chosen = a.tile
+    text = open(path).read()
+    assert text.count("|") == 1 and text.strip().endswith(f"{ms:.6f}")
+    # forces after tuning are those of the chosen shape at the same state
+    F1, Q1 = a.get_forces()
+    b = gpu_system(cfg, kernel=1)
+    b.step(3)
+    b.tile = chosen
+    b.compute_forces(3)
+    F2, Q2 = b.get_forces()
+    assert np.array_equal(F1, F2) and np.array_equal(Q1, Q2)
+    # a second system of the same workload takes the cached shape without timing
+    c = gpu_system(cfg, kernel=1)
+    c.autotune(path, reps=3)
+    assert c.tile == chosen and open(path).read() == text
+    with pytest.raises(tdpd.TdpdError):
+        c.tile = (3, 3, 3)
