@@ -239,6 +239,73 @@ int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps, double *bes
 int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split);
 int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split);
 
+/* ---------------------------------------------------------------------
+   Membrane surrogate.  Not part of the paper's method: a learned stand-in
+   for the bending force (Eq. 19) plus the local-area force (Eq. 17, k_l
+   term) of a membrane vertex, with the plain forces as judge and fallback.
+
+   Network: 20 inputs -> 128 -> 128 -> 128 (SiLU after each) -> 3, on the
+   matrix cores in bfloat16 with FP32 accumulation (weights, inputs and
+   hidden activations rounded to bfloat16 where they enter a product).
+   Parameters are TDPD_MLP_PARAMS floats, layer by layer [W1 (128 x 20, row
+   = output unit), b1, W2 (128 x 128), b2, W3, b3, W4 (3 x 128), b4].
+
+   Inputs of vertex v: the vectors to its 1-ring neighbours (counter-
+   clockwise seen from outside, starting at the smallest mesh index) in the
+   local frame (e1 = first ring vector projected on the tangent plane,
+   e2 = n x e1, n = normalised sum of consecutive ring cross products),
+   divided by the mesh's mean rest edge length, six slots (slot 6 zero for a
+   degree-5 vertex), then 100 (A - A0)/A0 and 100 (V - V0)/V0 of its cell
+   from the previous force evaluation.  Output y in the local frame; force =
+   force_scale (y1 e1 + y2 e2 + y3 n).  Vertices of degree other than 5 or 6
+   always use the plain forces. */
+#define TDPD_MLP_PARAMS 36099
+typedef struct tdpd_mlp tdpd_mlp;
+/* Network with parameters and Adam moments on the device (caller's allocator
+   as for tdpd_create; hip_stream borrowed).  Parameters start undefined. */
+int tdpd_mlp_create(void *hip_stream, tdpd_alloc_fn alloc, tdpd_free_fn free_fn, void *user,
+                    tdpd_mlp **out);
+int64_t tdpd_mlp_num_params(void);
+/* Copy TDPD_MLP_PARAMS host floats in (and reset the Adam moments) / out.
+   TDPD_ERR_INVALID_ARG for a non-finite value. */
+int tdpd_mlp_set_params(tdpd_mlp *m, const float *params);
+int tdpd_mlp_get_params(tdpd_mlp *m, float *params);
+/* Y [n][3] = network(X [n][20]); host buffers. */
+int tdpd_mlp_forward(tdpd_mlp *m, const float *X, int64_t n, float *Y);
+/* Mean over rows and outputs of (y - T/target_scale)^2 and its gradient
+   with respect to the parameters (TDPD_MLP_PARAMS floats, may be NULL). */
+int tdpd_mlp_loss_grad(tdpd_mlp *m, const float *X, const float *T, int64_t n,
+                       float target_scale, double *loss, float *grad);
+/* steps Adam updates (lr, beta1 0.9, beta2 0.999, eps 1e-8; moments kept
+   across calls) on consecutive full batches of `batch` rows of the data set
+   (taken in order, cycling; the caller shuffles), the loss of each batch
+   before its update in loss_out [steps] (may be NULL).  The data set is
+   copied to the device for the call.  Needs n >= batch. */
+int tdpd_mlp_train(tdpd_mlp *m, const float *X, const float *T, int64_t n, float target_scale,
+                   int32_t batch, int32_t steps, float lr, double *loss_out);
+const char *tdpd_mlp_last_error(const tdpd_mlp *m);
+void tdpd_mlp_destroy(tdpd_mlp *m);
+
+/* Training samples of every membrane vertex at the current state: inputs X
+   [n_vertices][20], the plain bending + local-area force in the vertex's
+   local frame T [n_vertices][3] (not scaled), and whether the vertex may use
+   the network ok [n_vertices] (any pointer may be NULL).  Vertices in the
+   order of tdpd_add_rbc calls.  TDPD_ERR_STATE without cells. */
+int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *ok);
+/* From now on the bending + local-area force of a vertex comes from a copy
+   of the network's current parameters, except where the last check found
+   |F_net - F_plain| > tol x (RMS of |F_plain| over the vertex's cell) or the
+   vertex's degree is not 5 or 6.  Checks run at steps k with k %
+   check_every == 0 (the set-up pass is k = 0).  Forces are re-evaluated at
+   the current state.  */
+int tdpd_surrogate_enable(tdpd_sys *s, const tdpd_mlp *mlp, float force_scale, float tol,
+                          int32_t check_every);
+int tdpd_surrogate_disable(tdpd_sys *s);
+/* Of the last check: out[0] fraction of vertices on the network, out[1]
+   max and out[2] mean relative error over vertices that may use it, out[3]
+   fraction of vertices that may use it. */
+int tdpd_surrogate_stats(tdpd_sys *s, double *out);
+
 int64_t tdpd_num_particles(const tdpd_sys *s);
 int32_t tdpd_num_boxes(const tdpd_sys *s);
 int64_t tdpd_step_counter(const tdpd_sys *s);

@@ -65,12 +65,13 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
     const int64_t *__restrict__ rbc_first, const int64_t *__restrict__ rbc_voff, State s,
     const uint32_t *__restrict__ slot_of_gid, double *__restrict__ av,
     double *__restrict__ centroid, const uint32_t *__restrict__ kdev, float *__restrict__ Fm,
-    uint32_t *err) {
+    uint32_t *err, SurrUse su) {
   extern __shared__ float lds[];
   __shared__ double red[kMemThreads];
   __shared__ double tot[5];
   const int r = blockIdx.x, tid = threadIdx.x;
   const uint32_t k = *kdev;
+  if (mc.gate > 0 && (k % uint32_t(mc.gate)) != 0u) return;
   const MeshDev &M = meshes[rbc_mesh[r]];
   const BoxDev &B = boxes[rbc_box[r]];
   const int nv = M.nv;
@@ -121,7 +122,7 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
       if (tid == 0) tot[f] = red[0];
       __syncthreads();
     }
-    if (tid == 0) {
+    if (tid == 0 && !mc.local_only) {
       av[2 * r] = tot[0];
       av[2 * r + 1] = tot[1];
       centroid[3 * r] = double(cf.x) + tot[2] / nv;
@@ -202,12 +203,14 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
   __syncthreads();
 
   // ---- 3. per vertex
-  const float cg = float(M.kg * (av[2 * r] - M.A0) / M.A0);
-  const float cv = float(M.kv * (av[2 * r + 1] - M.V0) / M.V0);
+  const float cg = mc.local_only ? 0.f : float(M.kg * (tot[0] - M.A0) / M.A0);
+  const float cv = mc.local_only ? 0.f : float(M.kv * (tot[1] - M.V0) / M.V0);
   const float s0 = sinf(M.theta0), c0 = cosf(M.theta0);
   for (int v = tid; v < nv; v += kMemThreads) {
     const float3 pv = P(v);
     float3 f = make_float3(0.f, 0.f, 0.f);
+    // bending and local area of this vertex come from the surrogate
+    const bool sv = su.flag && su.flag[rbc_voff[r] + v];
     if (terms & (TDPD_TERM_BOND | TDPD_TERM_BOND_VISCOUS | TDPD_TERM_BOND_RANDOM)) {
       for (int q = M.bond_off[v]; q < M.bond_off[v + 1]; ++q) {
         const int inc = M.bond_inc[q];
@@ -228,7 +231,8 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
           const float nl = sqrtf(dt3(nn, nn));
           const float At = 0.5f * nl;
           const float a0 = M.A0t[tr.z];
-          const float coef = -(cg + M.kl * (At - a0) / a0) * 0.5f / nl;
+          const float cl = sv ? 0.f : M.kl * (At - a0) / a0;
+          const float coef = -(cg + cl) * 0.5f / nl;
           const float3 g = crs(nn, sub(rc, rb));  // |n| * (n_hat x (c - b))
           f.x += coef * g.x;
           f.y += coef * g.y;
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
         }
       }
     }
-    if (terms & TDPD_TERM_BENDING) {
+    if ((terms & TDPD_TERM_BENDING) && !sv) {
       const float3 zero3 = make_float3(0.f, 0.f, 0.f);
       for (int q = M.dih_off[v]; q < M.dih_off[v + 1]; ++q) {
         const int4 D = M.dih_inc[q];
@@ -260,6 +264,11 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
       }
     }
     const int64_t o = 3 * (rbc_voff[r] + v);
+    if (sv) {
+      f.x += su.Fs[o];
+      f.y += su.Fs[o + 1];
+      f.z += su.Fs[o + 2];
+    }
     Fm[o] = f.x;
     Fm[o + 1] = f.y;
     Fm[o + 2] = f.z;
@@ -272,11 +281,11 @@ void launch_membrane(const MembraneConst &mc, const BoxDev *boxes, const MeshDev
                      const int64_t *rbc_voff, int nrbc, State s,
                      const uint32_t *slot_of_gid, double *av, double *centroid,
                      const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
-                     hipStream_t st) {
+                     SurrUse su, hipStream_t st) {
   if (nrbc <= 0) return;
   hipLaunchKernelGGL(k_membrane, dim3(nrbc), dim3(kMemThreads), lds_bytes, st, mc, boxes, meshes,
                      rbc_mesh, rbc_box, rbc_first, rbc_voff, s, slot_of_gid, av, centroid, kdev, Fm,
-                     err);
+                     err, su);
 }
 
 }  // namespace tdpd

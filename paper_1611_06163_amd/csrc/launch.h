@@ -100,6 +100,9 @@ struct MeshDev {
   const int4 *dih_inc;       // [nd] (a, b, c, d)
   const uint8_t *dih_role;   // [nd]
   const float *A0t;          // [ntri]
+  const int32_t *ring_off;   // [nv+1] 1-ring of each vertex
+  const int32_t *ring;       // counter-clockwise from outside, from the smallest index
+  float ell;                 // mean rest edge length (surrogate feature scale)
   float A0, V0, theta0;
   float p, m_pow, kb, kg, kl, kv, gamma_t, gamma_c;
 };
@@ -107,6 +110,15 @@ struct MeshDev {
 struct MembraneConst {
   float kT, dt;
   int terms;
+  int local_only;  // 1: bending and local area only (no K-Gather writes, no global terms)
+  int gate;        // > 0: run only at steps k with k % gate == 0
+};
+
+// Vertices whose bending and local-area forces come from the surrogate:
+// flag[v] != 0 selects Fs[v] instead (global vertex index).
+struct SurrUse {
+  const uint8_t *flag;
+  const float *Fs;
 };
 
 // All membrane terms of every cell, one workgroup per cell: per-cell FP64
@@ -122,6 +134,66 @@ void launch_membrane(const MembraneConst &mc, const BoxDev *boxes, const MeshDev
                      const int64_t *rbc_voff, int nrbc, State s,
                      const uint32_t *slot_of_gid, double *av, double *centroid,
                      const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
-                     hipStream_t st);
+                     SurrUse su, hipStream_t st);
+
+// ------------------------------------------------------------ surrogate
+constexpr int kSurrIn = 20, kSurrHid = 128, kSurrOut = 3;
+constexpr int kSurrParams = kSurrHid * kSurrIn + kSurrHid + 2 * (kSurrHid * kSurrHid + kSurrHid) +
+                            kSurrOut * kSurrHid + kSurrOut;  // 36,099
+constexpr float kSurrDev = 100.f;  // scale of the (A - A0)/A0, (V - V0)/V0 inputs
+constexpr int kRingMax = 12;
+
+// offsets of the layers in the flat parameter vector
+struct MlpLayout {
+  static constexpr int W1 = 0, b1 = W1 + kSurrHid * kSurrIn, W2 = b1 + kSurrHid,
+                       b2 = W2 + kSurrHid * kSurrHid, W3 = b2 + kSurrHid,
+                       b3 = W3 + kSurrHid * kSurrHid, W4 = b3 + kSurrHid,
+                       b4 = W4 + kSurrOut * kSurrHid, end = b4 + kSurrOut;
+};
+static_assert(MlpLayout::end == kSurrParams, "parameter layout");
+
+enum { kEpiStore = 0, kEpiSilu = 1, kEpiSiluGrad = 2 };
+struct GemmArgs {
+  const float *A;
+  int64_t sa_i, sa_p;
+  const float *B;
+  int64_t sb_p, sb_j;
+  float *C;
+  int64_t ldc;
+  int64_t M, N, K;
+  const float *bias;  // [N] or null
+  int epi;
+  float *H;           // kEpiSilu: activation out (same layout as C)
+  const float *Z;     // kEpiSiluGrad: pre-activation in (same layout as C)
+};
+void launch_gemm_bf16(const GemmArgs &g, hipStream_t st);
+void launch_loss_grad(const float *Y, const float *T, int64_t n, float inv_scale, float *dY,
+                      double *part, hipStream_t st);
+int64_t loss_grad_blocks(int64_t n);
+void launch_sum_parts(const double *part, int64_t n, double *out, hipStream_t st);
+void launch_colsum(const float *D, int64_t m, int ld, int ncol, float *out, hipStream_t st);
+void launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                 float b2, float eps, float bc1, float bc2, hipStream_t st);
+
+// Network forward pass on n rows of X [n][20] into Y [n][3] with two
+// scratch activations Ha, Hb [n][128]; params in the flat layout
+// [W1 (128x20), b1, W2, b2, W3, b3, W4 (3x128), b4].
+void mlp_forward(const float *params, const float *X, int64_t n, float *Ha, float *Hb, float *Y,
+                 hipStream_t st);
+
+struct SurrDev {
+  const int32_t *vcell, *rbc_mesh, *rbc_box;
+  const int64_t *rbc_voff, *rbc_first;
+  float *X, *R, *Y, *Fs, *Fp, *stats;
+  uint8_t *ok, *flag;
+  float s_F, tol;
+};
+void launch_surr_features(const SurrDev &sd, const BoxDev *boxes, const MeshDev *meshes, State s,
+                          const uint32_t *slot_of_gid, const double *av, int64_t nvert,
+                          hipStream_t st);
+void launch_surr_apply(const SurrDev &sd, int64_t nvert, hipStream_t st);
+void launch_surr_targets(const SurrDev &sd, float *T, int64_t nvert, hipStream_t st);
+void launch_surr_check(const SurrDev &sd, int nrbc, const uint32_t *kdev, int every,
+                       hipStream_t st);
 
 }  // namespace tdpd

@@ -26,6 +26,8 @@ struct HostMesh {
   std::vector<int4> tri_inc, dih_inc;
   std::vector<uint8_t> dih_role;
   std::vector<float> A0t;
+  std::vector<int32_t> ring_off, ring;  // 1-rings, counter-clockwise from the smallest index
+  double ell = 0;                       // mean rest edge length
   std::vector<std::pair<int, int>> bfs;  // (vertex, parent) breadth-first order
   double A0 = 0, V0 = 0, theta0 = 0, max_radius = 0;
   tdpd_mesh_params mp{};
@@ -116,6 +118,12 @@ struct tdpd_sys {
   uint32_t kdev_val = 0;          // host mirror of *kdev
   uint32_t *cell_count = nullptr, *bin_tmp = nullptr, *tile_sum = nullptr;
   float *Fm = nullptr;            // membrane forces by global vertex [nvert][3]
+  // membrane surrogate (bending + local area from the network)
+  bool surr_on = false;
+  int surr_every = 0;             // fallback check interval (steps)
+  SurrDev sd{};
+  float *surr_params = nullptr, *surr_Ha = nullptr, *surr_Hb = nullptr;
+  int32_t *d_vcell = nullptr;
   hipStream_t st2 = nullptr, gst = nullptr;  // membrane stream, capture stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};
@@ -563,6 +571,30 @@ extern "C" int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref, int32_t
     }
   }
   M.dih_off[nv] = int(M.dih_inc.size());
+  // 1-rings: next[v][p] = q for every triangle (v, p, q) in outward
+  // counter-clockwise order; each ring starts at the smallest neighbour index
+  {
+    std::vector<std::map<int, int>> nxt(nv);
+    for (int t = 0; t < ntri; ++t)
+      for (int e = 0; e < 3; ++e)
+        nxt[tri[3 * t + e]][tri[3 * t + (e + 1) % 3]] = tri[3 * t + (e + 2) % 3];
+    M.ring_off.assign(nv + 1, 0);
+    for (int v = 0; v < nv; ++v) {
+      M.ring_off[v] = int(M.ring.size());
+      const int start = nxt[v].begin()->first;
+      int q = start;
+      do {
+        M.ring.push_back(q);
+        q = nxt[v].at(q);
+      } while (q != start && int(M.ring.size()) - M.ring_off[v] <= int(nxt[v].size()));
+      if (q != start || int(M.ring.size()) - M.ring_off[v] != int(nxt[v].size()))
+        return s->fail(TDPD_ERR_INVALID_ARG, "add_mesh: a vertex neighbourhood is not a disc");
+    }
+    M.ring_off[nv] = int(M.ring.size());
+    double sl = 0;
+    for (double l : l0) sl += l;
+    M.ell = sl / double(l0.size());
+  }
   // largest distance from the rest centroid (for the periodic-image limit)
   double cen[3] = {0, 0, 0};
   for (int v = 0; v < nv; ++v)
@@ -709,13 +741,18 @@ static int prepare(tdpd_sys *s) {
       int4 *ti, *di;
       uint8_t *dr;
       float *a0t;
+      int32_t *rgo, *rg;
       if ((rc = upload(s, &tri, M.tri)) || (rc = upload(s, &bab, M.bond_ab)) ||
           (rc = upload(s, &bp, M.bond_par)) || (rc = upload(s, &bo, M.bond_off)) ||
           (rc = upload(s, &bi, M.bond_inc)) || (rc = upload(s, &to, M.tri_off)) ||
           (rc = upload(s, &ti, M.tri_inc)) || (rc = upload(s, &dof, M.dih_off)) ||
           (rc = upload(s, &di, M.dih_inc)) || (rc = upload(s, &dr, M.dih_role)) ||
-          (rc = upload(s, &a0t, M.A0t)))
+          (rc = upload(s, &a0t, M.A0t)) || (rc = upload(s, &rgo, M.ring_off)) ||
+          (rc = upload(s, &rg, M.ring)))
         return rc;
+      D.ring_off = rgo;
+      D.ring = rg;
+      D.ell = float(M.ell);
       D.nv = M.nv;
       D.ntri = M.ntri;
       D.nbond = int(M.bond_ab.size());
@@ -850,10 +887,29 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
     (void)hipEventRecord(s->ev_fork, st);
     (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
     const bool tm = s->phase_begin(2, s->st2);
+    SurrUse su{nullptr, nullptr};
+    if (s->surr_on) {
+      // network forces from the lagged cell totals, then (every surr_every
+      // steps, gated on the device counter) the plain bending + local-area
+      // forces and the per-vertex fallback decision
+      launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av,
+                           s->nvert, s->st2);
+      mlp_forward(s->surr_params, s->sd.X, s->nvert, s->surr_Ha, s->surr_Hb, s->sd.Y, s->st2);
+      launch_surr_apply(s->sd, s->nvert, s->st2);
+      MembraneConst ml = s->mc;
+      ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
+      ml.local_only = 1;
+      ml.gate = s->surr_every;
+      launch_membrane(ml, s->d_boxes, s->d_meshes, s->d_rbc_mesh, s->d_rbc_box, s->d_rbc_first,
+                      s->d_rbc_voff, nrbc, s->cur(), s->slot_of_gid, s->d_av, s->d_centroid,
+                      s->kdev, s->sd.Fp, s->errw, s->mem_lds, SurrUse{nullptr, nullptr}, s->st2);
+      launch_surr_check(s->sd, nrbc, s->kdev, s->surr_every, s->st2);
+      su = SurrUse{s->sd.flag, s->sd.Fs};
+    }
     launch_membrane(s->mc, s->d_boxes, s->d_meshes, s->d_rbc_mesh, s->d_rbc_box, s->d_rbc_first,
                     s->d_rbc_voff, nrbc,
                     s->cur(), s->slot_of_gid, s->d_av, s->d_centroid, s->kdev, s->Fm, s->errw,
-                    s->mem_lds, s->st2);
+                    s->mem_lds, su, s->st2);
     s->phase_end(2, tm, s->st2);
     (void)hipEventRecord(s->ev_join, s->st2);
   }
@@ -1339,5 +1395,132 @@ extern "C" int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks,
   *waves = s->tile.waves;
   *chunks = s->tile.chunks;
   *split = s->tile.split;
+  return TDPD_OK;
+}
+
+// ------------------------------------------------------------- surrogate
+const float *mlp_device_params(const tdpd_mlp *m);
+
+namespace {
+
+// buffers of the surrogate path (once per system)
+int surr_alloc(tdpd_sys *s) {
+  if (s->sd.X) return TDPD_OK;
+  const int64_t nv = s->nvert;
+  const int nrbc = int(s->rbc_mesh.size());
+  std::vector<int32_t> vcell(static_cast<size_t>(nv), 0);
+  for (int r = 0; r < nrbc; ++r)
+    for (int64_t v = s->rbc_voff[r]; v < s->rbc_voff[r + 1]; ++v) vcell[v] = r;
+  int rc = upload(s, &s->d_vcell, vcell);
+  if (rc) return rc;
+  SurrDev &d = s->sd;
+  d.vcell = s->d_vcell;
+  d.rbc_mesh = s->d_rbc_mesh;
+  d.rbc_box = s->d_rbc_box;
+  d.rbc_voff = s->d_rbc_voff;
+  d.rbc_first = s->d_rbc_first;
+  d.X = dallocT<float>(s, size_t(nv) * kSurrIn);
+  d.R = dallocT<float>(s, size_t(nv) * 9);
+  d.Y = dallocT<float>(s, size_t(nv) * kSurrOut);
+  d.Fs = dallocT<float>(s, size_t(nv) * 3);
+  d.Fp = dallocT<float>(s, size_t(nv) * 3);
+  d.stats = dallocT<float>(s, size_t(nrbc) * 3);
+  d.ok = dallocT<uint8_t>(s, size_t(nv));
+  d.flag = dallocT<uint8_t>(s, size_t(nv));
+  s->surr_params = dallocT<float>(s, kSurrParams);
+  s->surr_Ha = dallocT<float>(s, size_t(nv) * kSurrHid);
+  s->surr_Hb = dallocT<float>(s, size_t(nv) * kSurrHid);
+  if (!d.X || !d.R || !d.Y || !d.Fs || !d.Fp || !d.stats || !d.ok || !d.flag || !s->surr_params ||
+      !s->surr_Ha || !s->surr_Hb) {
+    d.X = nullptr;
+    return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  }
+  HIPCHK(hipMemsetAsync(d.flag, 0, size_t(nv), s->st));
+  HIPCHK(hipMemsetAsync(d.ok, 0, size_t(nv), s->st));
+  HIPCHK(hipMemsetAsync(d.stats, 0, sizeof(float) * 3 * nrbc, s->st));
+  HIPCHK(hipMemsetAsync(d.Fs, 0, sizeof(float) * 3 * nv, s->st));
+  return TDPD_OK;
+}
+
+}  // namespace
+
+extern "C" int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *ok) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  int rc = ensure_forces(s);
+  if (rc) return rc;
+  if (s->rbc_mesh.empty()) return s->fail(TDPD_ERR_STATE, "surrogate_sample: no cells");
+  if ((rc = surr_alloc(s))) return rc;
+  const int nrbc = int(s->rbc_mesh.size());
+  const int64_t nv = s->nvert;
+  launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av, nv, s->st);
+  MembraneConst ml = s->mc;
+  ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
+  ml.local_only = 1;
+  ml.gate = 0;
+  launch_membrane(ml, s->d_boxes, s->d_meshes, s->d_rbc_mesh, s->d_rbc_box, s->d_rbc_first,
+                  s->d_rbc_voff, nrbc, s->cur(), s->slot_of_gid, s->d_av, s->d_centroid, s->kdev,
+                  s->sd.Fp, s->errw, s->mem_lds, SurrUse{nullptr, nullptr}, s->st);
+  // targets go through Fs, which the next step's surrogate pass rewrites
+  launch_surr_targets(s->sd, s->sd.Fs, nv, s->st);
+  if ((rc = check_launch(s))) return rc;
+  if (X) HIPCHK(hipMemcpyAsync(X, s->sd.X, sizeof(float) * kSurrIn * nv, hipMemcpyDeviceToHost, s->st));
+  if (T) HIPCHK(hipMemcpyAsync(T, s->sd.Fs, sizeof(float) * 3 * nv, hipMemcpyDeviceToHost, s->st));
+  if (ok) HIPCHK(hipMemcpyAsync(ok, s->sd.ok, size_t(nv), hipMemcpyDeviceToHost, s->st));
+  return tdpd_sync(s);
+}
+
+extern "C" int tdpd_surrogate_enable(tdpd_sys *s, const tdpd_mlp *mlp, float force_scale,
+                                     float tol, int32_t check_every) {
+  if (!s || !mlp || !(force_scale > 0.f) || !(tol >= 0.f) || check_every < 1)
+    return TDPD_ERR_INVALID_ARG;
+  int rc = prepare(s);
+  if (rc) return rc;
+  if (s->rbc_mesh.empty()) return s->fail(TDPD_ERR_STATE, "surrogate_enable: no cells");
+  if ((rc = surr_alloc(s))) return rc;
+  HIPCHK(hipStreamSynchronize(s->st));
+  HIPCHK(hipMemcpy(s->surr_params, mlp_device_params(mlp), sizeof(float) * kSurrParams,
+                   hipMemcpyDeviceToDevice));
+  HIPCHK(hipMemset(s->sd.flag, 0, size_t(s->nvert)));
+  s->sd.s_F = force_scale;
+  s->sd.tol = tol;
+  s->surr_every = check_every;
+  s->surr_on = true;
+  s->destroy_graphs();
+  // forces at the current state with the network (a check runs when the
+  // current counter is a multiple of check_every)
+  if (s->forces_valid && (rc = evaluate_at(s, s->kdev_val))) return rc;
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_surrogate_disable(tdpd_sys *s) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (!s->surr_on) return TDPD_OK;
+  s->surr_on = false;
+  s->destroy_graphs();
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_surrogate_stats(tdpd_sys *s, double *out) {
+  if (!s || !out) return TDPD_ERR_INVALID_ARG;
+  for (int q = 0; q < 4; ++q) out[q] = 0.0;
+  if (!s->sd.X) return TDPD_OK;
+  int rc = tdpd_sync(s);
+  if (rc) return rc;
+  const int nrbc = int(s->rbc_mesh.size());
+  std::vector<float> st(3 * size_t(nrbc));
+  std::vector<uint8_t> ok(size_t(s->nvert));
+  HIPCHK(hipMemcpy(st.data(), s->sd.stats, sizeof(float) * st.size(), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ok.data(), s->sd.ok, ok.size(), hipMemcpyDeviceToHost));
+  double cnt = 0, mx = 0, sm = 0, nok = 0;
+  for (int r = 0; r < nrbc; ++r) {
+    cnt += st[3 * r];
+    mx = std::max(mx, double(st[3 * r + 1]));
+    sm += st[3 * r + 2];
+  }
+  for (uint8_t o : ok) nok += o ? 1.0 : 0.0;
+  out[0] = cnt / double(s->nvert);
+  out[1] = mx;
+  out[2] = nok > 0 ? sm / nok : 0.0;
+  out[3] = nok / double(s->nvert);
   return TDPD_OK;
 }

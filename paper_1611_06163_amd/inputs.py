@@ -386,3 +386,19 @@ def ensemble(n_boxes=256, seed=4, lo=2000, hi=60000, rho=3.0, max_cells=4, shear
         cfg.shear_rate = float(shears[b])
         boxes.append(cfg)
     return boxes
+
+
+# ---------------------------------------------------------------- surrogate
+SURR_SHAPES = [(128, 20), (128, 128), (128, 128), (3, 128)]
+
+
+def mlp_init_params(seed=0):
+    """Seeded initial parameters of the membrane-surrogate network, flat in
+    the layer order [W1, b1, W2, b2, W3, b3, W4, b4]: normal weights with
+    standard deviation sqrt(2 / fan_in), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for no, ni in SURR_SHAPES:
+        parts.append(rng.normal(0.0, math.sqrt(2.0 / ni), no * ni))
+        parts.append(np.zeros(no))
+    return np.concatenate(parts).astype(np.float32)

@@ -103,6 +103,19 @@ def lib():
             "tdpd_autotune": (C.c_int, [P, C.c_char_p, I32, C.POINTER(C.c_double)]),
             "tdpd_set_tile": (C.c_int, [P, I32, I32, I32]),
             "tdpd_get_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
+            "tdpd_mlp_create": (C.c_int, [P, ALLOC_FN, FREE_FN, P, C.POINTER(P)]),
+            "tdpd_mlp_num_params": (I64, []),
+            "tdpd_mlp_set_params": (C.c_int, [P, P]),
+            "tdpd_mlp_get_params": (C.c_int, [P, P]),
+            "tdpd_mlp_forward": (C.c_int, [P, P, I64, P]),
+            "tdpd_mlp_loss_grad": (C.c_int, [P, P, P, I64, C.c_float, C.POINTER(C.c_double), P]),
+            "tdpd_mlp_train": (C.c_int, [P, P, P, I64, C.c_float, I32, I32, C.c_float, P]),
+            "tdpd_mlp_last_error": (C.c_char_p, [P]),
+            "tdpd_mlp_destroy": (None, [P]),
+            "tdpd_surrogate_sample": (C.c_int, [P, P, P, P]),
+            "tdpd_surrogate_enable": (C.c_int, [P, P, C.c_float, C.c_float, I32]),
+            "tdpd_surrogate_disable": (C.c_int, [P]),
+            "tdpd_surrogate_stats": (C.c_int, [P, P]),
             "tdpd_save": (C.c_int, [P, C.c_char_p]),
             "tdpd_load": (C.c_int, [P, C.c_char_p]),
             "tdpd_num_particles": (I64, [P]),
@@ -299,6 +312,29 @@ class System:
         return dict(P=out[:3], kT=out[3], C=out[4:4 + self.S],
                     av=out[4 + self.S:].reshape(nrbc, 2))
 
+    def surrogate_sample(self):
+        """Inputs X [nv][20], plain bending + local-area targets in the local
+        frame T [nv][3] and the may-use mask of every membrane vertex."""
+        nv = sum(len(c.rbc_first_gid) * c.mesh_xyz.shape[0] for c in self.cfgs
+                 if c.mesh_xyz is not None)
+        X = np.empty((nv, 20), np.float32)
+        T = np.empty((nv, 3), np.float32)
+        ok = np.empty(nv, np.uint8)
+        self._check(lib().tdpd_surrogate_sample(self.h, _ptr(X), _ptr(T), _ptr(ok)))
+        return X, T, ok.astype(bool)
+
+    def surrogate_enable(self, mlp, force_scale, tol=1e-2, check_every=10):
+        self._check(lib().tdpd_surrogate_enable(self.h, mlp.h, float(force_scale), float(tol),
+                                                int(check_every)))
+
+    def surrogate_disable(self):
+        self._check(lib().tdpd_surrogate_disable(self.h))
+
+    def surrogate_stats(self):
+        out = np.zeros(4)
+        self._check(lib().tdpd_surrogate_stats(self.h, _ptr(out)))
+        return dict(on_network=out[0], max_err=out[1], mean_err=out[2], eligible=out[3])
+
     def autotune(self, cache_path=None, reps=5):
         """Pick the fastest tile shape of the pair kernel (returns its ms)."""
         ms = C.c_double()
@@ -337,3 +373,74 @@ class System:
     @property
     def coincident_pairs(self):
         return int(lib().tdpd_coincident_pairs(self.h))
+
+
+class Mlp:
+    """The membrane-surrogate network of libtdpd (tdpd_mlp_*): parameters and
+    Adam moments on the device; forward pass, gradient and training run in
+    the library's kernels."""
+
+    def __init__(self, params=None, stream=None):
+        L = lib()
+        self._alloc = _TorchAllocator()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        rc = L.tdpd_mlp_create(C.c_void_p(stream) if stream else None, self._alloc.alloc_cb,
+                               self._alloc.free_cb, None, C.byref(h))
+        if rc:
+            raise TdpdError(rc, "tdpd_mlp_create failed")
+        self.h = h
+        self.n_params = int(L.tdpd_mlp_num_params())
+        if params is not None:
+            self.set_params(params)
+
+    def _check(self, rc):
+        if rc:
+            raise TdpdError(rc, lib().tdpd_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tdpd_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        self._check(lib().tdpd_mlp_set_params(self.h, _ptr(p)))
+
+    def get_params(self):
+        p = np.empty(self.n_params, np.float32)
+        self._check(lib().tdpd_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def forward(self, X):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.empty((X.shape[0], 3), np.float32)
+        self._check(lib().tdpd_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(Y)))
+        return Y
+
+    def loss_grad(self, X, T, target_scale=1.0):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        loss = C.c_double()
+        g = np.empty(self.n_params, np.float32)
+        self._check(lib().tdpd_mlp_loss_grad(self.h, _ptr(X), _ptr(T), X.shape[0],
+                                             float(target_scale), C.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train(self, X, T, target_scale, batch, steps, lr):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        losses = np.empty(max(int(steps), 1))
+        self._check(lib().tdpd_mlp_train(self.h, _ptr(X), _ptr(T), X.shape[0],
+                                         float(target_scale), int(batch), int(steps), float(lr),
+                                         _ptr(losses)))
+        return losses[:int(steps)]

@@ -1,0 +1,169 @@
+"""GPU tests of the membrane surrogate: the library's bfloat16 MFMA network
+(forward, gradient, Adam) against the FP64 oracle with the same bfloat16
+rounding points, the features and plain targets against the oracle, and the
+step with the network switched in."""
+import copy
+
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_system
+from oracle import Oracle
+from oracle import surrogate as S
+from paper_1611_06163_amd import inputs as I
+from paper_1611_06163_amd import tdpd
+
+pytestmark = pytest.mark.gpu
+T_LOCAL = tdpd.TERM["area"] | tdpd.TERM["bend"]
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, 20)).astype(np.float32)
+    X[:, 18:] *= 0.1
+    T = rng.normal(size=(n, 3)).astype(np.float32)
+    return X, T
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000])
+def test_forward_matches_oracle(n):
+    p = I.mlp_init_params(1)
+    X, _ = _data(n, 2)
+    net = tdpd.Mlp(p)
+    Y = net.forward(X)
+    ref, _ = S.forward(p, X, rounding=True)
+    # Both sides round every hidden activation to bfloat16; where FP32 and
+    # FP64 sums fall on the two sides of a rounding boundary one activation
+    # differs by a bfloat16 ulp (2^-8 relative), so rows are compared on the
+    # scale of the batch's outputs, not of the row alone.
+    err = np.linalg.norm(Y - ref, axis=1)
+    nrm = np.linalg.norm(ref, axis=1)
+    scale = nrm + np.sqrt(np.mean(nrm ** 2))
+    print("forward err / scale max", (err / scale).max(), "p99",
+          np.quantile(err / scale, 0.99), flush=True)
+    assert (err <= 1e-3 * scale).all()
+    assert np.array_equal(net.get_params(), p)
+
+
+def test_gradient_matches_oracle():
+    p = I.mlp_init_params(3)
+    X, T = _data(700, 4)
+    net = tdpd.Mlp(p)
+    loss, g = net.loss_grad(X, T, target_scale=2.0)
+    rl, rg = S.loss_and_grad(p, X, T / 2.0, rounding=True)
+    assert abs(loss - rl) <= 1e-3 * rl
+    o = 0
+    for no, ni in S.SHAPES:
+        for size in (no * ni, no):
+            a, b = g[o:o + size], rg[o:o + size]
+            rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+            print("block", o, size, "rel", rel, flush=True)
+            assert rel <= 1e-2
+            o += size
+
+
+def test_adam_step_matches_oracle_and_training_descends():
+    p = I.mlp_init_params(5)
+    X, T = _data(512, 6)
+    net = tdpd.Mlp(p)
+    losses = net.train(X, T, target_scale=1.0, batch=512, steps=1, lr=1e-3)
+    _, rg = S.loss_and_grad(p, X, T, rounding=True)
+    ref, _, _ = S.adam(p.astype(np.float64), rg, np.zeros_like(rg), np.zeros_like(rg), 1, lr=1e-3)
+    got = net.get_params()
+    # the first step moves every parameter by about lr * sign(g)
+    big = np.abs(rg) > 1e-3 * np.abs(rg).max()
+    close = np.abs(got - ref) <= 1e-5
+    assert close[big].mean() >= 0.99
+    assert losses.shape == (1,)
+    # a few hundred steps on a learnable target reduce the loss
+    Tt = np.tanh(X[:, :3] - 0.5 * X[:, 3:6]).astype(np.float32)
+    net2 = tdpd.Mlp(I.mlp_init_params(7))
+    L = net2.train(X, Tt, target_scale=1.0, batch=128, steps=400, lr=3e-3)
+    print("loss first/last", L[:4].mean(), L[-4:].mean(), flush=True)
+    assert L[-4:].mean() < 0.3 * L[:4].mean()
+
+
+def _cell_cfg(seed=41):
+    cfg = I.small_suspension(seed=seed, box=(14.0, 14.0, 14.0), n_cells=1)
+    return cfg
+
+
+def test_features_and_targets_match_oracle():
+    cfg = _cell_cfg()
+    g = gpu_system(cfg)
+    g.step(5)
+    g.compute_forces(5)  # the lagged cell totals are those of this state
+    X, T, ok = g.surrogate_sample()
+    pos, vel, conc = g.get_state()
+    av = g.diagnostics()["av"][0]
+    nv = cfg.mesh_xyz.shape[0]
+    g0 = cfg.rbc_first_gid[0]
+    o = Oracle(cfg)
+    info = o.mesh_info()
+    rings = S.rings(cfg.mesh_tri, nv)
+    e = set()
+    for a, b, c in cfg.mesh_tri:
+        for u, w in ((a, b), (b, c), (c, a)):
+            e.add((min(u, w), max(u, w)))
+    ell = np.mean([np.linalg.norm(cfg.mesh_xyz[u] - cfg.mesh_xyz[w]) for u, w in e])
+    Xr, Rr, okr = S.features(pos[g0:g0 + nv], cfg.box, rings, av[0], info["A0"], av[1],
+                             info["V0"], ell, 100.0)
+    assert np.array_equal(ok, okr)
+    print("feature max abs err", np.abs(X - Xr).max(), flush=True)
+    assert np.abs(X - Xr).max() < 2e-4
+    # plain bending + local area forces of the oracle in the same frames
+    c2 = copy.deepcopy(cfg)
+    c2.mesh_params.kg = 0.0
+    o2 = Oracle(c2, terms=T_LOCAL)
+    F = o2.membrane(pos.astype(np.float64), vel, k=5)["F"][g0:g0 + nv]
+    Tr = np.einsum("nij,nj->ni", Rr, F)
+    rms = np.sqrt(np.mean(np.sum(F ** 2, axis=1)))
+    print("target max err / rms", np.abs(T - Tr).max() / rms, flush=True)
+    assert np.abs(T - Tr).max() <= 1e-3 * rms
+
+
+def test_step_with_network_matches_oracle_composition():
+    cfg = _cell_cfg(43)
+    p = I.mlp_init_params(8) * np.float32(0.3)
+    net = tdpd.Mlp(p)
+    g = gpu_system(cfg)
+    g.step(3)
+    g.compute_forces(3)
+    s_F = 50.0
+    g.surrogate_enable(net, force_scale=s_F, tol=1e30, check_every=1)
+    st = g.surrogate_stats()
+    assert st["on_network"] == pytest.approx(st["eligible"]) and st["eligible"] > 0.85
+    F, _ = g.get_forces()
+    pos, vel, conc = g.get_state()
+    X, _, ok = g.surrogate_sample()
+    nv = cfg.mesh_xyz.shape[0]
+    g0 = cfg.rbc_first_gid[0]
+    # expected: all terms minus the plain local part on network vertices plus the network
+    o = Oracle(cfg)
+    ref = o.forces(pos, vel, conc, k=3)
+    c2 = copy.deepcopy(cfg)
+    c2.mesh_params.kg = 0.0
+    o2 = Oracle(c2, terms=T_LOCAL)
+    Floc = o2.membrane(pos.astype(np.float64), vel, k=3)["F"][g0:g0 + nv]
+    rings = S.rings(cfg.mesh_tri, nv)
+    _, Rr, _ = S.features(pos[g0:g0 + nv], cfg.box, rings, 1.0, 1.0, 1.0, 1.0, 1.0, 100.0)
+    Fnet = S.surrogate_forces(p, X.astype(np.float64), Rr, s_F, rounding=True)
+    exp = ref["F"][g0:g0 + nv].copy()
+    exp[ok] += Fnet[ok] - Floc[ok]
+    err = np.linalg.norm(F[g0:g0 + nv] - exp, axis=1)
+    bound = 1e-5 * ref["Fabs"][g0:g0 + nv] + 2e-3 * np.linalg.norm(Fnet, axis=1) + 1e-3
+    print("network step err max", (err / bound).max(), flush=True)
+    assert (err <= bound).all()
+
+
+def test_zero_tolerance_falls_back_bitwise():
+    cfg = _cell_cfg(44)
+    net = tdpd.Mlp(I.mlp_init_params(9))
+    a = gpu_system(cfg)
+    b = gpu_system(cfg)
+    b.surrogate_enable(net, force_scale=10.0, tol=0.0, check_every=1)
+    a.step(6)
+    b.step(6)
+    assert b.surrogate_stats()["on_network"] == 0.0
+    for x, y in zip(a.get_state() + a.get_forces(), b.get_state() + b.get_forces()):
+        assert np.array_equal(x, y)
