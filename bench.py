@@ -118,6 +118,110 @@ def cpu_baseline(cfg, target_s=15.0):
                        f"state, FP64 oracle, {cores} OpenMP threads, {el:.1f} s")
 
 
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _timed_steps(torch, sysg, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysg.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sysg.sync()
+    return el
+
+
+def batched_leg(torch, tdpd, steps, warmup, n_boxes=256):
+    """The batched ensemble (256 uneven periodic boxes, 2k-60k particles, 0-4
+    cells each) as one system against the same boxes as separate systems
+    stepped one after another on the same GPU."""
+    from paper_1611_06163_amd import inputs as I
+    boxes = I.ensemble(n_boxes=n_boxes, shear_max=0.0)
+    n_tot = sum(b.n for b in boxes)
+    _log(f"batched: {n_boxes} boxes, {n_tot} particles")
+    sb = tdpd.System(boxes)
+    sb.compute_forces(0)
+    sb.autotune(reps=3)
+    sb.step(warmup)
+    sb.sync()
+    el_b = _timed_steps(torch, sb, steps)
+    tile = list(sb.tile)
+    sb.close()
+    solo = []
+    for b in boxes:
+        s = tdpd.System(b)
+        s.compute_forces(0)
+        s.autotune(reps=3)
+        s.step(warmup)
+        solo.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solo:
+        s.step(steps)
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t0
+    for s in solo:
+        s.sync()
+        s.close()
+    vb, vs = n_tot * steps / el_b, n_tot * steps / el_s
+    return dict(workload=f"{n_boxes} periodic boxes, N log-uniform in [2000, 60000], rho=3, "
+                         "0-4 cells each, 1 species, shear 0",
+                particles=n_tot, steps=steps, tile=tile, value=vb, unit="particle-steps/s",
+                plain_value=vs, plain="the same boxes as separate systems, stepped in turn",
+                speedup=vb / vs, tol="bitwise: a box in the batch follows its solo trajectory "
+                                     "at the same tile shape (tests/test_gpu_batch.py)")
+
+
+def surrogate_leg(torch, tdpd, steps, warmup, workload):
+    """Train the membrane surrogate on samples of plain channel runs, then run
+    the evaluation workload plain and with the network (fallback tolerance
+    1e-2 of the cell's RMS plain force, checked every 10 steps)."""
+    from paper_1611_06163_amd import inputs as I
+    from paper_1611_06163_amd import surrogate as SU
+    t0 = time.perf_counter()
+    X, T = SU.collect(I.c3(seed=11, scale=0.25, n_cells=25), steps=450, every=5, skip=50)
+    t1 = time.perf_counter()
+    net, s_F, rep = SU.train(X, T, seed=0, batch=4096, steps=3000, lr=1e-3)
+    t2 = time.perf_counter()
+    _log(f"surrogate: {X.shape[0]} samples in {t1 - t0:.1f} s, trained in {t2 - t1:.1f} s: {rep}")
+    cfg = I.c5() if workload == "c5" else I.c3()
+    runs = []
+    for tol in (None, 1e-2, 0.1, 0.5):
+        sysg = tdpd.System(cfg)
+        sysg.compute_forces(0)
+        sysg.autotune(reps=3)
+        if tol is not None:
+            sysg.surrogate_enable(net, s_F, tol=tol, check_every=10)
+        sysg.step(warmup)
+        sysg.sync()
+        el = _timed_steps(torch, sysg, steps)
+        sysg.set_timing(tdpd.PHASE["membrane"])
+        sysg.step(min(steps, 100))
+        mem_ms, mem_n = sysg.get_timing(tdpd.PHASE["membrane"])
+        sysg.set_timing(0)
+        r = dict(tol=tol, value=cfg.n * steps / el, ms_per_step=el * 1e3 / steps,
+                 membrane_us=mem_ms * 1e3 / max(mem_n, 1))
+        if tol is not None:
+            st = sysg.surrogate_stats()
+            r.update(on_network=st["on_network"], eligible=st["eligible"],
+                     check_max_err=st["max_err"], check_mean_err=st["mean_err"])
+        runs.append(r)
+        sysg.close()
+        _log(f"surrogate run {r}")
+    plain, at = runs[0], runs[1]
+    return dict(workload=("1000 RBCs in 96x96x72" if workload == "c5" else
+                          "100 RBCs in 64x32x32 channel") + ", rho=3, 2 species",
+                particles=cfg.n, value=at["value"], unit="particle-steps/s", tol=1e-2,
+                plain_value=plain["value"], membrane_us=at["membrane_us"],
+                plain_membrane_us=plain["membrane_us"], on_network=at["on_network"],
+                by_tol=runs[1:],
+                error="per-vertex |F_net - F_plain| / RMS_cell |F_plain| of bending + "
+                      "local-area force at the last check; vertices above tol use F_plain",
+                training=dict(rep, collect_s=t1 - t0, train_s=t2 - t1,
+                              data="channel 16x32x32, 25 cells, samples every 5 steps"))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +232,9 @@ def main():
     ap.add_argument("--kernel", type=int, default=None, help="pair kernel: 0 simple, 1 tiled")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shape of the pair kernel")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--surrogate-workload", default="c3", choices=["c3", "c5"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device with torch (a plain "
                          "copy of known size, to scale hardware byte counters)")
@@ -200,6 +307,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
+    if not args.no_batched:
+        out["batched"] = batched_leg(torch, tdpd, steps=20, warmup=5)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(torch, tdpd, steps=200, warmup=20,
+                                         workload=args.surrogate_workload)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
