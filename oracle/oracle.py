@@ -39,7 +39,7 @@ class _Params(C.Structure):
         ("sigma", C.c_double * (MAXT * MAXT)), ("kappa", C.c_double * (MAXS * MAXT * MAXT)),
         ("body_force", C.c_double * 3), ("wall_axis", C.c_int32), ("wall_w", C.c_double),
         ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("box_id", C.c_uint32),
-        ("terms", C.c_int32),
+        ("terms", C.c_int32), ("shear_rate", C.c_float),
     ]
 
 
@@ -68,7 +68,8 @@ def _load():
         L.orc_add_rbc.argtypes = [P, C.c_int, C.c_int64]
         L.orc_mesh_info.argtypes = [P, C.c_int, P]
         L.orc_mesh_topology.argtypes = [P, C.c_int, P, P]
-        L.orc_pairs.argtypes = [P, C.c_int64, P, C.c_int, C.c_int, C.c_int64, P, P, P]
+        L.orc_pairs.argtypes = [P, C.c_int64, P, C.c_int, C.c_int, C.c_uint32, C.c_int64, P, P,
+                                P]
         L.orc_forces.restype = C.c_int
         L.orc_forces.argtypes = [P, C.c_int64, P, P, P, P, C.c_uint32, P, P, P, P, P, P, P, P]
         L.orc_membrane.restype = C.c_int
@@ -82,7 +83,7 @@ def _load():
         L.orc_pair_normals4.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32,
                                         C.c_uint32, C.c_uint32, P]
         L.orc_disp.restype = C.c_float
-        L.orc_disp.argtypes = [P, P, P, P]
+        L.orc_disp.argtypes = [P, P, P, C.c_uint32, P]
         L.orc_u01.restype = C.c_double
         L.orc_u01.argtypes = [C.c_uint32]
         L.orc_pair_normals.argtypes = [C.POINTER(_Params), C.c_uint32, C.c_uint32,
@@ -132,6 +133,7 @@ def _params_from(cfg, terms=TERMS_ALL):
     p.seed_hi = (cfg.seed >> 32) & 0xFFFFFFFF
     p.box_id = cfg.box_id
     p.terms = terms
+    p.shear_rate = float(getattr(cfg, "shear_rate", 0.0))
     return p
 
 
@@ -209,14 +211,14 @@ class Oracle:
         self.L.orc_mesh_topology(self.h, mesh, _ptr(e), _ptr(d))
         return e, d
 
-    def disp(self, xi, xj):
+    def disp(self, xi, xj, k=0):
         a = np.ascontiguousarray(xi, dtype=np.float32)
         b = np.ascontiguousarray(xj, dtype=np.float32)
         d = np.zeros(3, dtype=np.float32)
-        d2 = self.L.orc_disp(self.h, _ptr(a), _ptr(b), _ptr(d))
+        d2 = self.L.orc_disp(self.h, _ptr(a), _ptr(b), int(k), _ptr(d))
         return d, np.float32(d2)
 
-    def pairs(self, pos_f32, which=0, brute=False, cap=None):
+    def pairs(self, pos_f32, which=0, brute=False, cap=None, k=0):
         x = np.ascontiguousarray(pos_f32, dtype=np.float32)
         n = x.shape[0]
         if cap is None:
@@ -224,11 +226,11 @@ class Oracle:
         out = np.zeros((cap, 2), dtype=np.int32)
         cnt = np.zeros(1, dtype=np.int64)
         nz = np.zeros(1, dtype=np.int64)
-        self.L.orc_pairs(self.h, n, _ptr(x), which, int(brute), cap, _ptr(out), _ptr(cnt),
-                         _ptr(nz))
+        self.L.orc_pairs(self.h, n, _ptr(x), which, int(brute), int(k), cap, _ptr(out),
+                         _ptr(cnt), _ptr(nz))
         m = int(cnt[0])
         if m > cap:
-            return self.pairs(x, which, brute, cap=m)
+            return self.pairs(x, which, brute, cap=m, k=k)
         return out[:m].copy(), int(nz[0])
 
     def forces(self, pos, vel, conc, flags=None, k=0, which=None, energy=False):

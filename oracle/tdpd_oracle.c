@@ -84,6 +84,7 @@ typedef struct {
   double wall_w;
   uint32_t seed_lo, seed_hi, box_id;
   int32_t terms;
+  float shear_rate; /* Lees-Edwards shear rate (0: plain periodic box) */
 } orc_params;
 
 typedef struct {
@@ -180,29 +181,100 @@ void orc_pair_normals4(const orc_params *p, uint32_t k, uint32_t gi, uint32_t gj
 
 /* ------------------------------------------------------------ predicate */
 
-/* FP32 displacement x_j - x_i under the nearest periodic image, and its
-   squared length; returns the image shifts of x_j through s (may be NULL).
-   For a pair across the boundary the coordinate nearer 0 is lifted by +L
-   (one rounding, the same from both sides), so d_ji = -d_ij exactly. */
-static float disp_f32(const float *xi, const float *xj, const float *L, float d[3],
-                      float s[3]) {
+/* Box geometry at step counter k.  With a shear rate (reading C21, Lees-
+   Edwards boundaries) the periodic image of the box above (y + L_y) is
+   displaced by delta_k in x and moves with +u = shear L_y in x:
+     u = fl32(shear * L_y), delta_k = fl32(fmod(shear L_y * (k dt), L_x))
+   with the products taken in FP64 from the FP32 parameters (the library
+   uses the same sequence). */
+typedef struct {
+  float L[3];
+  float delta, u;
+  int le;
+} geom_t;
+
+static geom_t geom_at(const orc_params *p, uint32_t k) {
+  geom_t g;
+  for (int a = 0; a < 3; ++a) g.L[a] = p->box[a];
+  g.le = p->shear_rate != 0.0f;
+  g.delta = 0.0f;
+  g.u = 0.0f;
+  if (g.le) {
+    const double a = (double)p->shear_rate * (double)p->box[1];
+    const double b = (double)k * (double)(float)p->dt;
+    g.u = (float)a;
+    g.delta = (float)fmod(a * b, (double)p->box[0]);
+    if (g.delta >= p->box[0]) g.delta = 0.0f;
+  }
+  return g;
+}
+
+/* FP32 displacement d = x_j - x_i at the nearest image (reading C4) and its
+   squared length.  For a pair across the periodic boundary of an axis the
+   coordinate nearer 0 is lifted by +L (one rounding, the same from both
+   sides), so d_ji = -d_ij exactly.  In a sheared box a pair across the y
+   boundary lifts the particle with the smaller y into the image above: y by
+   +L_y and x by delta + m L_x, where X1 = fl(x + delta) and m in {-2,..,1}
+   brings X1 nearest the other particle's x (decided from dx1 = fl(x_o - X1)
+   in FP32, again the same from both sides); x and z of such a pair use the
+   lifted coordinates, z the plain rule.  s (may be NULL) gets the shift of
+   x_j's image relative to x_i's image (the exact-arithmetic displacement is
+   x_j + s - x_i) and *sv (may be NULL) the x-velocity offset of x_j's image
+   relative to x_i's (v_ij = v_i - v_j - sv). */
+static float disp_geo(const float *xi, const float *xj, const geom_t *g, float d[3], double s[3],
+                      double *sv) {
+  int lift = 0; /* 1: x_i lifted into the image above, 2: x_j lifted */
+  if (g->le) {
+    const float ry = xj[1] - xi[1];
+    if (ry > 0.5f * g->L[1]) lift = 1;
+    else if (ry < -0.5f * g->L[1]) lift = 2;
+  }
+  if (sv) *sv = 0.0;
   for (int a = 0; a < 3; ++a) {
+    const float L = g->L[a];
+    double sh = 0.0;
+    if (lift && a < 2) {
+      const float *xl = lift == 1 ? xi : xj, *xo = lift == 1 ? xj : xi;
+      float X;
+      double shl; /* lifted coordinate and its exact shift */
+      if (a == 1) {
+        X = xl[1] + L;
+        shl = L;
+      } else {
+        const float X1 = xl[0] + g->delta;
+        const float dx1 = xo[0] - X1;
+        int m = 0;
+        if (dx1 > 0.5f * L) m = 1;
+        else if (dx1 < -0.5f * L) m = (dx1 + L < -0.5f * L) ? -2 : -1;
+        X = X1 + (float)m * L;
+        shl = (double)g->delta + (double)m * (double)L;
+      }
+      if (lift == 1) {
+        d[a] = xo[a] - X;
+        sh = -shl;
+      } else {
+        d[a] = X - xo[a];
+        sh = shl;
+      }
+      if (s) s[a] = sh;
+      continue;
+    }
     const float raw = xj[a] - xi[a];
-    const float half = 0.5f * L[a];
-    float sh = 0.0f;
+    const float half = 0.5f * L;
     if (raw > half) {          /* x_i near 0: lift x_i */
-      sh = -L[a];
-      const float xl = xi[a] + L[a];
+      sh = -L;
+      const float xl = xi[a] + L;
       d[a] = xj[a] - xl;
     } else if (raw < -half) {  /* x_j near 0: lift x_j */
-      sh = L[a];
-      const float xl = xj[a] + L[a];
+      sh = L;
+      const float xl = xj[a] + L;
       d[a] = xl - xi[a];
     } else {
       d[a] = raw;
     }
     if (s) s[a] = sh;
   }
+  if (sv && lift) *sv = lift == 2 ? (double)g->u : -(double)g->u;
   return fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
 }
 
@@ -248,9 +320,9 @@ static void cells_free(cells_t *c) {
   free(c->next);
 }
 
-static void cell_of(const cells_t *c, const orc_params *p, const float *x, int ci[3]) {
+static void cell_of(const cells_t *c, const float *box, const float *x, int ci[3]) {
   for (int a = 0; a < 3; ++a) {
-    int v = (int)floor((double)x[a] * c->n[a] / (double)p->box[a]);
+    int v = (int)floor((double)x[a] * c->n[a] / (double)box[a]);
     if (v < 0) v = 0;
     if (v >= c->n[a]) v = c->n[a] - 1;
     ci[a] = v;
@@ -258,36 +330,42 @@ static void cell_of(const cells_t *c, const orc_params *p, const float *x, int c
 }
 
 /* Collect all j != i with 0 < d2 < rcut2 into list (indices), returns count.
-   list must hold n entries. */
-static int neighbours(const cells_t *c, const orc_params *p, int n, const float *xf,
+   list must hold n entries.  In a sheared box a neighbour row across the y
+   boundary is searched over its whole x extent (its cells are displaced by
+   delta in x). */
+static int neighbours(const cells_t *c, const geom_t *g, int n, const float *xf,
                       int i, float rcut2, int *list, int *nzero) {
   int m = 0;
   float d[3];
   if (c->brute) {
     for (int j = 0; j < n; ++j) {
       if (j == i) continue;
-      const float d2 = disp_f32(xf + 3 * i, xf + 3 * j, p->box, d, NULL);
+      const float d2 = disp_geo(xf + 3 * i, xf + 3 * j, g, d, NULL, NULL);
       if (d2 == 0.0f) { if (nzero) ++*nzero; continue; }
       if (d2 < rcut2) list[m++] = j;
     }
     return m;
   }
   int ci[3];
-  cell_of(c, p, xf + 3 * i, ci);
+  cell_of(c, g->L, xf + 3 * i, ci);
   for (int dz = -1; dz <= 1; ++dz)
-    for (int dy = -1; dy <= 1; ++dy)
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int cx = (ci[0] + dx + c->n[0]) % c->n[0];
-        const int cy = (ci[1] + dy + c->n[1]) % c->n[1];
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int cyr = ci[1] + dy;
+      const int across = g->le && (cyr < 0 || cyr >= c->n[1]);
+      const int x0 = across ? 0 : -1, x1 = across ? c->n[0] - 1 : 1;
+      for (int dx = x0; dx <= x1; ++dx) {
+        const int cx = across ? dx : (ci[0] + dx + c->n[0]) % c->n[0];
+        const int cy = (cyr + c->n[1]) % c->n[1];
         const int cz = (ci[2] + dz + c->n[2]) % c->n[2];
         const long q = ((long)cz * c->n[1] + cy) * c->n[0] + cx;
         for (int j = c->head[q]; j >= 0; j = c->next[j]) {
           if (j == i) continue;
-          const float d2 = disp_f32(xf + 3 * i, xf + 3 * j, p->box, d, NULL);
+          const float d2 = disp_geo(xf + 3 * i, xf + 3 * j, g, d, NULL, NULL);
           if (d2 == 0.0f) { if (nzero) ++*nzero; continue; }
           if (d2 < rcut2) list[m++] = j;
         }
       }
+    }
   return m;
 }
 
@@ -516,9 +594,10 @@ static int32_t *make_body(const orc_sys *s, int n) {
    which = 0: rcut = rc, 1: rcut = rcc.  brute = 1 forces the O(N^2) scan.
    Writes up to cap pairs, returns the total count through *count and the
    number of coincident (d2 == 0) ordered pairs through *nzero. */
-void orc_pairs(const orc_sys *s, int64_t n, const float *xf, int which, int brute,
+void orc_pairs(const orc_sys *s, int64_t n, const float *xf, int which, int brute, uint32_t k,
                int64_t cap, int32_t *out, int64_t *count, int64_t *nzero) {
   const orc_params *p = &s->p;
+  const geom_t g = geom_at(p, k);
   const float rcut = which ? p->rcc : p->rc;
   const float rcut2 = rcut * rcut;
   cells_t c;
@@ -528,8 +607,8 @@ void orc_pairs(const orc_sys *s, int64_t n, const float *xf, int which, int brut
   int64_t m = 0;
   int nz = 0;
   for (int i = 0; i < n; ++i) {
-    const int k = neighbours(&c, p, (int)n, xf, i, rcut2, list, &nz);
-    for (int q = 0; q < k; ++q) {
+    const int cnt = neighbours(&c, &g, (int)n, xf, i, rcut2, list, &nz);
+    for (int q = 0; q < cnt; ++q) {
       const int j = list[q];
       if (j <= i) continue;
       if (m < cap) {
@@ -550,20 +629,34 @@ void orc_pairs(const orc_sys *s, int64_t n, const float *xf, int which, int brut
 static double wrap_delta(double d, double L) { return d - L * nearbyint(d / L); }
 
 /* Unwrapped coordinates of RBC r's vertices: breadth-first along bonds, each
-   bond taken at its nearest periodic image. */
-static void unwrap_rbc(const orc_sys *s, int r, const double *pos, double *u) {
+   bond taken at its nearest periodic image (in a sheared box a bond across
+   the y boundary takes the sheared image: x shifted by delta, and the
+   vertex's x velocity by u, which uvx [nv] accumulates). */
+static void unwrap_rbc(const orc_sys *s, const geom_t *g, int r, const double *pos, double *u,
+                       double *uvx) {
   const orc_mesh *M = &s->mesh[s->rbc_mesh[r]];
   const int64_t g0 = s->rbc_first[r];
   for (int q = 0; q < M->nv; ++q) {
     const int v = M->bfs[2 * q], par = M->bfs[2 * q + 1];
+    const double *xv = pos + 3 * (g0 + v);
     if (par < 0) {
-      for (int a = 0; a < 3; ++a) u[3 * v + a] = pos[3 * (g0 + v) + a];
-    } else {
-      for (int a = 0; a < 3; ++a)
-        u[3 * v + a] = u[3 * par + a] +
-                       wrap_delta(pos[3 * (g0 + v) + a] - pos[3 * (g0 + par) + a],
-                                  (double)s->p.box[a]);
+      for (int a = 0; a < 3; ++a) u[3 * v + a] = xv[a];
+      uvx[v] = 0.0;
+      continue;
     }
+    const double *xp = pos + 3 * (g0 + par);
+    int ny = 0; /* +1: v is taken in the image above its parent, -1: below */
+    if (g->le) {
+      const double dy = xv[1] - xp[1];
+      if (dy > 0.5 * g->L[1]) ny = -1;
+      else if (dy < -0.5 * g->L[1]) ny = 1;
+    }
+    const double shx = ny * (double)g->delta;
+    u[3 * v] = u[3 * par] + wrap_delta(xv[0] + shx - xp[0], (double)g->L[0]);
+    u[3 * v + 1] = u[3 * par + 1] + (xv[1] + ny * (double)g->L[1] - xp[1]);
+    if (!g->le) u[3 * v + 1] = u[3 * par + 1] + wrap_delta(xv[1] - xp[1], (double)g->L[1]);
+    u[3 * v + 2] = u[3 * par + 2] + wrap_delta(xv[2] - xp[2], (double)g->L[2]);
+    uvx[v] = uvx[par] + ny * (double)g->u;
   }
 }
 
@@ -575,6 +668,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
                     uint32_t k, double *F, double *energy, double *av, double *Fabs) {
   const orc_params *p = &s->p;
   const int terms = p->terms;
+  const geom_t g = geom_at(p, k);
   int err = 0;
   for (int r = 0; r < s->nrbc; ++r) {
     const orc_mesh *M = &s->mesh[s->rbc_mesh[r]];
@@ -582,9 +676,10 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
     const int64_t g0 = s->rbc_first[r];
     if (g0 < 0 || g0 + M->nv > n) return -1;
     double *u = (double *)malloc(sizeof(double) * 3 * M->nv);
+    double *uvx = (double *)malloc(sizeof(double) * M->nv);
     double *f = (double *)calloc(3 * M->nv, sizeof(double));
     double *fab = (double *)calloc(M->nv, sizeof(double));
-    unwrap_rbc(s, r, pos, u);
+    unwrap_rbc(s, &g, r, pos, u, uvx);
     const double *vv = vel + 3 * g0;
     /* bonds, Eqs. (13)-(16) */
     for (int e = 0; e < M->nedge; ++e) {
@@ -618,6 +713,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
       if (terms & T_BVISC) {
         double vab[3];
         sub3(vv + 3 * a, vv + 3 * b, vab);
+        vab[0] += uvx[a] - uvx[b];
         const double ve = dot3(vab, eab);
         for (int q = 0; q < 3; ++q) fa[q] += -mp->gamma_t * vab[q] - mp->gamma_c * ve * eab[q];
         fmag += mp->gamma_t * vnorm(vab) + mp->gamma_c * fabs(ve);
@@ -733,6 +829,7 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
       if (Fabs) Fabs[g0 + v] += fab[v];
     }
     free(u);
+    free(uvx);
     free(f);
     free(fab);
   }
@@ -764,6 +861,7 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
   const float rc2 = p->rc * p->rc, rcc2 = p->rcc * p->rcc;
   const float rmax2 = rc2 > rcc2 ? rc2 : rcc2;
   const double isdt = 1.0 / sqrt(p->dt);
+  const geom_t g = geom_at(p, k);
   int64_t nzero = 0;
 #pragma omp parallel reduction(+ : nzero)
   {
@@ -779,17 +877,18 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
       if (which && !which[i]) continue;
       if (flags[i] & FROZEN_BIT) continue;
       int nz = 0;
-      const int m = neighbours(&c, p, n, xf, i, rmax2, list, &nz);
+      const int m = neighbours(&c, &g, n, xf, i, rmax2, list, &nz);
       nzero += nz;
       const int ti = (int)(flags[i] & 0xffu);
       for (int q = 0; q < m; ++q) {
         const int j = list[q];
         const int tj = (int)(flags[j] & 0xffu);
-        float df[3], sh[3];
-        const float d2 = disp_f32(xf + 3 * i, xf + 3 * j, p->box, df, sh);
+        float df[3];
+        double sh[3], sv;
+        const float d2 = disp_geo(xf + 3 * i, xf + 3 * j, &g, df, sh, &sv);
         /* FP64 displacement x_j - x_i at the same periodic image */
         double d[3];
-        for (int a = 0; a < 3; ++a) d[a] = (pos[3 * j + a] + (double)sh[a]) - pos[3 * i + a];
+        for (int a = 0; a < 3; ++a) d[a] = (pos[3 * j + a] + sh[a]) - pos[3 * i + a];
         const double r = norm3(d);
         const double e[3] = {-d[0] / r, -d[1] / r, -d[2] / r}; /* e_ij, j -> i */
         if (d2 < rc2 && !(body[i] >= 0 && body[i] == body[j])) {
@@ -799,6 +898,7 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
           if (terms & T_DISS) {
             double vij[3];
             sub3(vel + 3 * i, vel + 3 * j, vij);
+            vij[0] -= sv; /* velocity of x_j's sheared image */
             fs += -p->gamma[ti * T + tj] * powp(w, p->s_exp) * dot3(e, vij);
           }
           if (terms & T_RAND) {
@@ -891,6 +991,7 @@ int orc_step(const orc_sys *s, int64_t n64, double *pos, double *vel, double *co
   const orc_params *p = &s->p;
   const int n = (int)n64, S = p->n_species;
   const double h = 0.5 * p->dt;
+  const geom_t g = geom_at(p, k); /* positions after the drift are at step k */
   for (int i = 0; i < n; ++i) {
     if (flags[i] & FROZEN_BIT) continue;
     for (int a = 0; a < 3; ++a) vel[3 * i + a] += h * F[3 * i + a];
@@ -905,6 +1006,20 @@ int orc_step(const orc_sys *s, int64_t n64, double *pos, double *vel, double *co
       else if (*x > L - w) { *x = 2 * (L - w) - *x; hit = 1; }
       if (hit)
         for (int q = 0; q < 3; ++q) vel[3 * i + q] = -vel[3 * i + q];
+    }
+    if (g.le) {
+      /* crossing the y boundary of a sheared box: into the image below or
+         above, x by -/+ delta and the x velocity by -/+ u */
+      double *x = pos + 3 * i;
+      if (x[1] >= p->box[1]) {
+        x[1] -= p->box[1];
+        x[0] -= (double)g.delta;
+        vel[3 * i] -= (double)g.u;
+      } else if (x[1] < 0) {
+        x[1] += p->box[1];
+        x[0] += (double)g.delta;
+        vel[3 * i] += (double)g.u;
+      }
     }
     for (int a = 0; a < 3; ++a) pos[3 * i + a] = wrap_pos(pos[3 * i + a], p->box[a]);
   }
@@ -949,6 +1064,7 @@ void orc_pair_normals_batch(const orc_params *p, uint32_t k, int64_t n, const ui
 }
 
 /* FP32 displacement of x_j seen from x_i (tests of the predicate rule) */
-float orc_disp(const orc_sys *s, const float *xi, const float *xj, float *d) {
-  return disp_f32(xi, xj, s->p.box, d, NULL);
+float orc_disp(const orc_sys *s, const float *xi, const float *xj, uint32_t k, float *d) {
+  const geom_t g = geom_at(&s->p, k);
+  return disp_geo(xi, xj, &g, d, NULL, NULL);
 }
