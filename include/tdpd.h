@@ -95,6 +95,12 @@ typedef struct {
   uint64_t seed;     /* Philox key */
   uint32_t box_id;   /* part of the Philox counter, < 2^24 */
   int32_t terms;     /* TDPD_TERM_* mask */
+  float shear_rate;  /* Lees-Edwards shear rate gamma (0: plain periodic box):
+                        the periodic image above in y sits
+                        delta_k = fl32(fmod(gamma L_y * (k dt), L_x)) further
+                        in x at step counter k and moves with
+                        u = fl32(gamma L_y) in x (FP64 products of the FP32
+                        values); not with walls (TDPD_ERR_UNSUPPORTED) */
 } tdpd_params;
 
 typedef struct {
@@ -114,7 +120,7 @@ typedef struct {
   float box[3];      /* box lengths */
   uint64_t seed;     /* Philox key */
   uint32_t box_id;   /* part of the Philox counter, < 2^24 */
-  float shear_rate;  /* must be 0 (sheared boxes are not supported) */
+  float shear_rate;  /* Lees-Edwards shear rate, as tdpd_params.shear_rate */
 } tdpd_box;
 
 typedef struct tdpd_sys tdpd_sys;

@@ -152,7 +152,6 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
                                                  uint32_t *__restrict__ cell_count,
                                                  uint32_t *__restrict__ kdev) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (integrate && kdev && i == 0) *kdev += 1u;  // step counter read by later kernels
   const bool active = i < n;
   uint32_t key = 0xffffffffu;
   if (active) {
@@ -183,6 +182,21 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
           vx = -vx;
           vy = -vy;
           vz = -vz;
+        }
+      }
+      if (B.shear != 0.f) {
+        // crossing the y boundary of a sheared box: into the image below
+        // (above), x by -delta (+delta), x velocity by -u (+u), with the
+        // offsets of this step's counter (the positions are at that time)
+        const LeOff le = le_offsets(B, *kdev, pc.dt);
+        if (y >= B.L[1]) {
+          y -= B.L[1];
+          x -= le.delta;
+          vx -= le.u;
+        } else if (y < 0.f) {
+          y += B.L[1];
+          x += le.delta;
+          vx += le.u;
         }
       }
       x = wrap_coord(x, B.L[0]);
@@ -367,11 +381,15 @@ void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint3
                      slot_of_gid, keys_sorted);
 }
 
-// F, Q are per particle in sorted order: F [n][3], Q [n][S]
+// F, Q are per particle in sorted order: F [n][3], Q [n][S].  The last
+// kernel of an evaluation: it advances the device step counter to the next
+// step's value (every kernel of this evaluation has read it already).
 __global__ void __launch_bounds__(256) k_postkick(PairConst pc, State s, float *__restrict__ F,
                                                   const float *__restrict__ Q, int64_t n,
-                                                  VertexMap vm, int integrate) {
+                                                  VertexMap vm, int integrate,
+                                                  uint32_t *__restrict__ kdev) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i == 0 && kdev) *kdev += 1u;
   if (i >= n) return;
   const uint32_t info = s.info[i];
   float fx = F[3 * i], fy = F[3 * i + 1], fz = F[3 * i + 2];
@@ -394,10 +412,10 @@ __global__ void __launch_bounds__(256) k_postkick(PairConst pc, State s, float *
 }
 
 void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,
-                     VertexMap vm, bool integrate, hipStream_t st) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_postkick, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, s, F, Q, n,
-                     vm, int(integrate));
+                     VertexMap vm, bool integrate, uint32_t *kdev, hipStream_t st) {
+  const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
+  hipLaunchKernelGGL(k_postkick, dim3(unsigned(nb)), dim3(256), 0, st, pc, s, F, Q, n, vm,
+                     int(integrate), kdev);
 }
 
 __global__ void k_set_counter(uint32_t *kdev, uint32_t k) { *kdev = k; }

@@ -23,12 +23,6 @@ __device__ __forceinline__ float3 crs(float3 a, float3 b) {
   return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ float dt3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ float3 rel(const BoxDev &B, float3 a, float3 o) {
-  return make_float3(min_image(a.x - o.x, B.L[0], B.invL[0]),
-                     min_image(a.y - o.y, B.L[1], B.invL[1]),
-                     min_image(a.z - o.z, B.L[2], B.invL[2]));
-}
-
 // gradient of the signed normal angle of triangles (a,b,c), (d,c,b) with
 // respect to the vertex in `role` (0..3 = a,b,c,d); also returns sin/cos.
 __device__ __forceinline__ float3 dihedral_grad(float3 a, float3 b, float3 c, float3 d, int role,
@@ -92,6 +86,9 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
   __syncthreads();
   auto P = [&](int v) { return make_float3(px[v], py[v], pz[v]); };
   const int terms = mc.terms;
+  // nearest image (sheared boxes: Lees-Edwards image of the step counter)
+  const LeOff le = le_offsets(B, k, mc.dt);
+  auto rel = [&](float3 a, float3 o) { return le_rel(B, a, o, le.delta, nullptr); };
 
   // ---- 1. K-Gather
   {
@@ -99,15 +96,15 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
                                   float(centroid[3 * r + 2]));
     double acc[5] = {0, 0, 0, 0, 0};
     for (int t = tid; t < M.ntri; t += kMemThreads) {
-      const float3 a = rel(B, P(M.tri[3 * t]), cf);
-      const float3 b = rel(B, P(M.tri[3 * t + 1]), cf);
-      const float3 c = rel(B, P(M.tri[3 * t + 2]), cf);
+      const float3 a = rel(P(M.tri[3 * t]), cf);
+      const float3 b = rel(P(M.tri[3 * t + 1]), cf);
+      const float3 c = rel(P(M.tri[3 * t + 2]), cf);
       const float3 nn = crs(sub(b, a), sub(c, a));
       acc[0] += double(0.5f * sqrtf(dt3(nn, nn)));
       acc[1] += double(dt3(a, crs(b, c)) * (1.f / 6.f));
     }
     for (int v = tid; v < nv; v += kMemThreads) {
-      const float3 a = rel(B, P(v), cf);
+      const float3 a = rel(P(v), cf);
       acc[2] += a.x;
       acc[3] += a.y;
       acc[4] += a.z;
@@ -138,7 +135,8 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
     const float cc = sqrtf(fmaxf(3.f * M.gamma_c - M.gamma_t, 0.f)) * (1.f / 3.f);
     for (int bnd = tid; bnd < M.nbond; bnd += kMemThreads) {
       const int2 ab = M.bond_ab[bnd];
-      const float3 d = rel(B, P(ab.y), P(ab.x));  // a -> b
+      int nyb = 0;  // b taken in the sheared image below (-1) or above (+1) a
+      const float3 d = le_rel(B, P(ab.y), P(ab.x), le.delta, &nyb);  // a -> b
       const float l = sqrtf(dt3(d, d));
       const float il = 1.f / l;
       float3 f = make_float3(0.f, 0.f, 0.f);
@@ -160,7 +158,8 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
       // e points from b to a (the paper's e_ij with i = a)
       const float3 e = make_float3(-d.x * il, -d.y * il, -d.z * il);
       if (terms & TDPD_TERM_BOND_VISCOUS) {
-        const float3 vr = make_float3(wx[ab.x] - wx[ab.y], wy[ab.x] - wy[ab.y], wz[ab.x] - wz[ab.y]);
+        const float3 vr = make_float3(wx[ab.x] - wx[ab.y] - float(nyb) * le.u, wy[ab.x] - wy[ab.y],
+                                      wz[ab.x] - wz[ab.y]);
         const float ve = dt3(vr, e);
         f.x += -M.gamma_t * vr.x - M.gamma_c * ve * e.x;
         f.y += -M.gamma_t * vr.y - M.gamma_c * ve * e.y;
@@ -224,8 +223,8 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
     if (terms & (TDPD_TERM_AREA | TDPD_TERM_VOLUME)) {
       for (int q = M.tri_off[v]; q < M.tri_off[v + 1]; ++q) {
         const int4 tr = M.tri_inc[q];  // (b, c, triangle, -), v first, counter-clockwise
-        const float3 rb = rel(B, P(tr.x), pv);
-        const float3 rc = rel(B, P(tr.y), pv);
+        const float3 rb = rel(P(tr.x), pv);
+        const float3 rc = rel(P(tr.y), pv);
         const float3 nn = crs(rb, rc);
         if (terms & TDPD_TERM_AREA) {
           const float nl = sqrtf(dt3(nn, nn));
@@ -251,10 +250,10 @@ __global__ void __launch_bounds__(kMemThreads) k_membrane(
       for (int q = M.dih_off[v]; q < M.dih_off[v + 1]; ++q) {
         const int4 D = M.dih_inc[q];
         const int role = M.dih_role[q];
-        const float3 a = role == 0 ? zero3 : rel(B, P(D.x), pv);
-        const float3 b = role == 1 ? zero3 : rel(B, P(D.y), pv);
-        const float3 c = role == 2 ? zero3 : rel(B, P(D.z), pv);
-        const float3 d = role == 3 ? zero3 : rel(B, P(D.w), pv);
+        const float3 a = role == 0 ? zero3 : rel(P(D.x), pv);
+        const float3 b = role == 1 ? zero3 : rel(P(D.y), pv);
+        const float3 c = role == 2 ? zero3 : rel(P(D.z), pv);
+        const float3 d = role == 3 ? zero3 : rel(P(D.w), pv);
         float sn, cs;
         const float3 g = dihedral_grad(a, b, c, d, role, sn, cs);
         const float coef = -M.kb * (sn * c0 - cs * s0);  // -kb sin(theta - theta0)

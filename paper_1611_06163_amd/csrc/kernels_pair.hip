@@ -73,6 +73,75 @@ __device__ __forceinline__ void pair_term(const PairConst &pc, const BoxDev &B, 
   }
 }
 
+
+// Visit every candidate j of a home particle at (xi, yi, zi) in local cell
+// (cx, cy, cz): fn(j, dx, dy, dz, d2, lift) with the FP32 displacement of
+// the pair rule (lift: 0 none, 1 the home, 2 the candidate is taken in the
+// sheared image above; the lifted particle's x velocity gains le.u).  In a
+// sheared box a neighbour row across the y boundary is displaced by delta:
+// its candidates come from the min(4, n_x) cells around x -/+ delta.
+template <class Fn>
+__device__ __forceinline__ void for_candidates(const BoxDev &B, const LeOff &le, const State &s,
+                                               const uint32_t *__restrict__ cell_start, int cx,
+                                               int cy, int cz, float xi, float yi, float zi,
+                                               Fn &&fn) {
+  const int nx = B.nc[0], ny = B.nc[1], nz = B.nc[2];
+  for (int dz = -1; dz <= 1; ++dz) {
+    int qz = cz + dz;
+    float sz = 0.f;
+    if (qz < 0) { qz += nz; sz = -B.L[2]; }
+    else if (qz >= nz) { qz -= nz; sz = B.L[2]; }
+    for (int dy = -1; dy <= 1; ++dy) {
+      int qy = cy + dy;
+      float sy = 0.f;
+      if (qy < 0) { qy += ny; sy = -B.L[1]; }
+      else if (qy >= ny) { qy -= ny; sy = B.L[1]; }
+      if (B.shear != 0.f && sy != 0.f) {
+        const int lift = sy > 0.f ? 2 : 1;  // candidate above the top, or home below the bottom
+        const float cshift = (lift == 2 ? -le.delta : le.delta) * B.inv_h[0];
+        const int clo = int(floorf(float(cx) + cshift)) - 1;
+        const int nw = nx < 4 ? nx : 4;
+        for (int t = 0; t < nw; ++t) {
+          const int qx = ((clo + t) % nx + nx) % nx;
+          const uint32_t c = B.cell_base + uint32_t((qz * ny + qy) * nx + qx);
+          for (uint32_t j = cell_start[c]; j < cell_start[c + 1]; ++j) {
+            const float xj = s.x[j], yj = s.y[j];
+            float dx, dy2;
+            if (lift == 2) {
+              dx = __fsub_rn(le_lift_x(xj, xi, le.delta, B.L[0]), xi);
+              dy2 = __fsub_rn(__fadd_rn(yj, B.L[1]), yi);
+            } else {
+              dx = __fsub_rn(xj, le_lift_x(xi, xj, le.delta, B.L[0]));
+              dy2 = __fsub_rn(yj, __fadd_rn(yi, B.L[1]));
+            }
+            const float dz2 = disp(s.z[j], sz, zi);
+            fn(j, dx, dy2, dz2, dist2(dx, dy2, dz2), lift);
+          }
+        }
+        continue;
+      }
+      for (int dx = -1; dx <= 1; ++dx) {
+        int qx = cx + dx;
+        float sx = 0.f;
+        if (qx < 0) { qx += nx; sx = -B.L[0]; }
+        else if (qx >= nx) { qx -= nx; sx = B.L[0]; }
+        const uint32_t c = B.cell_base + uint32_t((qz * ny + qy) * nx + qx);
+        for (uint32_t j = cell_start[c]; j < cell_start[c + 1]; ++j) {
+          const float ddx = disp(s.x[j], sx, xi);
+          const float ddy = disp(s.y[j], sy, yi);
+          const float ddz = disp(s.z[j], sz, zi);
+          fn(j, ddx, ddy, ddz, dist2(ddx, ddy, ddz), 0);
+        }
+      }
+    }
+  }
+}
+
+// home cells whose neighbour rows cross a sheared y boundary
+__device__ __forceinline__ bool le_row(const BoxDev &B, int cy) {
+  return B.shear != 0.f && (cy == 0 || cy == B.nc[1] - 1);
+}
+
 // ------------------------------------------------------------ simple kernel
 // One thread per home particle (sorted order), scanning the 27 neighbour
 // cells of its own cell in global memory.
@@ -82,12 +151,19 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
                                                      const uint32_t *__restrict__ cell_start,
                                                      int64_t n, const uint32_t *__restrict__ kdev,
                                                      float *__restrict__ F, float *__restrict__ Q,
-                                                     unsigned long long *nzero, uint32_t *err) {
+                                                     unsigned long long *nzero, uint32_t *err,
+                                                     int le_only) {
   const uint32_t k = *kdev;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int S = pc.n_species;
   const uint32_t infoi = s.info[i];
+  const BoxDev &B = boxes[info_box(infoi)];
+  const uint32_t key = cell_keys[i] - B.cell_base;
+  const int cx = int(key % uint32_t(B.nc[0]));
+  const int cy = int((key / uint32_t(B.nc[0])) % uint32_t(B.nc[1]));
+  const int cz = int(key / uint32_t(B.nc[0] * B.nc[1]));
+  if (le_only && !le_row(B, cy)) return;  // the tiled kernel has this particle
   PairAcc acc;
   acc.fx = acc.fy = acc.fz = 0.f;
   for (int sp = 0; sp < kMaxS; ++sp) acc.q[sp] = 0.f;
@@ -96,50 +172,25 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
     const float vxi = s.vx[i], vyi = s.vy[i], vzi = s.vz[i];
     float ci[kMaxS], cj[kMaxS];
     for (int sp = 0; sp < S; ++sp) ci[sp] = s.C[sp * n + i];
-    const BoxDev &B = boxes[info_box(infoi)];
     const uint32_t gi = s.gid[i] - B.gid_base;
     const int ti = info_type(infoi), bi = info_body(infoi);
-    const uint32_t key = cell_keys[i] - B.cell_base;
-    const int cx = int(key % uint32_t(B.nc[0]));
-    const int cy = int((key / uint32_t(B.nc[0])) % uint32_t(B.nc[1]));
-    const int cz = int(key / uint32_t(B.nc[0] * B.nc[1]));
+    const LeOff le = le_offsets(B, k, pc.dt);
     unsigned zero = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-      int qz = cz + dz;
-      float sz = 0.f;
-      if (qz < 0) { qz += B.nc[2]; sz = -B.L[2]; }
-      else if (qz >= B.nc[2]) { qz -= B.nc[2]; sz = B.L[2]; }
-      for (int dy = -1; dy <= 1; ++dy) {
-        int qy = cy + dy;
-        float sy = 0.f;
-        if (qy < 0) { qy += B.nc[1]; sy = -B.L[1]; }
-        else if (qy >= B.nc[1]) { qy -= B.nc[1]; sy = B.L[1]; }
-        for (int dx = -1; dx <= 1; ++dx) {
-          int qx = cx + dx;
-          float sx = 0.f;
-          if (qx < 0) { qx += B.nc[0]; sx = -B.L[0]; }
-          else if (qx >= B.nc[0]) { qx -= B.nc[0]; sx = B.L[0]; }
-          const uint32_t c = B.cell_base + uint32_t((qz * B.nc[1] + qy) * B.nc[0] + qx);
-          const uint32_t j0 = cell_start[c], j1 = cell_start[c + 1];
-          for (uint32_t j = j0; j < j1; ++j) {
-            const float ddx = disp(s.x[j], sx, xi);
-            const float ddy = disp(s.y[j], sy, yi);
-            const float ddz = disp(s.z[j], sz, zi);
-            const float d2 = dist2(ddx, ddy, ddz);
-            if (d2 == 0.f) {
-              if (j != uint32_t(i)) ++zero;
-              continue;
-            }
-            if (!(d2 < pc.rmax2)) continue;
-            const uint32_t infoj = s.info[j];
-            const int bj = info_body(infoj);
-            for (int sp = 0; sp < S; ++sp) cj[sp] = s.C[sp * n + j];
-            pair_term(pc, B, ddx, ddy, ddz, d2, vxi, vyi, vzi, s.vx[j], s.vy[j], s.vz[j], ci, cj, ti,
-                      info_type(infoj), bi >= 0 && bi == bj, gi, s.gid[j] - B.gid_base, k, acc);
-          }
-        }
+    for_candidates(B, le, s, cell_start, cx, cy, cz, xi, yi, zi,
+                   [&](uint32_t j, float ddx, float ddy, float ddz, float d2, int lift) {
+      if (d2 == 0.f) {
+        if (j != uint32_t(i)) ++zero;
+        return;
       }
-    }
+      if (!(d2 < pc.rmax2)) return;
+      const uint32_t infoj = s.info[j];
+      const int bj = info_body(infoj);
+      for (int sp = 0; sp < S; ++sp) cj[sp] = s.C[sp * n + j];
+      const float vxh = lift == 1 ? __fadd_rn(vxi, le.u) : vxi;
+      const float vxj = lift == 2 ? __fadd_rn(s.vx[j], le.u) : s.vx[j];
+      pair_term(pc, B, ddx, ddy, ddz, d2, vxh, vyi, vzi, vxj, s.vy[j], s.vz[j], ci, cj, ti,
+                info_type(infoj), bi >= 0 && bi == bj, gi, s.gid[j] - B.gid_base, k, acc);
+    });
     if (zero) atomicAdd(nzero, (unsigned long long)zero);
     if (pc.terms & TDPD_TERM_BODY_FORCE) {
       acc.fx += pc.body_force[0];
@@ -157,10 +208,10 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
 void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
                         const uint32_t *cell_keys, const uint32_t *cell_start, int64_t n,
                         const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
-                        uint32_t *err, hipStream_t st) {
+                        uint32_t *err, bool le_only, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_pair_simple, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, boxes, s,
-                     cell_keys, cell_start, n, kdev, F, Q, nzero, err);
+                     cell_keys, cell_start, n, kdev, F, Q, nzero, err, int(le_only));
 }
 
 // ------------------------------------------------------------ pair listing
@@ -168,7 +219,7 @@ __global__ void __launch_bounds__(256) k_pair_emit(PairConst pc, const BoxDev *_
                                                    State s,
                                                    const uint32_t *__restrict__ cell_keys,
                                                    const uint32_t *__restrict__ cell_start,
-                                                   int64_t n, float rcut2, int32_t *out,
+                                                   int64_t n, float rcut2, uint32_t k, int32_t *out,
                                                    int64_t cap, unsigned long long *count) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -179,46 +230,28 @@ __global__ void __launch_bounds__(256) k_pair_emit(PairConst pc, const BoxDev *_
   const int cx = int(key % uint32_t(B.nc[0]));
   const int cy = int((key / uint32_t(B.nc[0])) % uint32_t(B.nc[1]));
   const int cz = int(key / uint32_t(B.nc[0] * B.nc[1]));
-  for (int dz = -1; dz <= 1; ++dz) {
-    int qz = cz + dz;
-    float sz = 0.f;
-    if (qz < 0) { qz += B.nc[2]; sz = -B.L[2]; }
-    else if (qz >= B.nc[2]) { qz -= B.nc[2]; sz = B.L[2]; }
-    for (int dy = -1; dy <= 1; ++dy) {
-      int qy = cy + dy;
-      float sy = 0.f;
-      if (qy < 0) { qy += B.nc[1]; sy = -B.L[1]; }
-      else if (qy >= B.nc[1]) { qy -= B.nc[1]; sy = B.L[1]; }
-      for (int dx = -1; dx <= 1; ++dx) {
-        int qx = cx + dx;
-        float sx = 0.f;
-        if (qx < 0) { qx += B.nc[0]; sx = -B.L[0]; }
-        else if (qx >= B.nc[0]) { qx -= B.nc[0]; sx = B.L[0]; }
-        const uint32_t c = B.cell_base + uint32_t((qz * B.nc[1] + qy) * B.nc[0] + qx);
-        for (uint32_t j = cell_start[c]; j < cell_start[c + 1]; ++j) {
-          const uint32_t gj = s.gid[j];
-          if (gj <= gi) continue;
-          const float d2 = dist2(disp(s.x[j], sx, xi), disp(s.y[j], sy, yi), disp(s.z[j], sz, zi));
-          if (d2 > 0.f && d2 < rcut2) {
-            const unsigned long long pos = atomicAdd(count, 1ull);
-            if (int64_t(pos) < cap) {
-              out[2 * pos] = int32_t(gi);
-              out[2 * pos + 1] = int32_t(gj);
-            }
-          }
-        }
+  const LeOff le = le_offsets(B, k, pc.dt);
+  for_candidates(B, le, s, cell_start, cx, cy, cz, xi, yi, zi,
+                 [&](uint32_t j, float, float, float, float d2, int) {
+    const uint32_t gj = s.gid[j];
+    if (gj <= gi) return;
+    if (d2 > 0.f && d2 < rcut2) {
+      const unsigned long long pos = atomicAdd(count, 1ull);
+      if (int64_t(pos) < cap) {
+        out[2 * pos] = int32_t(gi);
+        out[2 * pos + 1] = int32_t(gj);
       }
     }
-  }
+  });
 }
 
 void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
                       const uint32_t *cell_keys, const uint32_t *cell_start, int64_t n,
-                      float rcut2, int32_t *out, int64_t cap, unsigned long long *count,
-                      hipStream_t st) {
+                      float rcut2, uint32_t k, int32_t *out, int64_t cap,
+                      unsigned long long *count, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_pair_emit, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, boxes, s,
-                     cell_keys, cell_start, n, rcut2, out, cap, count);
+                     cell_keys, cell_start, n, rcut2, k, out, cap, count);
 }
 
 }  // namespace tdpd

@@ -152,6 +152,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
   const int nx = B.nc[0], ny = B.nc[1], nz = B.nc[2];
   const int64_t lc = cell - B.cell_base;  // cell index inside its box
   const int cx = int(lc % nx), cy = int((lc / nx) % ny), cz = int(lc / (int64_t(nx) * ny));
+  // rows of a sheared box whose neighbours cross its y boundary go to the
+  // one-thread-per-particle kernel (their stencil is displaced by delta)
+  if (B.shear != 0.f && (cy == 0 || cy == ny - 1)) return;
   if (tid < 27) {
     const int dz = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dx = tid % 3 - 1;
     int qx = cx + dx, qy = cy + dy, qz = cz + dz;

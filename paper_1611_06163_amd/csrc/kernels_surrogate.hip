@@ -198,7 +198,8 @@ __global__ void __launch_bounds__(256) k_surr_features(SurrDev sd, const BoxDev 
                                                        const MeshDev *__restrict__ meshes, State s,
                                                        const uint32_t *__restrict__ slot_of_gid,
                                                        const double *__restrict__ av,
-                                                       int64_t nvert) {
+                                                       int64_t nvert,
+                                                       const uint32_t *__restrict__ kdev, float dt) {
   const int64_t vg = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (vg >= nvert) return;
   const int r = sd.vcell[vg];
@@ -213,11 +214,8 @@ __global__ void __launch_bounds__(256) k_surr_features(SurrDev sd, const BoxDev 
   const float3 pv = pos(v);
   const int r0 = M.ring_off[v], deg = M.ring_off[v + 1] - r0;
   float3 u[kRingMax];
-  for (int kk = 0; kk < deg && kk < kRingMax; ++kk) {
-    const float3 d = f3sub(pos(M.ring[r0 + kk]), pv);
-    u[kk] = make_float3(min_image(d.x, B.L[0], B.invL[0]), min_image(d.y, B.L[1], B.invL[1]),
-                        min_image(d.z, B.L[2], B.invL[2]));
-  }
+  const LeOff le = le_offsets(B, *kdev, dt);
+  for (int kk = 0; kk < deg && kk < kRingMax; ++kk) u[kk] = le_rel(B, pos(M.ring[r0 + kk]), pv, le.delta, nullptr);
   const int dg = deg < kRingMax ? deg : kRingMax;
   float3 nn = make_float3(0.f, 0.f, 0.f);
   for (int kk = 0; kk < dg; ++kk) {
@@ -260,10 +258,10 @@ __global__ void __launch_bounds__(256) k_surr_features(SurrDev sd, const BoxDev 
 
 void launch_surr_features(const SurrDev &sd, const BoxDev *boxes, const MeshDev *meshes, State s,
                           const uint32_t *slot_of_gid, const double *av, int64_t nvert,
-                          hipStream_t st) {
+                          const uint32_t *kdev, float dt, hipStream_t st) {
   if (nvert <= 0) return;
   hipLaunchKernelGGL(k_surr_features, dim3(unsigned((nvert + 255) / 256)), dim3(256), 0, st, sd,
-                     boxes, meshes, s, slot_of_gid, av, nvert);
+                     boxes, meshes, s, slot_of_gid, av, nvert, kdev, dt);
 }
 
 // Fs = s_F R^T y (global frame) for every vertex

@@ -18,8 +18,8 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
 
 // First half kick + drift + walls + wrap + cell key (one thread per particle).
 // With cell_count, vals gets the particle's unordered rank in its cell (the
-// counting binning); else vals = index (the radix binning).  With integrate
-// and kdev, the device step counter *kdev is incremented.
+// counting binning); else vals = index (the radix binning).  *kdev is the
+// counter of this evaluation (sheared boxes take its image offsets).
 void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
                     const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
                     uint32_t *cell_count, uint32_t *kdev, hipStream_t st);
@@ -40,14 +40,17 @@ void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
 void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
                     uint32_t *slot_of_gid, hipStream_t st);
 // Adds the membrane forces Fm (indexed by global vertex, see launch_membrane)
-// into F, then (integrate) the second half kick of mobile particles.
+// into F, then (integrate) the second half kick of mobile particles; ends
+// the evaluation by advancing the device step counter *kdev by one (the
+// kernels of an evaluation at counter k all read k; the next step reads
+// k + 1).
 struct VertexMap {
   const float *Fm;          // [nvert][3] or null
   const int64_t *rbc_first; // [nrbc]
   const int64_t *rbc_voff;  // [nrbc]
 };
 void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,
-                     VertexMap vm, bool integrate, hipStream_t st);
+                     VertexMap vm, bool integrate, uint32_t *kdev, hipStream_t st);
 // Sets *kdev = k.
 void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st);
 
@@ -57,7 +60,8 @@ void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st);
 void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
                         const uint32_t *cell_keys,
                         const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
-                        float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st);
+                        float *Q, unsigned long long *nzero, uint32_t *err, bool le_only,
+                        hipStream_t st);
 // Tile shape of the cell-tiled pair kernel: wavefronts per workgroup,
 // 64-candidate chunks per wavefront held in registers, workgroups per cell.
 struct PairTile {
@@ -75,8 +79,8 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
 // Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
 void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
                       const uint32_t *cell_keys,
-                      const uint32_t *cell_start, int64_t n, float rcut2, int32_t *out,
-                      int64_t cap, unsigned long long *count, hipStream_t st);
+                      const uint32_t *cell_start, int64_t n, float rcut2, uint32_t k,
+                      int32_t *out, int64_t cap, unsigned long long *count, hipStream_t st);
 
 // FP64 diagnostics in fixed order: [P0,P1,P2, sum v^2, n_mobile, C_0..C_{S-1}]
 void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hipStream_t st);
@@ -190,7 +194,7 @@ struct SurrDev {
 };
 void launch_surr_features(const SurrDev &sd, const BoxDev *boxes, const MeshDev *meshes, State s,
                           const uint32_t *slot_of_gid, const double *av, int64_t nvert,
-                          hipStream_t st);
+                          const uint32_t *kdev, float dt, hipStream_t st);
 void launch_surr_apply(const SurrDev &sd, int64_t nvert, hipStream_t st);
 void launch_surr_targets(const SurrDev &sd, float *T, int64_t nvert, hipStream_t st);
 void launch_surr_check(const SurrDev &sd, int nrbc, const uint32_t *kdev, int every,

@@ -64,6 +64,7 @@ struct HostBox {
   int64_t gid_base = 0, n = 0;
   uint64_t seed = 0;
   uint32_t box_id = 0;
+  float shear = 0.f;  // Lees-Edwards shear rate
 };
 
 struct tdpd_sys {
@@ -111,6 +112,7 @@ struct tdpd_sys {
   int64_t nvert = 0;
   size_t mem_lds = 0;  // dynamic LDS of the membrane kernel
   int pair_kernel = 1;  // 0: one thread per particle, 1: cell-tiled
+  bool any_shear = false;  // a box has Lees-Edwards boundaries
   PairTile tile{4, 2, 1};  // shape of the cell-tiled kernel
   int bin_mode = 0;     // 0: counting (one-digit stable) sort, 1: LSD radix sort
   bool use_graph = true;
@@ -249,8 +251,9 @@ static int check_common(const tdpd_params *p) {
 // Geometry of one box; fails if it holds fewer than 3 cells of edge
 // > max(rc, rcc) per axis.
 static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
-  if (in.box_id >= (1u << 24)) return TDPD_ERR_INVALID_ARG;
-  if (in.shear_rate != 0.f) return TDPD_ERR_UNSUPPORTED;
+  if (in.box_id >= (1u << 24) || !std::isfinite(in.shear_rate)) return TDPD_ERR_INVALID_ARG;
+  // sheared boundaries and frozen walls both act on the y faces
+  if (in.shear_rate != 0.f && p->wall_axis >= 0) return TDPD_ERR_UNSUPPORTED;
   const float rmax = std::max(p->rc, p->rcc);
   for (int a = 0; a < 3; ++a) {
     if (!(in.box[a] > 0.f)) return TDPD_ERR_INVALID_ARG;
@@ -263,6 +266,7 @@ static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
   b.ncell = int64_t(b.nc[0]) * b.nc[1] * b.nc[2];
   b.seed = in.seed;
   b.box_id = in.box_id;
+  b.shear = in.shear_rate;
   return TDPD_OK;
 }
 
@@ -284,6 +288,7 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
   s->user = user;
   s->S = p->n_species;
   s->boxes = std::move(boxes);
+  for (auto &b : s->boxes) s->any_shear = s->any_shear || b.shear != 0.f;
   s->ncell = 0;
   for (auto &b : s->boxes) {
     b.cell_base = s->ncell;
@@ -342,6 +347,7 @@ extern "C" int tdpd_create(const tdpd_params *p, void *hip_stream, tdpd_alloc_fn
   for (int a = 0; a < 3; ++a) in.box[a] = p->box[a];
   in.seed = p->seed;
   in.box_id = p->box_id;
+  in.shear_rate = p->shear_rate;
   std::vector<HostBox> boxes(1);
   if ((rc = make_box(p, in, boxes[0]))) return rc;
   return create_common(p, std::move(boxes), hip_stream, alloc, free_fn, user, out);
@@ -849,6 +855,7 @@ static int prepare(tdpd_sys *s) {
       D.seed_lo = uint32_t(H.seed & 0xffffffffu);
       D.seed_hi = uint32_t(H.seed >> 32);
       D.ctr3 = H.box_id << 8;
+      D.shear = H.shear;
     }
     if ((rc = upload(s, &s->d_boxes, bd))) return rc;
   }
@@ -867,6 +874,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
                  s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, st);
   if (n == 0) {
     s->phase_end(1, tb, st);
+    launch_postkick(s->pc, s->cur(), s->F, s->Q, 0, VertexMap{nullptr, nullptr, nullptr}, false,
+                    s->kdev, st);  // advances the counter
     return TDPD_OK;
   }
   if (s->bin_mode == 0) {
@@ -893,7 +902,7 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
       // steps, gated on the device counter) the plain bending + local-area
       // forces and the per-vertex fallback decision
       launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av,
-                           s->nvert, s->st2);
+                           s->nvert, s->kdev, s->pc.dt, s->st2);
       mlp_forward(s->surr_params, s->sd.X, s->nvert, s->surr_Ha, s->surr_Hb, s->sd.Y, s->st2);
       launch_surr_apply(s->sd, s->nvert, s->st2);
       MembraneConst ml = s->mc;
@@ -917,19 +926,23 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
   // one-thread-per-particle kernel; it also packs a slot into 26 bits
   const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
-  if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26))
+  if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26)) {
     launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
-                       s->Q,
-                       s->nzero, s->errw, st);
-  else
+                       s->Q, s->nzero, s->errw, false, st);
+  } else {
     (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, n, s->kdev,
                             s->F, s->Q, s->nzero, s->errw, s->tile, st);
+    // the boundary rows of sheared boxes (their stencil is displaced)
+    if (s->any_shear)
+      launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
+                         s->Q, s->nzero, s->errw, true, st);
+  }
   s->phase_end(0, tp, st);
   if (nrbc > 0) (void)hipStreamWaitEvent(st, s->ev_join, 0);
-  if (integrate || nrbc > 0) {
+  {
     const bool tk = s->phase_begin(3, st);
     VertexMap vm{nrbc > 0 ? s->Fm : nullptr, s->d_rbc_first, s->d_rbc_voff};
-    launch_postkick(s->pc, s->cur(), s->F, s->Q, n, vm, integrate, st);
+    launch_postkick(s->pc, s->cur(), s->F, s->Q, n, vm, integrate, s->kdev, st);
     s->phase_end(3, tk, st);
   }
   return TDPD_OK;
@@ -941,7 +954,8 @@ static int check_launch(tdpd_sys *s) {
   return TDPD_OK;
 }
 
-// Force evaluation at counter k without integration.
+// Force evaluation at counter k without integration (the device counter is
+// k + 1 afterwards, ready for the next step).
 static int evaluate_at(tdpd_sys *s, uint32_t k) {
   launch_set_counter(s->kdev, k, s->st);
   s->kdev_val = k;
@@ -985,9 +999,10 @@ extern "C" int tdpd_step(tdpd_sys *s, int32_t n_steps) {
   if (!s->forces_valid && (rc = evaluate_at(s, 0))) return rc;
   if (s->step + n_steps > 0xffffffffLL) return s->fail(TDPD_ERR_UNSUPPORTED, "step counter exhausted");
   if (n_steps == 0) return TDPD_OK;
-  // the first kick of step n increments the device counter to n
+  // step n reads counter n from the device; each evaluation's last kernel
+  // advances it (kdev_val is the counter of the last evaluation)
   if (s->kdev_val != uint32_t(s->step)) {
-    launch_set_counter(s->kdev, uint32_t(s->step), s->st);
+    launch_set_counter(s->kdev, uint32_t(s->step) + 1u, s->st);
     s->kdev_val = uint32_t(s->step);
   }
   const bool graphs = s->use_graph && s->timing_mask == 0 && s->n > 0;
@@ -1073,8 +1088,8 @@ extern "C" int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *
   int32_t *dout = dallocT<int32_t>(s, 2 * size_t(cap > 0 ? cap : 1));
   if (!dout) return s->fail(TDPD_ERR_OOM, "device allocation failed");
   HIPCHK(hipMemsetAsync(s->pair_count, 0, sizeof(unsigned long long), s->st));
-  launch_pair_emit(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, s->n, which ? s->pc.rcc2 : s->pc.rc2,
-                   dout, cap, s->pair_count, s->st);
+  launch_pair_emit(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, s->n,
+                   which ? s->pc.rcc2 : s->pc.rc2, s->kdev_val, dout, cap, s->pair_count, s->st);
   unsigned long long cnt = 0;
   hipError_t e = hipMemcpyAsync(&cnt, s->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -1272,7 +1287,7 @@ extern "C" int tdpd_load(tdpd_sys *s, const char *path) {
   for (size_t i = 0; i < regs.size(); ++i)
     if (regs[i].second)
       HIPCHK(hipMemcpy(regs[i].first, data[i].data(), regs[i].second, hipMemcpyHostToDevice));
-  launch_set_counter(s->kdev, h.kdev, s->st);
+  launch_set_counter(s->kdev, h.kdev + 1u, s->st);  // the next step's counter
   HIPCHK(hipStreamSynchronize(s->st));
   s->kdev_val = h.kdev;
   s->step = h.step;
@@ -1452,7 +1467,11 @@ extern "C" int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *o
   if ((rc = surr_alloc(s))) return rc;
   const int nrbc = int(s->rbc_mesh.size());
   const int64_t nv = s->nvert;
-  launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av, nv, s->st);
+  // the state is that of the last evaluation (counter kdev_val); the device
+  // counter already holds the next step's
+  launch_set_counter(s->kdev, s->kdev_val, s->st);
+  launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av, nv,
+                       s->kdev, s->pc.dt, s->st);
   MembraneConst ml = s->mc;
   ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
   ml.local_only = 1;
@@ -1462,6 +1481,7 @@ extern "C" int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *o
                   s->sd.Fp, s->errw, s->mem_lds, SurrUse{nullptr, nullptr}, s->st);
   // targets go through Fs, which the next step's surrogate pass rewrites
   launch_surr_targets(s->sd, s->sd.Fs, nv, s->st);
+  launch_set_counter(s->kdev, s->kdev_val + 1u, s->st);
   if ((rc = check_launch(s))) return rc;
   if (X) HIPCHK(hipMemcpyAsync(X, s->sd.X, sizeof(float) * kSurrIn * nv, hipMemcpyDeviceToHost, s->st));
   if (T) HIPCHK(hipMemcpyAsync(T, s->sd.Fs, sizeof(float) * 3 * nv, hipMemcpyDeviceToHost, s->st));

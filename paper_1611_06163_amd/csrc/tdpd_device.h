@@ -39,6 +39,7 @@ struct BoxDev {
   uint32_t cell_base, ncell;
   uint32_t gid_base;
   uint32_t seed_lo, seed_hi, ctr3;  // ctr3 = box_id << 8
+  float shear;                      // Lees-Edwards shear rate, 0 = plain periodic
 };
 
 // Parameters shared by every box, passed by value.
@@ -164,6 +165,63 @@ __device__ __forceinline__ int cell_coord(float x, float inv_h, int n) {
 
 __device__ __forceinline__ float min_image(float d, float L, float invL) {
   return d - L * rintf(d * invL);
+}
+
+// Lees-Edwards offsets of a sheared box at step counter k: the image above
+// in y sits delta to the right and moves with +u in x,
+//   u = fl32(shear L_y), delta = fl32(fmod(shear L_y * (k dt), L_x)),
+// products in FP64 from the FP32 parameters.
+struct LeOff {
+  float delta, u;
+};
+__device__ __forceinline__ LeOff le_offsets(const BoxDev &B, uint32_t k, float dt) {
+  LeOff o{0.f, 0.f};
+  if (B.shear != 0.f) {
+    const double a = double(B.shear) * double(B.L[1]);
+    const double b = double(k) * double(dt);
+    o.u = float(a);
+    const float d = float(fmod(a * b, double(B.L[0])));
+    o.delta = d >= B.L[0] ? 0.f : d;
+  }
+  return o;
+}
+
+// x of a particle lifted into the image above (y + L_y) of a sheared box,
+// nearest to the other particle's x: fl(fl(x + delta) + m L_x) with m in
+// {-2, .., 1} decided in FP32 from dx1 = fl(x_o - fl(x + delta)), the same
+// sequence whichever particle of the pair evaluates it.
+__device__ __forceinline__ float le_lift_x(float x, float xo, float delta, float Lx) {
+  const float X1 = __fadd_rn(x, delta);
+  const float dx1 = __fsub_rn(xo, X1);
+  float m = 0.f;
+  if (dx1 > 0.5f * Lx) m = 1.f;
+  else if (dx1 < -0.5f * Lx) m = (__fadd_rn(dx1, Lx) < -0.5f * Lx) ? -2.f : -1.f;
+  return __fadd_rn(X1, m * Lx);
+}
+
+// nearest-image difference a - o in a (possibly sheared) box; *ny gets -1
+// when a was taken in the image below o (+1 above), which shifts a's x
+// velocity by -u (+u)
+__device__ __forceinline__ float3 le_rel(const BoxDev &B, float3 a, float3 o, float delta,
+                                         int *ny) {
+  float dx = a.x - o.x, dy = a.y - o.y;
+  int s = 0;
+  if (B.shear != 0.f) {
+    if (dy > 0.5f * B.L[1]) {
+      dy -= B.L[1];
+      dx -= delta;
+      s = -1;
+    } else if (dy < -0.5f * B.L[1]) {
+      dy += B.L[1];
+      dx += delta;
+      s = 1;
+    }
+  } else {
+    dy = min_image(dy, B.L[1], B.invL[1]);
+  }
+  if (ny) *ny = s;
+  return make_float3(min_image(dx, B.L[0], B.invL[0]), dy,
+                     min_image(a.z - o.z, B.L[2], B.invL[2]));
 }
 
 }  // namespace tdpd

@@ -46,6 +46,7 @@ class tdpd_params(C.Structure):
         ("kappa", C.c_float * (MAX_SPECIES * MAX_TYPES * MAX_TYPES)),
         ("body_force", C.c_float * 3), ("wall_axis", C.c_int32), ("wall_w", C.c_float),
         ("seed", C.c_uint64), ("box_id", C.c_uint32), ("terms", C.c_int32),
+        ("shear_rate", C.c_float),
     ]
 
 
@@ -158,6 +159,7 @@ def params_from_config(cfg, terms=TERMS_ALL):
                 p.kappa[(s * T + i) * T + j] = cfg.kappa[s, i, j]
     p.wall_axis, p.wall_w = cfg.wall_axis, cfg.wall_w
     p.seed, p.box_id, p.terms = cfg.seed, cfg.box_id, terms
+    p.shear_rate = float(getattr(cfg, "shear_rate", 0.0))
     return p
 
 

@@ -47,11 +47,26 @@ def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL):
     dr / r_c with the pair's own noise draw xi; a particle is excluded when
     the sum over its pairs exceeds half of its tolerance tol * sum_j |F_ij|
     (ref = the oracle's evaluation)."""
-    p, _ = o.pairs(pos.astype(np.float32), 0)
+    p, _ = o.pairs(pos.astype(np.float32), 0, k=k)
     xi_ = pos[p[:, 0]].astype(np.float64)
     xj = pos[p[:, 1]].astype(np.float64)
     d = xj - xi_
     L = np.asarray(cfg.box)
+    shear = float(getattr(cfg, "shear_rate", 0.0))
+    le = np.zeros(len(p), bool)
+    if shear != 0.0:
+        # pairs across the sheared y boundary: the lower particle is lifted
+        # by +L_y and by delta + m L_x in x (two roundings of values < 2 L_x)
+        a = float(np.float32(shear)) * float(np.float32(L[1]))
+        delta = float(np.float32(np.fmod(a * (k * float(np.float32(cfg.dt))), float(np.float32(L[0])))))
+        le = np.abs(d[:, 1]) > 0.5 * L[1]
+        sgn = -np.sign(d[le, 1])
+        d[le, 1] += sgn * L[1]
+        d[le, 0] += sgn * delta
+        # the lower particle's lifted coordinates, before the x wrap
+        low = np.where((sgn < 0)[:, None], xi_[le], xj[le])
+        X1 = low[:, 0] + delta
+        Yl = low[:, 1] + L[1]
     shift = -L * np.round(d / L)
     d += shift
     r = np.linalg.norm(d, axis=1)
@@ -61,11 +76,21 @@ def near_cutoff_mask(o, cfg, pos, vel, ref, k, tol=TOL):
     # plain difference rounds to half an ulp of d
     lifted = np.minimum(xi_, xj) + L
     dd = np.where(shift != 0.0, 0.5 * _ulp32(lifted), 0.5 * _ulp32(d))
+    if le.any():
+        # y: fl(y + L_y); x: fl(x + delta), then fl(X1 + m L_x) when m != 0;
+        # the differences round to half an ulp of d
+        m_ne0 = shift[le, 0] != 0.0
+        dd[le, 0] = (0.5 * _ulp32(X1) + np.where(m_ne0, 0.5 * _ulp32(2.0 * L[0]), 0.0)
+                     + 0.5 * _ulp32(d[le, 0]))
+        dd[le, 1] = 0.5 * _ulp32(Yl) + 0.5 * _ulp32(d[le, 1])
     dr = (np.abs(d) / r[:, None] * dd).sum(axis=1) + 3.0 * _ulp32(r)
     w = np.maximum(1.0 - r / cfg.rc, 1e-12)
     s = cfg.s_exp
     xi = np.abs(pair_normals_batch(cfg, k, p[:, 0], p[:, 1], 0)[:, 0])
-    vij = np.linalg.norm(vel[p[:, 0]].astype(np.float64) - vel[p[:, 1]], axis=1)
+    vv = vel[p[:, 0]].astype(np.float64) - vel[p[:, 1]]
+    if shear != 0.0:
+        vv[le, 0] -= sgn * a  # the lifted particle's image moves with +u
+    vij = np.linalg.norm(vv, axis=1)
     sig = float(np.max(cfg.sigma))
     gam = float(np.max(cfg.gamma))
     sens = (sig * xi * (0.5 * s) * w ** (0.5 * s - 1.0) / np.sqrt(cfg.dt)
