@@ -137,11 +137,6 @@ __device__ __forceinline__ void for_candidates(const BoxDev &B, const LeOff &le,
   }
 }
 
-// home cells whose neighbour rows cross a sheared y boundary
-__device__ __forceinline__ bool le_row(const BoxDev &B, int cy) {
-  return B.shear != 0.f && (cy == 0 || cy == B.nc[1] - 1);
-}
-
 // ------------------------------------------------------------ simple kernel
 // One thread per home particle (sorted order), scanning the 27 neighbour
 // cells of its own cell in global memory.
@@ -151,8 +146,7 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
                                                      const uint32_t *__restrict__ cell_start,
                                                      int64_t n, const uint32_t *__restrict__ kdev,
                                                      float *__restrict__ F, float *__restrict__ Q,
-                                                     unsigned long long *nzero, uint32_t *err,
-                                                     int le_only) {
+                                                     unsigned long long *nzero, uint32_t *err) {
   const uint32_t k = *kdev;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -163,7 +157,6 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
   const int cx = int(key % uint32_t(B.nc[0]));
   const int cy = int((key / uint32_t(B.nc[0])) % uint32_t(B.nc[1]));
   const int cz = int(key / uint32_t(B.nc[0] * B.nc[1]));
-  if (le_only && !le_row(B, cy)) return;  // the tiled kernel has this particle
   PairAcc acc;
   acc.fx = acc.fy = acc.fz = 0.f;
   for (int sp = 0; sp < kMaxS; ++sp) acc.q[sp] = 0.f;
@@ -208,10 +201,10 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
 void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
                         const uint32_t *cell_keys, const uint32_t *cell_start, int64_t n,
                         const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
-                        uint32_t *err, bool le_only, hipStream_t st) {
+                        uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_pair_simple, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, boxes, s,
-                     cell_keys, cell_start, n, kdev, F, Q, nzero, err, int(le_only));
+                     cell_keys, cell_start, n, kdev, F, Q, nzero, err);
 }
 
 // ------------------------------------------------------------ pair listing

@@ -16,6 +16,8 @@
 //     then summed per home particle in ring order.
 // Each wave keeps its own partial sums; they are added in wave order at the
 // end, so the summation order, and the result, does not depend on timing.
+#include <type_traits>
+
 #include "launch.h"
 #include "pair_terms.h"
 
@@ -24,6 +26,8 @@ namespace tdpd {
 constexpr int kRing = 128;     // per-wave force-pair ring (>= 63 + 64)
 constexpr int kHome = 64;      // home particles per pass
 constexpr uint32_t kJBits = 26;
+// 27 neighbour cells; a sheared boundary row replaces its 3 cells by up to 4
+constexpr int kMaxSeg = 30;
 static_assert((kRing & (kRing - 1)) == 0 && kRing >= 127, "ring");
 
 template <int CTRL, int ROWS>
@@ -72,21 +76,24 @@ struct TiledShared {
   float fa[W][3][kHome];
   float qa[W][NS][kHome];
   float kap[NS][kMaxT * kMaxT];
-  int seg_start[27];
-  int seg_pref[28];
-  float seg_sh[27][3];
+  int seg_start[kMaxSeg];
+  int seg_pref[kMaxSeg + 1];
+  float seg_sh[kMaxSeg][3];
+  int8_t seg_le[kMaxSeg];  // 0 plain, 1 home lifted, 2 candidate lifted (sheared image)
+  int8_t seg_m[kMaxSeg];   // multiple of L_x added to the lifted x
   float rd[W][3][kRing];   // ring: displacement, overwritten by the force
   uint32_t rij[W][kRing];  // ring: home index << kJBits | candidate slot
+  uint8_t rl[W][kRing];    // ring: sheared-image code of the pair (sheared rows only)
 };
 
 // Evaluate ring entries [head, head+m) of wave w (m <= 64) and add them to
 // that wave's home accumulators; every home index forms one run in the
 // window (entries are appended in home order and the ring is flushed at the
 // end of each register block), so run leaders never collide.
-template <int NS, int W>
+template <int NS, int W, bool LE>
 __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B, const State &s,
                                            TiledShared<NS, W> &sh, int w, uint32_t head, int m,
-                                           uint32_t k) {
+                                           uint32_t k, float le_u) {
   const int lane = threadIdx.x & 63;
   const uint32_t e = (head + lane) & (kRing - 1);
   int hi_i = -1;
@@ -96,8 +103,14 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
     hi_i = int(wd >> kJBits);
     const uint32_t j = wd & ((1u << kJBits) - 1);
     const float dx = sh.rd[w][0][e], dy = sh.rd[w][1][e], dz = sh.rd[w][2][e];
-    const float3 f = force_term(pc, B, dx, dy, dz, dist2(dx, dy, dz), sh.hvx[hi_i], sh.hvy[hi_i],
-                                sh.hvz[hi_i], s.vx[j], s.vy[j], s.vz[j], info_type(sh.hinfo[hi_i]),
+    float vxi = sh.hvx[hi_i], vxj = s.vx[j];
+    if constexpr (LE) {  // the lifted particle's image moves with +u in x
+      const int code = sh.rl[w][e];
+      if (code == 1) vxi = __fadd_rn(vxi, le_u);
+      if (code == 2) vxj = __fadd_rn(vxj, le_u);
+    }
+    const float3 f = force_term(pc, B, dx, dy, dz, dist2(dx, dy, dz), vxi, sh.hvy[hi_i],
+                                sh.hvz[hi_i], vxj, s.vy[j], s.vz[j], info_type(sh.hinfo[hi_i]),
                                 info_type(s.info[j]), sh.hgid[hi_i] - B.gid_base,
                                 s.gid[j] - B.gid_base, k);
     sh.rd[w][0][e] = f.x;
@@ -125,7 +138,7 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
   wave_sync();
 }
 
-template <int NS, int W, int KC>
+template <int NS, int W, int KC, bool SH>
 __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
                                                             const BoxDev *__restrict__ boxes,
                                                             State s,
@@ -152,31 +165,63 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
   const int nx = B.nc[0], ny = B.nc[1], nz = B.nc[2];
   const int64_t lc = cell - B.cell_base;  // cell index inside its box
   const int cx = int(lc % nx), cy = int((lc / nx) % ny), cz = int(lc / (int64_t(nx) * ny));
-  // rows of a sheared box whose neighbours cross its y boundary go to the
-  // one-thread-per-particle kernel (their stencil is displaced by delta)
-  if (B.shear != 0.f && (cy == 0 || cy == ny - 1)) return;
-  if (tid < 27) {
-    const int dz = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dx = tid % 3 - 1;
-    int qx = cx + dx, qy = cy + dy, qz = cz + dz;
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    if (qx < 0) { qx += nx; sx = -B.L[0]; } else if (qx >= nx) { qx -= nx; sx = B.L[0]; }
-    if (qy < 0) { qy += ny; sy = -B.L[1]; } else if (qy >= ny) { qy -= ny; sy = B.L[1]; }
-    if (qz < 0) { qz += nz; sz = -B.L[2]; } else if (qz >= nz) { qz -= nz; sz = B.L[2]; }
-    const int64_t q = B.cell_base + (int64_t(qz) * ny + qy) * nx + qx;
-    const uint32_t a0 = cell_start[q], a1 = cell_start[q + 1];
-    sh.seg_start[tid] = int(a0);
-    sh.seg_pref[tid + 1] = int(a1 - a0);  // counts, prefixed below
-    sh.seg_sh[tid][0] = sx;
-    sh.seg_sh[tid][1] = sy;
-    sh.seg_sh[tid][2] = sz;
+  // In a sheared box the neighbour row across the y boundary is displaced
+  // by delta in x: its candidates come from the min(4, n_x) cells around
+  // x -/+ delta, taken in the sheared image (the candidate lifted when the
+  // home is in the top row, the home lifted when it is in the bottom row).
+  const bool lecell = SH && B.shear != 0.f && (cy == 0 || cy == ny - 1);
+  const LeOff le = le_offsets(B, k, pc.dt);
+  const int nw = nx < 4 ? nx : 4;
+  // 9 (dz, dy) groups of 3 cells, or nw for a group across the sheared boundary
+  auto gsize = [&](int g) {
+    const int qy = cy + (g % 3) - 1;
+    return (lecell && (qy < 0 || qy >= ny)) ? nw : 3;
+  };
+  if (tid < 36) {
+    const int g = tid / 4, t = tid % 4;
+    const int dz = g / 3 - 1, dy = g % 3 - 1;
+    int off = 0;
+    for (int q = 0; q < g; ++q) off += gsize(q);
+    if (t < gsize(g)) {
+      const int seg = off + t;
+      int qy = cy + dy, qz = cz + dz, qx;
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+      int code = 0, mm = 0;
+      if (qz < 0) { qz += nz; sz = -B.L[2]; } else if (qz >= nz) { qz -= nz; sz = B.L[2]; }
+      const bool cross = qy < 0 || qy >= ny;
+      if (qy < 0) { qy += ny; sy = -B.L[1]; } else if (qy >= ny) { qy -= ny; sy = B.L[1]; }
+      if (lecell && cross) {
+        code = sy > 0.f ? 2 : 1;
+        const float cshift = (code == 2 ? -le.delta : le.delta) * B.inv_h[0];
+        const int qu = int(floorf(float(cx) + cshift)) - 1 + t;  // unwrapped cell index
+        qx = ((qu % nx) + nx) % nx;
+        const int wraps = (qu - qx) / nx;                        // floor(qu / nx)
+        mm = code == 2 ? wraps : -wraps;
+        sy = 0.f;  // the y lift is part of the sheared image
+      } else {
+        qx = cx + t - 1;
+        if (qx < 0) { qx += nx; sx = -B.L[0]; } else if (qx >= nx) { qx -= nx; sx = B.L[0]; }
+      }
+      const int64_t q = B.cell_base + (int64_t(qz) * ny + qy) * nx + qx;
+      const uint32_t a0 = cell_start[q], a1 = cell_start[q + 1];
+      sh.seg_start[seg] = int(a0);
+      sh.seg_pref[seg + 1] = int(a1 - a0);  // counts, prefixed below
+      sh.seg_sh[seg][0] = sx;
+      sh.seg_sh[seg][1] = sy;
+      sh.seg_sh[seg][2] = sz;
+      sh.seg_le[seg] = int8_t(code);
+      sh.seg_m[seg] = int8_t(mm);
+    }
   }
+  int nseg = 0;
+  for (int g = 0; g < 9; ++g) nseg += gsize(g);
   __syncthreads();
   if (tid == 0) {
     sh.seg_pref[0] = 0;
-    for (int q = 1; q <= 27; ++q) sh.seg_pref[q] += sh.seg_pref[q - 1];
+    for (int q = 1; q <= nseg; ++q) sh.seg_pref[q] += sh.seg_pref[q - 1];
   }
   __syncthreads();
-  const int ncand = sh.seg_pref[27];
+  const int ncand = sh.seg_pref[nseg];
   const int nchunk = (ncand + 63) / 64;
   const int my_chunks = nchunk > w ? (nchunk - w + W - 1) / W : 0;
   // this workgroup's share of the cell's home particles
@@ -212,11 +257,16 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
     const float Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
     const bool fick = (pc.terms & TDPD_TERM_FLUX_FICK) != 0;
 
+    // the register blocks, specialised for cells with a sheared boundary row
+    auto blocks = [&](auto le_tag) {
+      constexpr bool LE = decltype(le_tag)::value;
     for (int cb = 0; cb < my_chunks; cb += KC) {
       // candidate coordinates, lifted by +L where the candidate sits across
       // the high boundary; lift[kk] bit a says the home coordinate is lifted
-      // instead (candidate across the low boundary).  Empty lanes hold NaN,
-      // which fails every distance test.
+      // instead (candidate across the low boundary).  In a sheared row the
+      // candidate takes its sheared image (code 2), or bits 3-4 select the
+      // home's sheared x for the segment's multiple m (code 1, bits 5-6 =
+      // m + 2).  Empty lanes hold NaN, which fails every distance test.
       float cxs[KC], cys[KC], czs[KC], cc[KC][NS];
       uint32_t cj[KC], lift[KC];
       int ct[KC], cbody[KC];
@@ -232,7 +282,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
 #pragma unroll
         for (int sp = 0; sp < NS; ++sp) cc[kk][sp] = 0.f;
         if ((cb + kk) < my_chunks && t < ncand) {
-          int lo = 0, hi = 26;  // largest segment whose prefix is <= t
+          int lo = 0, hi = nseg - 1;  // largest segment whose prefix is <= t
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (sh.seg_pref[mid] <= t) lo = mid;
@@ -245,6 +295,17 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
           cys[kk] = sy > 0.f ? __fadd_rn(s.y[j], sy) : s.y[j];
           czs[kk] = sz > 0.f ? __fadd_rn(s.z[j], sz) : s.z[j];
           lift[kk] = (sx < 0.f ? 1u : 0u) | (sy < 0.f ? 2u : 0u) | (sz < 0.f ? 4u : 0u);
+          if constexpr (LE) {
+            const int code = sh.seg_le[lo];
+            const float mL = float(sh.seg_m[lo]) * Lx;
+            if (code == 2) {  // candidate in the sheared image above
+              cxs[kk] = __fadd_rn(__fadd_rn(s.x[j], le.delta), mL);
+              cys[kk] = __fadd_rn(s.y[j], Ly);
+              lift[kk] |= 2u << 3;
+            } else if (code == 1) {  // home in the sheared image above
+              lift[kk] |= 2u | (1u << 3) | (uint32_t(sh.seg_m[lo] + 2) << 5);
+            }
+          }
           const uint32_t inf = s.info[j];
           ct[kk] = info_type(inf);
           cbody[kk] = info_body(inf);
@@ -259,6 +320,12 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
         if (info_frozen(infoi)) continue;  // frozen particles get F = Q = 0
         const float xi = sh.hx[i], yi = sh.hy[i], zi = sh.hz[i];
         const float xil = __fadd_rn(xi, Lx), yil = __fadd_rn(yi, Ly), zil = __fadd_rn(zi, Lz);
+        float xm[4] = {0.f, 0.f, 0.f, 0.f};  // home x in the sheared image, m = -2..1
+        if constexpr (LE) {
+          const float X1 = __fadd_rn(xi, le.delta);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) xm[c] = __fadd_rn(X1, float(c - 2) * Lx);
+        }
         // pair forces skip partners of the home's own cell body; body ids
         // are >= -2 (-1 none, -2 empty lane), so -3 matches nothing
         const int bq = info_body(infoi) >= 0 ? info_body(infoi) : -3;
@@ -273,7 +340,14 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
           if (cb + kk >= my_chunks) break;  // wave-uniform
-          const float dx = __fsub_rn(cxs[kk], (lift[kk] & 1u) ? xil : xi);
+          float hx = (lift[kk] & 1u) ? xil : xi;
+          if constexpr (LE) {
+            if (((lift[kk] >> 3) & 3u) == 1u) {
+              const uint32_t c = (lift[kk] >> 5) & 3u;
+              hx = (c & 2u) ? ((c & 1u) ? xm[3] : xm[2]) : ((c & 1u) ? xm[1] : xm[0]);
+            }
+          }
+          const float dx = __fsub_rn(cxs[kk], hx);
           const float dy = __fsub_rn(cys[kk], (lift[kk] & 2u) ? yil : yi);
           const float dz = __fsub_rn(czs[kk], (lift[kk] & 4u) ? zil : zi);
           const float d2 = dist2(dx, dy, dz);
@@ -296,10 +370,11 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
               sh.rd[w][1][e] = dy;
               sh.rd[w][2][e] = dz;
               sh.rij[w][e] = hbits | cj[kk];
+              if constexpr (LE) sh.rl[w][e] = uint8_t((lift[kk] >> 3) & 3u);
             }
             tail = uniform(tail + uint32_t(__popcll(fm)));
             if (tail - head >= 64) {
-              flush_ring<NS, W>(pc, B, s, sh, w, head, 64, k);
+              flush_ring<NS, W, LE>(pc, B, s, sh, w, head, 64, k, le.u);
               head = uniform(head + 64u);
             }
           }
@@ -316,9 +391,17 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       // ever mixes entries of two blocks (which would repeat home indices)
       while (tail != head) {
         const int m = int(min(tail - head, 64u));
-        flush_ring<NS, W>(pc, B, s, sh, w, head, m, k);
+        flush_ring<NS, W, LE>(pc, B, s, sh, w, head, m, k, le.u);
         head = uniform(head + uint32_t(m));
       }
+    }
+    };
+    // (SH: a build of the kernel that has the sheared-row variant at all)
+    if constexpr (SH) {
+      if (lecell) blocks(std::true_type{});
+      else blocks(std::false_type{});
+    } else {
+      blocks(std::false_type{});
     }
     __syncthreads();
     if (tid < nh) {
@@ -361,20 +444,27 @@ template <int NS, int W, int KC>
 static void launch_shape(const PairConst &pc, const BoxDev *boxes, State s,
                          const uint32_t *cell_start, int64_t ncell, int split, int64_t n,
                          const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
-                         uint32_t *err, hipStream_t st) {
+                         uint32_t *err, bool sheared, hipStream_t st) {
   const int64_t per_xcd = (ncell * split + 7) / 8;
-  hipLaunchKernelGGL((k_pair_tiled<NS, W, KC>), dim3(unsigned(per_xcd * 8)), dim3(64 * W), 0, st, pc,
-                     boxes, s, cell_start, ncell, split, per_xcd, n, kdev, F, Q, nzero, err);
+  const dim3 grid(unsigned(per_xcd * 8)), block(64 * W);
+  // the sheared-row variant costs registers: only systems with a sheared box get it
+  if (sheared)
+    hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, true>), grid, block, 0, st, pc, boxes, s,
+                       cell_start, ncell, split, per_xcd, n, kdev, F, Q, nzero, err);
+  else
+    hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, false>), grid, block, 0, st, pc, boxes, s,
+                       cell_start, ncell, split, per_xcd, n, kdev, F, Q, nzero, err);
 }
 
 template <int NS>
 static bool launch_ns(const PairConst &pc, const BoxDev *boxes, State s, const uint32_t *cell_start,
                       int64_t ncell, int64_t n, const uint32_t *kdev, float *F, float *Q,
-                      unsigned long long *nzero, uint32_t *err, const PairTile &t, hipStream_t st) {
+                      unsigned long long *nzero, uint32_t *err, const PairTile &t,
+                      bool sheared, hipStream_t st) {
 #define TDPD_SHAPE(W, KC)                                                                    \
   if (t.waves == W && t.chunks == KC) {                                                      \
     launch_shape<NS, W, KC>(pc, boxes, s, cell_start, ncell, t.split, n, kdev, F, Q, nzero, err, \
-                            st);                                                             \
+                            sheared, st);                                                    \
     return true;                                                                             \
   }
   TDPD_SHAPE(4, 2)
@@ -395,16 +485,16 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
                        const uint32_t *cell_start, int64_t ncell,
                        int64_t n, const uint32_t *kdev, float *F, float *Q,
                        unsigned long long *nzero, uint32_t *err, const PairTile &tile,
-                       hipStream_t st) {
+                       bool sheared, hipStream_t st) {
   if (n <= 0 || ncell <= 0) return true;
   if (tile.split < 1 || tile.split > 8) return false;
   if (pc.n_species <= 1)
-    return launch_ns<1>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
+    return launch_ns<1>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
   if (pc.n_species == 2)
-    return launch_ns<2>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
+    return launch_ns<2>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
   if (pc.n_species <= 4)
-    return launch_ns<4>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
-  return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, st);
+    return launch_ns<4>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
+  return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
 }
 
 }  // namespace tdpd

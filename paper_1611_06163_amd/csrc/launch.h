@@ -60,8 +60,7 @@ void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st);
 void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
                         const uint32_t *cell_keys,
                         const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
-                        float *Q, unsigned long long *nzero, uint32_t *err, bool le_only,
-                        hipStream_t st);
+                        float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st);
 // Tile shape of the cell-tiled pair kernel: wavefronts per workgroup,
 // 64-candidate chunks per wavefront held in registers, workgroups per cell.
 struct PairTile {
@@ -69,13 +68,13 @@ struct PairTile {
 };
 extern const PairTile kPairTiles[];  // the shapes the kernel is built for
 extern const int kNumPairTiles;
-// Pair forces and fluxes, cell-tiled kernel.  Returns false for a shape
-// that is not built.
+// Pair forces and fluxes, cell-tiled kernel (sheared: some box has
+// Lees-Edwards boundaries).  Returns false for a shape that is not built.
 bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
                        const uint32_t *cell_start, int64_t ncell,
                        int64_t n, const uint32_t *kdev, float *F, float *Q,
                        unsigned long long *nzero, uint32_t *err, const PairTile &tile,
-                       hipStream_t st);
+                       bool sheared, hipStream_t st);
 // Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
 void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
                       const uint32_t *cell_keys,

@@ -928,14 +928,10 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
   if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26)) {
     launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
-                       s->Q, s->nzero, s->errw, false, st);
+                       s->Q, s->nzero, s->errw, st);
   } else {
     (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, n, s->kdev,
-                            s->F, s->Q, s->nzero, s->errw, s->tile, st);
-    // the boundary rows of sheared boxes (their stencil is displaced)
-    if (s->any_shear)
-      launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
-                         s->Q, s->nzero, s->errw, true, st);
+                            s->F, s->Q, s->nzero, s->errw, s->tile, s->any_shear, st);
   }
   s->phase_end(0, tp, st);
   if (nrbc > 0) (void)hipStreamWaitEvent(st, s->ev_join, 0);
@@ -1359,7 +1355,7 @@ extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
       const PairTile &t = kPairTiles[i];
       auto launch = [&]() {
         (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, s->n,
-                                s->kdev, s->F, s->Q, s->nzero, s->errw, t, s->st);
+                                s->kdev, s->F, s->Q, s->nzero, s->errw, t, s->any_shear, s->st);
       };
       launch();  // warm-up
       (void)hipEventRecord(e0, s->st);
