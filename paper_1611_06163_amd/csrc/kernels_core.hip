@@ -252,18 +252,30 @@ void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const flo
 // same as a stable sort's and does not depend on atomic ordering.
 constexpr int kCellTile = 4 * kScanThreads;  // cells per scan tile
 
-// Inclusive scan of one value per thread over the block (1024 threads).
+// Inclusive scan of one value per thread over the block (1024 threads):
+// shuffle scans inside each wavefront, then a scan of the 16 wavefront
+// totals (sh holds at least 16 words).
 __device__ __forceinline__ uint32_t block_scan_incl(uint32_t v, uint32_t *sh) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const uint32_t u = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += u;
-    __syncthreads();
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = uint32_t(__shfl_up(int(v), off));
+    if (lane >= off) v += u;
   }
-  return sh[t];
+  __syncthreads();  // sh may still be read by the caller's previous scan
+  if (lane == 63) sh[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    uint32_t tw = lane < kScanThreads / 64 ? sh[lane] : 0u;
+#pragma unroll
+    for (int off = 1; off < kScanThreads / 64; off <<= 1) {
+      const uint32_t u = uint32_t(__shfl_up(int(tw), off));
+      if (lane >= off) tw += u;
+    }
+    if (lane < kScanThreads / 64) sh[lane] = tw;
+  }
+  __syncthreads();
+  return v + (w > 0 ? sh[w - 1] : 0u);
 }
 
 // Sum of the cell counts of each tile of kCellTile cells.
@@ -296,7 +308,7 @@ __global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restric
   uint32_t pre = 0;
   for (int64_t q = t; q < int64_t(blockIdx.x); q += kScanThreads) pre += tile_sum[q];
   (void)block_scan_incl(pre, sh);
-  const uint32_t base = sh[kScanThreads - 1];
+  const uint32_t base = sh[kScanThreads / 64 - 1];  // the block total
   __syncthreads();
   // coalesced load of the tile, then four consecutive cells per thread
 #pragma unroll
@@ -370,8 +382,9 @@ void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint3
                          uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
                          uint32_t *keys_sorted, hipStream_t st) {
   const int64_t nt = count_scan_tiles(ncell);
-  hipLaunchKernelGGL(k_count_tiles, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count, ncell,
-                     tile_sum);
+  if (nt > 1)  // one tile needs no tile prefix
+    hipLaunchKernelGGL(k_count_tiles, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count,
+                       ncell, tile_sum);
   hipLaunchKernelGGL(k_count_scan, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count, ncell,
                      tile_sum, cell_start);
   if (n <= 0) return;

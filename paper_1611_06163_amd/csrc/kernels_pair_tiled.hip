@@ -314,12 +314,26 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
             if (sp < S) cc[kk][sp] = s.C[sp * n + j];
         }
       }
+      // chunks without any lifted coordinate (all of an interior cell's)
+      // take the plain difference without lane selects
+      bool lifted[KC];
+      bool blk_lifted = false;
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        lifted[kk] = ballot(lift[kk] != 0u) != 0ull;
+        blk_lifted = blk_lifted || lifted[kk];
+      }
 
       for (int i = 0; i < nh; ++i) {
         const uint32_t infoi = sh.hinfo[i];
         if (info_frozen(infoi)) continue;  // frozen particles get F = Q = 0
         const float xi = sh.hx[i], yi = sh.hy[i], zi = sh.hz[i];
-        const float xil = __fadd_rn(xi, Lx), yil = __fadd_rn(yi, Ly), zil = __fadd_rn(zi, Lz);
+        float xil = xi, yil = yi, zil = zi;
+        if (blk_lifted) {
+          xil = __fadd_rn(xi, Lx);
+          yil = __fadd_rn(yi, Ly);
+          zil = __fadd_rn(zi, Lz);
+        }
         float xm[4] = {0.f, 0.f, 0.f, 0.f};  // home x in the sheared image, m = -2..1
         if constexpr (LE) {
           const float X1 = __fadd_rn(xi, le.delta);
@@ -340,16 +354,23 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk) {
           if (cb + kk >= my_chunks) break;  // wave-uniform
-          float hx = (lift[kk] & 1u) ? xil : xi;
-          if constexpr (LE) {
-            if (((lift[kk] >> 3) & 3u) == 1u) {
-              const uint32_t c = (lift[kk] >> 5) & 3u;
-              hx = (c & 2u) ? ((c & 1u) ? xm[3] : xm[2]) : ((c & 1u) ? xm[1] : xm[0]);
+          float dx, dy, dz;
+          if (!lifted[kk]) {
+            dx = __fsub_rn(cxs[kk], xi);
+            dy = __fsub_rn(cys[kk], yi);
+            dz = __fsub_rn(czs[kk], zi);
+          } else {
+            float hx = (lift[kk] & 1u) ? xil : xi;
+            if constexpr (LE) {
+              if (((lift[kk] >> 3) & 3u) == 1u) {
+                const uint32_t c = (lift[kk] >> 5) & 3u;
+                hx = (c & 2u) ? ((c & 1u) ? xm[3] : xm[2]) : ((c & 1u) ? xm[1] : xm[0]);
+              }
             }
+            dx = __fsub_rn(cxs[kk], hx);
+            dy = __fsub_rn(cys[kk], (lift[kk] & 2u) ? yil : yi);
+            dz = __fsub_rn(czs[kk], (lift[kk] & 4u) ? zil : zi);
           }
-          const float dx = __fsub_rn(cxs[kk], hx);
-          const float dy = __fsub_rn(cys[kk], (lift[kk] & 2u) ? yil : yi);
-          const float dz = __fsub_rn(czs[kk], (lift[kk] & 4u) ? zil : zi);
           const float d2 = dist2(dx, dy, dz);
           if (ballot(d2 == 0.f)) {  // the home itself, or a coincident particle
             const uint32_t self = uint32_t(hb + i);
