@@ -148,3 +148,25 @@ def test_walls_reflect_and_frozen_stay_put():
     assert np.all((y >= cfg.wall_w) & (y <= 32 - cfg.wall_w))
     assert np.array_equal(st["pos"][frozen], cfg.pos[frozen].astype(np.float64))
     assert np.all(st["vel"][frozen] == 0)
+
+
+def test_membrane_thermostat_recovers_kT():
+    """An isolated cell with only its membrane terms: the bond viscosity
+    (Eq. 15) and its random partner (Eq. 16, reading C13) form a thermostat,
+    so the kinetic temperature of the vertices (centre-of-mass motion
+    removed) relaxes to kT.  Checks the normalisation of the random bond
+    force against the dissipative one."""
+    MEM = TERM["bond"] | TERM["bvisc"] | TERM["brand"] | TERM["area"] | TERM["vol"] | TERM["bend"]
+    cfg = I._suspension("isolated_cell", (20.0, 20.0, 20.0), 0.0, 1, 21, n_species=1,
+                        permeability=(1.0,))
+    assert cfg.n == cfg.mesh_xyz.shape[0]
+    o = Oracle(cfg, terms=MEM)
+    st = o.init_state()
+    kts = []
+    for k in range(1, 3001):
+        o.step(st, k)
+        if k > 600 and k % 10 == 0:
+            kts.append(o.diag(st["vel"], st["conc"])["kT"])
+    kt = float(np.mean(kts))
+    print("membrane thermostat kT", kt, flush=True)
+    assert abs(kt - cfg.kT) < 0.03 * cfg.kT
