@@ -228,9 +228,12 @@ int tdpd_load(tdpd_sys *s, const char *path);
 
 /* Tile shape of the cell-tiled pair kernel: wavefronts per workgroup (2 or
    4), 64-candidate chunks per wavefront held in registers (1-4), workgroups
-   per cell (1-4).  Every shape gives a valid result; summation order, and
-   so the last bits, depend on the shape, and results are bit-for-bit
-   reproducible for a fixed shape.  tdpd_autotune times every built shape on
+   per cell (1-4), and filter (1: candidates of the 27-cell stencil farther
+   than max(r_c, r_cc) from the home cell's box are dropped before the pair
+   tests, for stencils of up to 768 candidates; 0: the whole stencil is
+   tested).  Every shape gives a valid result; summation order, and so the
+   last bits, depend on the shape, and results are bit-for-bit reproducible
+   for a fixed shape.  tdpd_autotune times every built shape on
    the system's current state (reps launches each, HIP events on the
    system's stream), keeps the fastest and re-evaluates the forces with it.
    With cache_path (may be NULL) it first looks for a line written for the
@@ -242,8 +245,9 @@ int tdpd_load(tdpd_sys *s, const char *path);
    These calls are not part of the paper's method: they choose among
    equivalent evaluation orders of Eqs. (2)-(10). */
 int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps, double *best_ms);
-int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split);
-int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split);
+int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split, int32_t filter);
+int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split,
+                  int32_t *filter);
 
 /* ---------------------------------------------------------------------
    Membrane surrogate.  Not part of the paper's method: a learned stand-in

@@ -28,7 +28,11 @@ constexpr int kHome = 64;      // home particles per pass
 constexpr uint32_t kJBits = 26;
 // 27 neighbour cells; a sheared boundary row replaces its 3 cells by up to 4
 constexpr int kMaxSeg = 30;
+// candidates of a cell that can reach it are kept in an LDS list (up to
+// kMaxList; larger stencils use the raw candidate order)
+constexpr int kMaxList = 768;
 static_assert((kRing & (kRing - 1)) == 0 && kRing >= 127, "ring");
+static_assert(kMaxList <= 1024 && kMaxSeg <= 64, "list entries: 6-bit segment, 10-bit offset");
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp(float v) {
@@ -68,7 +72,7 @@ __device__ __forceinline__ uint32_t lane_slot(uint64_t m, uint32_t tail) {
          uint32_t(kRing - 1);
 }
 
-template <int NS, int W>
+template <int NS, int W, bool SH>
 struct TiledShared {
   float hx[kHome], hy[kHome], hz[kHome], hvx[kHome], hvy[kHome], hvz[kHome];
   float hc[NS][kHome];
@@ -78,21 +82,24 @@ struct TiledShared {
   float kap[NS][kMaxT * kMaxT];
   int seg_start[kMaxSeg];
   int seg_pref[kMaxSeg + 1];
-  float seg_sh[kMaxSeg][3];
+  int8_t seg_sg[kMaxSeg][4];  // periodic image per axis: -1, 0 or +1 box length
   int8_t seg_le[kMaxSeg];  // 0 plain, 1 home lifted, 2 candidate lifted (sheared image)
   int8_t seg_m[kMaxSeg];   // multiple of L_x added to the lifted x
   float rd[W][3][kRing];   // ring: displacement, overwritten by the force
   uint32_t rij[W][kRing];  // ring: home index << kJBits | candidate slot
-  uint8_t rl[W][kRing];    // ring: sheared-image code of the pair (sheared rows only)
+  uint8_t rl[SH ? W : 1][kRing];  // ring: sheared-image code of the pair (sheared rows only)
+  uint16_t list[kMaxList];  // kept candidates: segment << 10 | offset in the segment
+  int list_cnt[kMaxList / 64];
+  int list_pref[kMaxList / 64 + 1];
 };
 
 // Evaluate ring entries [head, head+m) of wave w (m <= 64) and add them to
 // that wave's home accumulators; every home index forms one run in the
 // window (entries are appended in home order and the ring is flushed at the
 // end of each register block), so run leaders never collide.
-template <int NS, int W, bool LE>
+template <int NS, int W, bool LE, typename Shm>
 __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B, const State &s,
-                                           TiledShared<NS, W> &sh, int w, uint32_t head, int m,
+                                           Shm &sh, int w, uint32_t head, int m,
                                            uint32_t k, float le_u) {
   const int lane = threadIdx.x & 63;
   const uint32_t e = (head + lane) & (kRing - 1);
@@ -143,14 +150,14 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
                                                             const BoxDev *__restrict__ boxes,
                                                             State s,
                                                             const uint32_t *__restrict__ cell_start,
-                                                            int64_t ncell, int split,
+                                                            int64_t ncell, int split, int filter,
                                                             int64_t per_xcd, int64_t n,
                                                             const uint32_t *__restrict__ kdev,
                                                             float *__restrict__ F,
                                                             float *__restrict__ Q,
                                                             unsigned long long *nzero,
                                                             uint32_t *err) {
-  __shared__ TiledShared<NS, W> sh;
+  __shared__ TiledShared<NS, W, SH> sh;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t k = *kdev;  // random-number step counter
   // consecutive workgroups go to different XCDs; give each XCD a contiguous
@@ -206,9 +213,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       const uint32_t a0 = cell_start[q], a1 = cell_start[q + 1];
       sh.seg_start[seg] = int(a0);
       sh.seg_pref[seg + 1] = int(a1 - a0);  // counts, prefixed below
-      sh.seg_sh[seg][0] = sx;
-      sh.seg_sh[seg][1] = sy;
-      sh.seg_sh[seg][2] = sz;
+      sh.seg_sg[seg][0] = int8_t(sx > 0.f ? 1 : (sx < 0.f ? -1 : 0));
+      sh.seg_sg[seg][1] = int8_t(sy > 0.f ? 1 : (sy < 0.f ? -1 : 0));
+      sh.seg_sg[seg][2] = int8_t(sz > 0.f ? 1 : (sz < 0.f ? -1 : 0));
       sh.seg_le[seg] = int8_t(code);
       sh.seg_m[seg] = int8_t(mm);
     }
@@ -221,7 +228,79 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
     for (int q = 1; q <= nseg; ++q) sh.seg_pref[q] += sh.seg_pref[q - 1];
   }
   __syncthreads();
-  const int ncand = sh.seg_pref[nseg];
+  const int nraw = sh.seg_pref[nseg];
+  // Keep only candidates within r_max of the home cell's box (with cells of
+  // edge r_max, about a quarter of the 27 cells' volume lies farther from
+  // every point of the cell).  The test is a conservative superset filter
+  // (margins of 1e-3 cell edges); the exact pair rule is applied per home
+  // below.  Kept candidates stay in raw order (per-chunk ballots, then an
+  // exclusive scan of the chunk counts), so the lane of a candidate, and
+  // with it every summation order, does not depend on timing.
+  const bool use_list = filter != 0 && nraw <= kMaxList;
+  int ncand = nraw, nlist = 0;
+  if (use_list) {
+    const float hx = B.L[0] / float(nx), hy = B.L[1] / float(ny), hz = B.L[2] / float(nz);
+    const float lox = (float(cx) - 1e-3f) * hx, hix = (float(cx) + 1.001f) * hx;
+    const float loy = (float(cy) - 1e-3f) * hy, hiy = (float(cy) + 1.001f) * hy;
+    const float loz = (float(cz) - 1e-3f) * hz, hiz = (float(cz) + 1.001f) * hz;
+    const float reach = sqrtf(pc.rmax2) * 1.0002f + 1e-3f * fmaxf(hx, fmaxf(hy, hz));
+    const float reach2 = reach * reach;
+    const int nrc = (nraw + 63) / 64;
+    for (int c = w; c < nrc; c += W) {
+      const int t = c * 64 + lane;
+      bool keep = false;
+      uint32_t ent = 0;
+      if (t < nraw) {
+        int lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sh.seg_pref[mid] <= t) lo = mid;
+          else hi = mid - 1;
+        }
+        const uint32_t j = uint32_t(sh.seg_start[lo] + (t - sh.seg_pref[lo]));
+        ent = (uint32_t(lo) << 10) | uint32_t(t - sh.seg_pref[lo]);
+        // candidate position in the home cell's frame (approximate)
+        float px = s.x[j] + float(sh.seg_sg[lo][0]) * B.L[0],
+              py = s.y[j] + float(sh.seg_sg[lo][1]) * B.L[1],
+              pz = s.z[j] + float(sh.seg_sg[lo][2]) * B.L[2];
+        if (SH && lecell) {
+          const float mL = float(sh.seg_m[lo]) * B.L[0];
+          if (sh.seg_le[lo] == 2) {
+            px = s.x[j] + le.delta + mL;
+            py = s.y[j] + B.L[1];
+          } else if (sh.seg_le[lo] == 1) {
+            px = s.x[j] - le.delta - mL;
+            py = s.y[j] - B.L[1];
+          }
+        }
+        const float ex = fmaxf(fmaxf(lox - px, px - hix), 0.f);
+        const float ey = fmaxf(fmaxf(loy - py, py - hiy), 0.f);
+        const float ez = fmaxf(fmaxf(loz - pz, pz - hiz), 0.f);
+        keep = ex * ex + ey * ey + ez * ez < reach2;
+      }
+      const uint64_t m = ballot(keep);
+      if (lane == 0) sh.list_cnt[c] = __popcll(m);
+      if (keep)
+        sh.list[c * 64 + int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)))] = ent;
+    }
+    __syncthreads();
+    // exclusive prefix of the per-chunk counts: kept candidate t lives in
+    // chunk c (list_pref[c] <= t < list_pref[c + 1]) at c * 64 + t - list_pref[c]
+    if (w == 0) {
+      int v = lane < nrc ? sh.list_cnt[lane] : 0;
+#pragma unroll
+      for (int o = 1; o < kMaxList / 64; o <<= 1) {
+        const int u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+      }
+      if (lane < nrc) sh.list_pref[lane + 1] = v;
+      if (lane == 0) sh.list_pref[0] = 0;
+    }
+    __syncthreads();
+    ncand = sh.list_pref[nrc];
+    nlist = nrc;
+  }
   const int nchunk = (ncand + 63) / 64;
   const int my_chunks = nchunk > w ? (nchunk - w + W - 1) / W : 0;
   // this workgroup's share of the cell's home particles
@@ -282,19 +361,34 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
 #pragma unroll
         for (int sp = 0; sp < NS; ++sp) cc[kk][sp] = 0.f;
         if ((cb + kk) < my_chunks && t < ncand) {
-          int lo = 0, hi = nseg - 1;  // largest segment whose prefix is <= t
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sh.seg_pref[mid] <= t) lo = mid;
-            else hi = mid - 1;
+          int lo;
+          uint32_t j;
+          if (use_list) {
+            int c = 0, chi = nlist - 1;  // chunk of the list holding t
+            while (c < chi) {
+              const int mid = (c + chi + 1) >> 1;
+              if (sh.list_pref[mid] <= t) c = mid;
+              else chi = mid - 1;
+            }
+            const uint32_t ent = sh.list[c * 64 + t - sh.list_pref[c]];
+            lo = int(ent >> 10);
+            j = uint32_t(sh.seg_start[lo]) + (ent & 1023u);
+          } else {
+            lo = 0;  // largest segment whose prefix is <= t
+            int hi = nseg - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (sh.seg_pref[mid] <= t) lo = mid;
+              else hi = mid - 1;
+            }
+            j = uint32_t(sh.seg_start[lo] + (t - sh.seg_pref[lo]));
           }
-          const uint32_t j = uint32_t(sh.seg_start[lo] + (t - sh.seg_pref[lo]));
           cj[kk] = j;
-          const float sx = sh.seg_sh[lo][0], sy = sh.seg_sh[lo][1], sz = sh.seg_sh[lo][2];
-          cxs[kk] = sx > 0.f ? __fadd_rn(s.x[j], sx) : s.x[j];
-          cys[kk] = sy > 0.f ? __fadd_rn(s.y[j], sy) : s.y[j];
-          czs[kk] = sz > 0.f ? __fadd_rn(s.z[j], sz) : s.z[j];
-          lift[kk] = (sx < 0.f ? 1u : 0u) | (sy < 0.f ? 2u : 0u) | (sz < 0.f ? 4u : 0u);
+          const int gx = sh.seg_sg[lo][0], gy = sh.seg_sg[lo][1], gz = sh.seg_sg[lo][2];
+          cxs[kk] = gx > 0 ? __fadd_rn(s.x[j], Lx) : s.x[j];
+          cys[kk] = gy > 0 ? __fadd_rn(s.y[j], Ly) : s.y[j];
+          czs[kk] = gz > 0 ? __fadd_rn(s.z[j], Lz) : s.z[j];
+          lift[kk] = (gx < 0 ? 1u : 0u) | (gy < 0 ? 2u : 0u) | (gz < 0 ? 4u : 0u);
           if constexpr (LE) {
             const int code = sh.seg_le[lo];
             const float mL = float(sh.seg_m[lo]) * Lx;
@@ -314,8 +408,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
             if (sp < S) cc[kk][sp] = s.C[sp * n + j];
         }
       }
-      // chunks without any lifted coordinate (all of an interior cell's)
-      // take the plain difference without lane selects
+      // chunks without any lifted coordinate take the plain difference
       bool lifted[KC];
       bool blk_lifted = false;
 #pragma unroll
@@ -324,12 +417,16 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
         blk_lifted = blk_lifted || lifted[kk];
       }
 
+      // the home loop, built twice: blocks without any lifted lane (all of
+      // an interior cell's) take the plain differences with no lane selects
+      auto homes = [&](auto lift_tag) {
+        constexpr bool LB = decltype(lift_tag)::value;
       for (int i = 0; i < nh; ++i) {
         const uint32_t infoi = sh.hinfo[i];
         if (info_frozen(infoi)) continue;  // frozen particles get F = Q = 0
         const float xi = sh.hx[i], yi = sh.hy[i], zi = sh.hz[i];
         float xil = xi, yil = yi, zil = zi;
-        if (blk_lifted) {
+        if constexpr (LB) {
           xil = __fadd_rn(xi, Lx);
           yil = __fadd_rn(yi, Ly);
           zil = __fadd_rn(zi, Lz);
@@ -355,7 +452,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
         for (int kk = 0; kk < KC; ++kk) {
           if (cb + kk >= my_chunks) break;  // wave-uniform
           float dx, dy, dz;
-          if (!lifted[kk]) {
+          if (!LB || !lifted[kk]) {
             dx = __fsub_rn(cxs[kk], xi);
             dy = __fsub_rn(cys[kk], yi);
             dz = __fsub_rn(czs[kk], zi);
@@ -408,6 +505,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
           }
         }
       }
+      };
+      if (LE || blk_lifted) homes(std::true_type{});
+      else homes(std::false_type{});
       // end of the register block: empty the ring so that no flush window
       // ever mixes entries of two blocks (which would repeat home indices)
       while (tail != head) {
@@ -463,7 +563,8 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
 
 template <int NS, int W, int KC>
 static void launch_shape(const PairConst &pc, const BoxDev *boxes, State s,
-                         const uint32_t *cell_start, int64_t ncell, int split, int64_t n,
+                         const uint32_t *cell_start, int64_t ncell, int split, int filter,
+                         int64_t n,
                          const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
                          uint32_t *err, bool sheared, hipStream_t st) {
   const int64_t per_xcd = (ncell * split + 7) / 8;
@@ -471,10 +572,10 @@ static void launch_shape(const PairConst &pc, const BoxDev *boxes, State s,
   // the sheared-row variant costs registers: only systems with a sheared box get it
   if (sheared)
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, true>), grid, block, 0, st, pc, boxes, s,
-                       cell_start, ncell, split, per_xcd, n, kdev, F, Q, nzero, err);
+                       cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err);
   else
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, false>), grid, block, 0, st, pc, boxes, s,
-                       cell_start, ncell, split, per_xcd, n, kdev, F, Q, nzero, err);
+                       cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err);
 }
 
 template <int NS>
@@ -484,8 +585,8 @@ static bool launch_ns(const PairConst &pc, const BoxDev *boxes, State s, const u
                       bool sheared, hipStream_t st) {
 #define TDPD_SHAPE(W, KC)                                                                    \
   if (t.waves == W && t.chunks == KC) {                                                      \
-    launch_shape<NS, W, KC>(pc, boxes, s, cell_start, ncell, t.split, n, kdev, F, Q, nzero, err, \
-                            sheared, st);                                                    \
+    launch_shape<NS, W, KC>(pc, boxes, s, cell_start, ncell, t.split, t.filter, n, kdev, F, Q, \
+                            nzero, err, sheared, st);                                        \
     return true;                                                                             \
   }
   TDPD_SHAPE(4, 2)
@@ -498,8 +599,12 @@ static bool launch_ns(const PairConst &pc, const BoxDev *boxes, State s, const u
   return false;
 }
 
-const PairTile kPairTiles[] = {{4, 2, 1}, {4, 1, 1}, {4, 3, 1}, {2, 2, 1}, {2, 3, 1}, {2, 4, 1},
-                               {4, 2, 2}, {4, 1, 2}, {2, 2, 2}, {2, 3, 2}, {2, 2, 4}, {4, 1, 4}};
+// (each shape is built with and without the stencil filter)
+const PairTile kPairTiles[] = {
+    {4, 2, 1, 1}, {4, 1, 1, 1}, {4, 3, 1, 1}, {2, 2, 1, 1}, {2, 3, 1, 1}, {2, 4, 1, 1},
+    {4, 2, 2, 1}, {4, 1, 2, 1}, {2, 2, 2, 1}, {2, 3, 2, 1}, {2, 2, 4, 1}, {4, 1, 4, 1},
+    {4, 2, 1, 0}, {4, 1, 1, 0}, {4, 3, 1, 0}, {2, 2, 1, 0}, {2, 3, 1, 0}, {2, 4, 1, 0},
+    {4, 2, 2, 0}, {4, 1, 2, 0}, {2, 2, 2, 0}, {2, 3, 2, 0}, {2, 2, 4, 0}, {4, 1, 4, 0}};
 const int kNumPairTiles = int(sizeof(kPairTiles) / sizeof(kPairTiles[0]));
 
 bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
@@ -508,7 +613,7 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
                        unsigned long long *nzero, uint32_t *err, const PairTile &tile,
                        bool sheared, hipStream_t st) {
   if (n <= 0 || ncell <= 0) return true;
-  if (tile.split < 1 || tile.split > 8) return false;
+  if (tile.split < 1 || tile.split > 8 || tile.filter < 0 || tile.filter > 1) return false;
   if (pc.n_species <= 1)
     return launch_ns<1>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
   if (pc.n_species == 2)

@@ -62,9 +62,11 @@ void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
                         const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
                         float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st);
 // Tile shape of the cell-tiled pair kernel: wavefronts per workgroup,
-// 64-candidate chunks per wavefront held in registers, workgroups per cell.
+// 64-candidate chunks per wavefront held in registers, workgroups per cell,
+// and whether the 27-cell stencil is first filtered against the home cell's
+// box (1) or tested whole (0).
 struct PairTile {
-  int waves, chunks, split;
+  int waves, chunks, split, filter;
 };
 extern const PairTile kPairTiles[];  // the shapes the kernel is built for
 extern const int kNumPairTiles;

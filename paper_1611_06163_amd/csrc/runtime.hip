@@ -113,7 +113,7 @@ struct tdpd_sys {
   size_t mem_lds = 0;  // dynamic LDS of the membrane kernel
   int pair_kernel = 1;  // 0: one thread per particle, 1: cell-tiled
   bool any_shear = false;  // a box has Lees-Edwards boundaries
-  PairTile tile{4, 2, 1};  // shape of the cell-tiled kernel
+  PairTile tile{4, 2, 1, 1};  // shape of the cell-tiled kernel
   int bin_mode = 0;     // 0: counting (one-digit stable) sort, 1: LSD radix sort
   bool use_graph = true;
   uint32_t *kdev = nullptr;       // device step counter read by the kernels
@@ -273,7 +273,7 @@ static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
 static bool tile_built(const PairTile &t) {
   for (int i = 0; i < kNumPairTiles; ++i)
     if (kPairTiles[i].waves == t.waves && kPairTiles[i].chunks == t.chunks &&
-        kPairTiles[i].split == t.split)
+        kPairTiles[i].split == t.split && kPairTiles[i].filter == t.filter)
       return true;
   return false;
 }
@@ -328,9 +328,11 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
   if (const char *e = std::getenv("TDPD_PAIR_KERNEL")) s->pair_kernel = std::atoi(e);
   if (const char *e = std::getenv("TDPD_BIN")) s->bin_mode = std::atoi(e);
   if (const char *e = std::getenv("TDPD_GRAPH")) s->use_graph = std::atoi(e) != 0;
-  if (const char *e = std::getenv("TDPD_TILE")) {  // "waves,chunks,split"
+  if (const char *e = std::getenv("TDPD_TILE")) {  // "waves,chunks,split,filter"
     PairTile t{};
-    if (std::sscanf(e, "%d,%d,%d", &t.waves, &t.chunks, &t.split) == 3 && tile_built(t)) s->tile = t;
+    if (std::sscanf(e, "%d,%d,%d,%d", &t.waves, &t.chunks, &t.split, &t.filter) == 4 &&
+        tile_built(t))
+      s->tile = t;
   }
   *out = s;
   return TDPD_OK;
@@ -1319,7 +1321,8 @@ bool cache_lookup(const char *path, const std::string &sig, PairTile *t) {
     const char *bar = std::strchr(line, '|');
     if (!bar || std::string(line, bar - line) != sig) continue;
     PairTile c{};
-    if (std::sscanf(bar + 1, "%d %d %d", &c.waves, &c.chunks, &c.split) == 3 && tile_built(c)) {
+    if (std::sscanf(bar + 1, "%d %d %d %d", &c.waves, &c.chunks, &c.split, &c.filter) == 4 &&
+        tile_built(c)) {
       *t = c;
       found = true;  // the last matching line wins
     }
@@ -1378,8 +1381,8 @@ extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
     if (cache_path) {
       FILE *fp = std::fopen(cache_path, "a");
       if (!fp) return s->fail(TDPD_ERR_IO, std::string("autotune: cannot write ") + cache_path);
-      std::fprintf(fp, "%s|%d %d %d %.6f\n", sig.c_str(), best.waves, best.chunks, best.split,
-                   best_t);
+      std::fprintf(fp, "%s|%d %d %d %d %.6f\n", sig.c_str(), best.waves, best.chunks, best.split,
+                   best.filter, best_t);
       std::fclose(fp);
     }
   }
@@ -1392,20 +1395,23 @@ extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
   return tdpd_sync(s);
 }
 
-extern "C" int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split) {
+extern "C" int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split,
+                             int32_t filter) {
   if (!s) return TDPD_ERR_INVALID_ARG;
-  const PairTile t{waves, chunks, split};
+  const PairTile t{waves, chunks, split, filter};
   if (!tile_built(t)) return s->fail(TDPD_ERR_UNSUPPORTED, "set_tile: shape not built");
   s->tile = t;
   s->destroy_graphs();
   return TDPD_OK;
 }
 
-extern "C" int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split) {
-  if (!s || !waves || !chunks || !split) return TDPD_ERR_INVALID_ARG;
+extern "C" int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split,
+                             int32_t *filter) {
+  if (!s || !waves || !chunks || !split || !filter) return TDPD_ERR_INVALID_ARG;
   *waves = s->tile.waves;
   *chunks = s->tile.chunks;
   *split = s->tile.split;
+  *filter = s->tile.filter;
   return TDPD_OK;
 }
 

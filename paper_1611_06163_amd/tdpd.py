@@ -102,8 +102,9 @@ def lib():
             "tdpd_set_timing": (C.c_int, [P, I32]),
             "tdpd_get_timing": (C.c_int, [P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
             "tdpd_autotune": (C.c_int, [P, C.c_char_p, I32, C.POINTER(C.c_double)]),
-            "tdpd_set_tile": (C.c_int, [P, I32, I32, I32]),
-            "tdpd_get_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32)]),
+            "tdpd_set_tile": (C.c_int, [P, I32, I32, I32, I32]),
+            "tdpd_get_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
+                                        C.POINTER(I32)]),
             "tdpd_mlp_create": (C.c_int, [P, ALLOC_FN, FREE_FN, P, C.POINTER(P)]),
             "tdpd_mlp_num_params": (I64, []),
             "tdpd_mlp_set_params": (C.c_int, [P, P]),
@@ -346,13 +347,14 @@ class System:
 
     @property
     def tile(self):
-        w, c, sp = C.c_int32(), C.c_int32(), C.c_int32()
-        self._check(lib().tdpd_get_tile(self.h, C.byref(w), C.byref(c), C.byref(sp)))
-        return (w.value, c.value, sp.value)
+        """(waves, chunks, split, filter) of the cell-tiled pair kernel."""
+        w, c, sp, f = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(lib().tdpd_get_tile(self.h, C.byref(w), C.byref(c), C.byref(sp), C.byref(f)))
+        return (w.value, c.value, sp.value, f.value)
 
     @tile.setter
     def tile(self, t):
-        self._check(lib().tdpd_set_tile(self.h, int(t[0]), int(t[1]), int(t[2])))
+        self._check(lib().tdpd_set_tile(self.h, int(t[0]), int(t[1]), int(t[2]), int(t[3])))
 
     def save(self, path):
         self._check(lib().tdpd_save(self.h, os.fsencode(path)))

@@ -261,13 +261,21 @@ def test_checkpoint_resume_bitwise(tmp_path):
         gpu_system(I.c1()).load(path)
 
 
-@pytest.mark.parametrize("tile", [(4, 1, 1), (4, 3, 1), (2, 2, 1), (2, 4, 1), (4, 2, 2), (2, 2, 4)])
-@pytest.mark.parametrize("name", ["cluster", "c2"])
+@pytest.mark.parametrize("tile", [(4, 1, 1, 1), (4, 3, 1, 0), (2, 2, 1, 1), (2, 4, 1, 0),
+                                  (4, 2, 2, 1), (2, 2, 4, 0), (2, 3, 1, 1), (4, 2, 1, 0)])
+@pytest.mark.parametrize("name", ["cluster", "c2", "dense"])
 def test_tile_shapes_match_oracle(tile, name):
-    """Every tile shape of the cell-tiled kernel gives forces and fluxes
-    within tolerance of the oracle (cluster: cells above 64 particles and
-    stencils above 256 candidates; c2: one cell body in solvent)."""
-    cfg = _cluster_cfg() if name == "cluster" else I.c2()
+    """Every tile shape of the cell-tiled kernel, with and without the
+    stencil filter, gives forces and fluxes within tolerance of the oracle
+    (cluster: cells above 64 particles and stencils above 256 candidates;
+    c2: one cell body in solvent; dense: stencils of 1000 candidates, beyond
+    the filter's list, which then tests the whole stencil)."""
+    if name == "cluster":
+        cfg = _cluster_cfg()
+    elif name == "dense":
+        cfg = I.make_fluid(box=(6.0, 6.0, 6.0), n=1000, seed=17)
+    else:
+        cfg = I.c2()
     sysg = gpu_system(cfg, kernel=1)
     sysg.tile = tile
     assert sysg.tile == tile
@@ -306,4 +314,6 @@ def test_autotune_picks_a_built_shape_and_caches(tmp_path):
     c.autotune(path, reps=3)
     assert c.tile == chosen and open(path).read() == text
     with pytest.raises(tdpd.TdpdError):
-        c.tile = (3, 3, 3)
+        c.tile = (3, 3, 3, 1)
+    with pytest.raises(tdpd.TdpdError):
+        c.tile = (4, 2, 1, 2)
