@@ -66,10 +66,9 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return uint32_t(__builtin_amdgcn_readfirstlane(int(v)));
 }
 
-// ring slot of this lane among the set lanes of mask m, after `tail`
-__device__ __forceinline__ uint32_t lane_slot(uint64_t m, uint32_t tail) {
-  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), tail)) &
-         uint32_t(kRing - 1);
+// rank of this lane among the set lanes of mask m
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
 }
 
 template <int NS, int W, bool SH>
@@ -85,8 +84,9 @@ struct TiledShared {
   int8_t seg_sg[kMaxSeg][4];  // periodic image per axis: -1, 0 or +1 box length
   int8_t seg_le[kMaxSeg];  // 0 plain, 1 home lifted, 2 candidate lifted (sheared image)
   int8_t seg_m[kMaxSeg];   // multiple of L_x added to the lifted x
-  float rd[W][3][kRing];   // ring: displacement, overwritten by the force
-  uint32_t rij[W][kRing];  // ring: home index << kJBits | candidate slot
+  // ring entries: displacement (overwritten by the force) and, as the bits
+  // of w, home index << kJBits | candidate slot
+  float4 ring[W][kRing];
   uint8_t rl[SH ? W : 1][kRing];  // ring: sheared-image code of the pair (sheared rows only)
   uint16_t list[kMaxList];  // kept candidates: segment << 10 | offset in the segment
   int list_cnt[kMaxList / 64];
@@ -106,10 +106,11 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
   int hi_i = -1;
   wave_sync();
   if (lane < m) {
-    const uint32_t wd = sh.rij[w][e];
+    const float4 re = sh.ring[w][e];
+    const uint32_t wd = __float_as_uint(re.w);
     hi_i = int(wd >> kJBits);
     const uint32_t j = wd & ((1u << kJBits) - 1);
-    const float dx = sh.rd[w][0][e], dy = sh.rd[w][1][e], dz = sh.rd[w][2][e];
+    const float dx = re.x, dy = re.y, dz = re.z;
     float vxi = sh.hvx[hi_i], vxj = s.vx[j];
     if constexpr (LE) {  // the lifted particle's image moves with +u in x
       const int code = sh.rl[w][e];
@@ -120,22 +121,21 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
                                 sh.hvz[hi_i], vxj, s.vy[j], s.vz[j], info_type(sh.hinfo[hi_i]),
                                 info_type(s.info[j]), sh.hgid[hi_i] - B.gid_base,
                                 s.gid[j] - B.gid_base, k);
-    sh.rd[w][0][e] = f.x;
-    sh.rd[w][1][e] = f.y;
-    sh.rd[w][2][e] = f.z;
+    sh.ring[w][e] = make_float4(f.x, f.y, f.z, re.w);
   }
   wave_sync();
   if (lane < m) {
     const bool leader =
-        lane == 0 || int(sh.rij[w][(head + lane - 1) & (kRing - 1)] >> kJBits) != hi_i;
+        lane == 0 ||
+        int(__float_as_uint(sh.ring[w][(head + lane - 1) & (kRing - 1)].w) >> kJBits) != hi_i;
     if (leader) {
       float ax = 0.f, ay = 0.f, az = 0.f;
       for (int q = lane; q < m; ++q) {
-        const uint32_t eq = (head + q) & (kRing - 1);
-        if (int(sh.rij[w][eq] >> kJBits) != hi_i) break;
-        ax += sh.rd[w][0][eq];
-        ay += sh.rd[w][1][eq];
-        az += sh.rd[w][2][eq];
+        const float4 rq = sh.ring[w][(head + q) & (kRing - 1)];
+        if (int(__float_as_uint(rq.w) >> kJBits) != hi_i) break;
+        ax += rq.x;
+        ay += rq.y;
+        az += rq.z;
       }
       sh.fa[w][0][hi_i] += ax;
       sh.fa[w][1][hi_i] += ay;
@@ -335,6 +335,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
     uint32_t head = 0, tail = 0;  // this wave's ring cursors (wave-uniform)
     const float Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
     const bool fick = (pc.terms & TDPD_TERM_FLUX_FICK) != 0;
+    // cutoff bit patterns less one (with fluxes off no pair passes the flux test)
+    const uint32_t rcc2m1 = fick ? __float_as_uint(pc.rcc2) - 1u : 0u;
+    const uint32_t rc2m1 = __float_as_uint(pc.rc2) - 1u;
 
     // the register blocks, specialised for cells with a sheared boundary row
     auto blocks = [&](auto le_tag) {
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       auto homes = [&](auto lift_tag) {
         constexpr bool LB = decltype(lift_tag)::value;
       for (int i = 0; i < nh; ++i) {
-        const uint32_t infoi = sh.hinfo[i];
+        const uint32_t infoi = uniform(sh.hinfo[i]);
         if (info_frozen(infoi)) continue;  // frozen particles get F = Q = 0
         const float xi = sh.hx[i], yi = sh.hy[i], zi = sh.hz[i];
         float xil = xi, yil = yi, zil = zi;
@@ -473,21 +476,23 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
             const uint32_t self = uint32_t(hb + i);
             zero += uint32_t(__popcll(ballot((d2 == 0.f) & (cj[kk] != self))));
           }
-          if (fick && ((d2 > 0.f) & (d2 < pc.rcc2))) {
-            const float wdc = flux_weight(pc, d2);
+          // 0 < d2 < r^2 as one unsigned compare of the bit patterns (d2 is
+          // +0 or above; the NaN of an empty lane lies above every cutoff)
+          const uint32_t d2m1 = __float_as_uint(d2) - 1u;
+          {  // flux on every lane, with zero weight outside the flux cutoff
+            const float wdc = d2m1 < rcc2m1 ? flux_weight(pc, d2) : 0.f;
             const int tt = trow + ct[kk];
 #pragma unroll
-            for (int sp = 0; sp < NS; ++sp) qp[sp] -= sh.kap[sp][tt] * wdc * (ci[sp] - cc[kk][sp]);
+            for (int sp = 0; sp < NS; ++sp)
+              qp[sp] = fmaf(sh.kap[sp][tt] * wdc, cc[kk][sp] - ci[sp], qp[sp]);
           }
-          const bool hitf = (d2 > 0.f) & (d2 < pc.rc2) & (cbody[kk] != bq);
+          // homes outside any cell body test the cutoff alone
+          const bool hitf = bq == -3 ? d2m1 < rc2m1 : (d2m1 < rc2m1) & (cbody[kk] != bq);
           const uint64_t fm = ballot(hitf);
           if (fm) {
             if (hitf) {
-              const uint32_t e = lane_slot(fm, tail);
-              sh.rd[w][0][e] = dx;
-              sh.rd[w][1][e] = dy;
-              sh.rd[w][2][e] = dz;
-              sh.rij[w][e] = hbits | cj[kk];
+              const uint32_t e = (lane_rank(fm) + tail) & uint32_t(kRing - 1);
+              sh.ring[w][e] = make_float4(dx, dy, dz, __uint_as_float(hbits | cj[kk]));
               if constexpr (LE) sh.rl[w][e] = uint8_t((lift[kk] >> 3) & 3u);
             }
             tail = uniform(tail + uint32_t(__popcll(fm)));
