@@ -144,13 +144,41 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
 // its cell: lanes of a wave holding the same key in a run (slots are in the
 // previous step's cell order, so most runs are whole cells) take one atomic
 // for the run, and each lane adds its offset in the run.
+// The closing work of an evaluation for particle i: membrane forces added
+// into F, then (integrate) the second half kick of a mobile particle.
+// Returns the total force.
+__device__ __forceinline__ float3 close_step(const PairConst &pc, State s, float *F,
+                                             const float *Q, int64_t n, const VertexMap &vm,
+                                             bool integrate, int64_t i, uint32_t info) {
+  float fx = F[3 * i], fy = F[3 * i + 1], fz = F[3 * i + 2];
+  const int body = info_body(info);
+  if (vm.Fm && body >= 0) {
+    const int64_t v = vm.rbc_voff[body] + (int64_t(s.gid[i]) - vm.rbc_first[body]);
+    fx += vm.Fm[3 * v];
+    fy += vm.Fm[3 * v + 1];
+    fz += vm.Fm[3 * v + 2];
+    F[3 * i] = fx;
+    F[3 * i + 1] = fy;
+    F[3 * i + 2] = fz;
+  }
+  if (integrate && !info_frozen(info)) {
+    const float h = pc.half_dt;
+    s.vx[i] += h * fx;
+    s.vy[i] += h * fy;
+    s.vz[i] += h * fz;
+    for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+  }
+  return make_float3(fx, fy, fz);
+}
+
 __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__restrict__ boxes,
-                                                 State s, const float *__restrict__ F,
+                                                 State s, float *__restrict__ F,
                                                  const float *__restrict__ Q, int64_t n,
                                                  uint32_t *__restrict__ keys,
                                                  uint32_t *__restrict__ vals, int integrate,
                                                  uint32_t *__restrict__ cell_count,
-                                                 uint32_t *__restrict__ kdev) {
+                                                 uint32_t *__restrict__ kdev, int finish,
+                                                 VertexMap vprev) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const bool active = i < n;
   uint32_t key = 0xffffffffu;
@@ -158,11 +186,17 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
     const uint32_t info = s.info[i];
     const BoxDev &B = boxes[info_box(info)];
     float x = s.x[i], y = s.y[i], z = s.z[i];
+    float3 f;
+    if (finish) {
+      f = close_step(pc, s, F, Q, n, vprev, true, i, info);
+    } else {
+      f = make_float3(F[3 * i], F[3 * i + 1], F[3 * i + 2]);
+    }
     if (integrate && !info_frozen(info)) {
       const float h = pc.half_dt;
-      float vx = s.vx[i] + h * F[3 * i];
-      float vy = s.vy[i] + h * F[3 * i + 1];
-      float vz = s.vz[i] + h * F[3 * i + 2];
+      float vx = s.vx[i] + h * f.x;
+      float vy = s.vy[i] + h * f.y;
+      float vz = s.vz[i] + h * f.z;
       for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
       x += pc.dt * vx;
       y += pc.dt * vy;
@@ -188,7 +222,7 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
         // crossing the y boundary of a sheared box: into the image below
         // (above), x by -delta (+delta), x velocity by -u (+u), with the
         // offsets of this step's counter (the positions are at that time)
-        const LeOff le = le_offsets(B, *kdev, pc.dt);
+        const LeOff le = le_offsets(B, *kdev + uint32_t(finish), pc.dt);
         if (y >= B.L[1]) {
           y -= B.L[1];
           x -= le.delta;
@@ -235,12 +269,13 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
   if (active) vals[i] = b0 + uint32_t(lane - leader);
 }
 
-void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
+void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
                     const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
-                    uint32_t *cell_count, uint32_t *kdev, hipStream_t st) {
+                    uint32_t *cell_count, uint32_t *kdev, bool finish, VertexMap prev,
+                    hipStream_t st) {
   const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
   hipLaunchKernelGGL(k_prekick, dim3(unsigned(nb)), dim3(256), 0, st, pc, boxes, s, F, Q, n, keys,
-                     vals, int(integrate), cell_count, kdev);
+                     vals, int(integrate), cell_count, kdev, int(finish), prev);
 }
 
 // ------------------------------------------------------------- counting binning
@@ -299,7 +334,9 @@ __global__ void __launch_bounds__(kScanThreads) k_count_tiles(const uint32_t *__
 __global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restrict__ count,
                                                              int64_t ncell,
                                                              const uint32_t *__restrict__ tile_sum,
-                                                             uint32_t *__restrict__ start) {
+                                                             uint32_t *__restrict__ start,
+                                                             uint32_t *__restrict__ advance) {
+  if (advance && blockIdx.x == 0 && threadIdx.x == 0) *advance += 1u;  // nothing here reads it
   __shared__ uint32_t sh[kScanThreads];
   __shared__ uint32_t tile[kCellTile];
   const int t = threadIdx.x;
@@ -360,8 +397,16 @@ __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uin
   const uint32_t q = tmp[p0];
   const uint32_t c = keys[q];
   const uint32_t s0 = start[c], s1 = start[c + 1];
+  // rank among the cell's entries by previous slot; eight independent loads
+  // per round so that their latencies overlap (past the cell end: no entry)
   uint32_t r = 0;
-  for (uint32_t m = s0; m < s1; ++m) r += tmp[m] < q ? 1u : 0u;
+  for (uint32_t m = s0; m < s1; m += 8) {
+    uint32_t t[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) t[u] = m + u < s1 ? tmp[m + u] : 0xffffffffu;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) r += t[u] < q ? 1u : 0u;
+  }
   const uint32_t p = s0 + r;
   b.x[p] = a.x[q];
   b.y[p] = a.y[q];
@@ -380,13 +425,13 @@ __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uin
 void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
                          uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
                          uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
-                         uint32_t *keys_sorted, hipStream_t st) {
+                         uint32_t *keys_sorted, uint32_t *advance, hipStream_t st) {
   const int64_t nt = count_scan_tiles(ncell);
   if (nt > 1)  // one tile needs no tile prefix
     hipLaunchKernelGGL(k_count_tiles, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count,
                        ncell, tile_sum);
   hipLaunchKernelGGL(k_count_scan, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count, ncell,
-                     tile_sum, cell_start);
+                     tile_sum, cell_start, advance);
   if (n <= 0) return;
   const dim3 g(unsigned((n + 255) / 256));
   hipLaunchKernelGGL(k_scatter_rank, g, dim3(256), 0, st, keys, rank, cell_start, n, tmp);
@@ -404,24 +449,7 @@ __global__ void __launch_bounds__(256) k_postkick(PairConst pc, State s, float *
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i == 0 && kdev) *kdev += 1u;
   if (i >= n) return;
-  const uint32_t info = s.info[i];
-  float fx = F[3 * i], fy = F[3 * i + 1], fz = F[3 * i + 2];
-  const int body = info_body(info);
-  if (vm.Fm && body >= 0) {
-    const int64_t v = vm.rbc_voff[body] + (int64_t(s.gid[i]) - vm.rbc_first[body]);
-    fx += vm.Fm[3 * v];
-    fy += vm.Fm[3 * v + 1];
-    fz += vm.Fm[3 * v + 2];
-    F[3 * i] = fx;
-    F[3 * i + 1] = fy;
-    F[3 * i + 2] = fz;
-  }
-  if (!integrate || info_frozen(info)) return;
-  const float h = pc.half_dt;
-  s.vx[i] += h * fx;
-  s.vy[i] += h * fy;
-  s.vz[i] += h * fz;
-  for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+  (void)close_step(pc, s, F, Q, n, vm, integrate != 0, i, s.info[i]);
 }
 
 void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,

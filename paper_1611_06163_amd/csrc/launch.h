@@ -16,23 +16,35 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
                 uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, uint32_t *hist,
                 int64_t n, int key_bits, hipStream_t st);
 
+// Membrane forces of an evaluation, indexed by global vertex (launch_membrane).
+struct VertexMap {
+  const float *Fm;          // [nvert][3] or null
+  const int64_t *rbc_first; // [nrbc]
+  const int64_t *rbc_voff;  // [nrbc]
+};
 // First half kick + drift + walls + wrap + cell key (one thread per particle).
 // With cell_count, vals gets the particle's unordered rank in its cell (the
 // counting binning); else vals = index (the radix binning).  *kdev is the
 // counter of this evaluation (sheared boxes take its image offsets).
-void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
+// finish: the previous step's closing work (launch_postkick's, with `prev`
+// its membrane forces) is done first, per particle, with the same
+// arithmetic; the counter is then not yet advanced, so this evaluation's is
+// *kdev + 1 (the binning advances it: launch_bin_counting's advance).
+void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
                     const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
-                    uint32_t *cell_count, uint32_t *kdev, hipStream_t st);
+                    uint32_t *cell_count, uint32_t *kdev, bool finish, VertexMap prev,
+                    hipStream_t st);
 // Counting binning after launch_prekick: scan of the cell counts into
 // cell_start (counts zeroed for the next step; tile_sum holds
 // count_scan_tiles(ncell) words), scatter, and the rank fix-up fused with
 // the reorder of every state plane into dst (slot_of_gid and the sorted keys
 // updated).  Same permutation as the stable radix sort.
 int64_t count_scan_tiles(int64_t ncell);
+// With advance, the scan also advances the step counter *advance by one.
 void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
                          uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
                          uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
-                         uint32_t *keys_sorted, hipStream_t st);
+                         uint32_t *keys_sorted, uint32_t *advance, hipStream_t st);
 // cell_start[c] = first sorted index of cell c, cell_start[ncell] = n.
 void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
                         uint32_t *cell_start, hipStream_t st);
@@ -44,11 +56,6 @@ void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int n
 // the evaluation by advancing the device step counter *kdev by one (the
 // kernels of an evaluation at counter k all read k; the next step reads
 // k + 1).
-struct VertexMap {
-  const float *Fm;          // [nvert][3] or null
-  const int64_t *rbc_first; // [nrbc]
-  const int64_t *rbc_voff;  // [nrbc]
-};
 void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,
                      VertexMap vm, bool integrate, uint32_t *kdev, hipStream_t st);
 // Sets *kdev = k.

@@ -128,8 +128,10 @@ struct tdpd_sys {
   int32_t *d_vcell = nullptr;
   hipStream_t st2 = nullptr, gst = nullptr;  // membrane stream, capture stream
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  // captured steps: [0], [1] one step from buffer parity A / B; [2], [3]
+  // kGraphSteps steps from parity A / B (an even count ends at the start parity)
+  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   // event timing per phase (index = log2 of TDPD_PHASE_*)
   int timing_mask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool[4];
@@ -155,7 +157,7 @@ struct tdpd_sys {
     return p;
   }
   void destroy_graphs() {
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 4; ++q) {
       if (gexec[q]) (void)hipGraphExecDestroy(gexec[q]);
       if (graph[q]) (void)hipGraphDestroy(graph[q]);
       gexec[q] = nullptr;
@@ -866,14 +868,26 @@ static int prepare(tdpd_sys *s) {
   return TDPD_OK;
 }
 
+// Whether consecutive integrated steps may fold one step's closing kick
+// into the next step's first kick (counting binning, which then advances
+// the counter).
+static bool can_fuse_kicks(const tdpd_sys *s) { return s->bin_mode == 0 && s->n > 0; }
+
 // Enqueue one force evaluation on stream `st`, optionally wrapped in the two
 // velocity-Verlet half kicks.  The random-number counter is *kdev (set by the
-// caller, or incremented by the first kick).  Host-side only swaps A/B.
-static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
+// caller; each evaluation's last kernel advances it).  Host-side only swaps
+// A/B.  Between integrated steps (can_fuse_kicks): fuse_prev does the
+// previous evaluation's closing kick at the start of this one's first kick
+// (the binning then advances the counter), and fuse_next leaves this
+// evaluation's closing kick to the next one.
+static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool fuse_prev = false,
+                              bool fuse_next = false) {
   const int64_t n = s->n;
+  const int nrbc = int(s->rbc_mesh.size());
+  const VertexMap vmap{nrbc > 0 ? s->Fm : nullptr, s->d_rbc_first, s->d_rbc_voff};
   const bool tb = s->phase_begin(1, st);
   launch_prekick(s->pc, s->d_boxes, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate,
-                 s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, st);
+                 s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, fuse_prev, vmap, st);
   if (n == 0) {
     s->phase_end(1, tb, st);
     launch_postkick(s->pc, s->cur(), s->F, s->Q, 0, VertexMap{nullptr, nullptr, nullptr}, false,
@@ -883,7 +897,7 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   if (s->bin_mode == 0) {
     launch_bin_counting(s->cur(), s->nxt(), s->keys, s->vals, s->cell_count, s->ncell,
                         s->cell_start, s->bin_tmp, s->tile_sum, n, s->S, s->slot_of_gid, s->keys_s,
-                        st);
+                        fuse_prev ? s->kdev : nullptr, st);
   } else {
     radix_sort(s->keys, s->vals, s->keys_tmp, s->vals_tmp, s->keys_s, s->perm, s->hist, n,
                s->key_bits, st);
@@ -892,7 +906,6 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   }
   s->phase_end(1, tb, st);
   s->cur_A = !s->cur_A;
-  const int nrbc = int(s->rbc_mesh.size());
   // membrane terms on the second stream, beside the pair kernel
   if (nrbc > 0) {
     (void)hipEventRecord(s->ev_fork, st);
@@ -937,10 +950,9 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st) {
   }
   s->phase_end(0, tp, st);
   if (nrbc > 0) (void)hipStreamWaitEvent(st, s->ev_join, 0);
-  {
+  if (!fuse_next) {
     const bool tk = s->phase_begin(3, st);
-    VertexMap vm{nrbc > 0 ? s->Fm : nullptr, s->d_rbc_first, s->d_rbc_voff};
-    launch_postkick(s->pc, s->cur(), s->F, s->Q, n, vm, integrate, s->kdev, st);
+    launch_postkick(s->pc, s->cur(), s->F, s->Q, n, vmap, integrate, s->kdev, st);
     s->phase_end(3, tk, st);
   }
   return TDPD_OK;
@@ -963,21 +975,31 @@ static int evaluate_at(tdpd_sys *s, uint32_t k) {
   return check_launch(s);
 }
 
-// Capture one integrated step for each A/B parity on a private stream.
+// Capture, on a private stream, one integrated step and kGraphSteps
+// integrated steps for each A/B parity (capturing runs nothing: only the
+// host-side parity advances, and it is restored).
+constexpr int kGraphSteps = 4;
+static_assert(kGraphSteps % 2 == 0, "a multi-step graph must end at its start parity");
 static int capture_graphs(tdpd_sys *s) {
   if (!s->gst) HIPCHK(hipStreamCreateWithFlags(&s->gst, hipStreamNonBlocking));
   const bool start_A = s->cur_A;
-  for (int q = 0; q < 2; ++q) {
-    const int slot = s->cur_A ? 0 : 1;
+  for (int q = 0; q < 4; ++q) {
+    const int slot = (q < 2 ? 0 : 2) + (s->cur_A ? 0 : 1);
     HIPCHK(hipStreamBeginCapture(s->gst, hipStreamCaptureModeThreadLocal));
-    const int rc = enqueue_evaluation(s, true, s->gst);
+    int rc = TDPD_OK;
+    const int steps = q < 2 ? 1 : kGraphSteps;
+    const bool fuse = can_fuse_kicks(s);
+    for (int r = 0; r < steps && !rc; ++r)
+      rc = enqueue_evaluation(s, true, s->gst, fuse && r > 0, fuse && r + 1 < steps);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s->gst, &g);
     if (rc) return rc;
     if (e != hipSuccess) return s->fail(TDPD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
     s->graph[slot] = g;
     HIPCHK(hipGraphInstantiate(&s->gexec[slot], g, nullptr, nullptr, 0));
+    if (q == 2) s->cur_A = !s->cur_A;  // the multi-step graph of the other parity
   }
+  s->cur_A = !s->cur_A;
   if (s->cur_A != start_A) return s->fail(TDPD_ERR_HIP, "graph capture: parity mismatch");
   return TDPD_OK;
 }
@@ -1005,15 +1027,24 @@ extern "C" int tdpd_step(tdpd_sys *s, int32_t n_steps) {
   }
   const bool graphs = s->use_graph && s->timing_mask == 0 && s->n > 0;
   if (graphs && !s->gexec[0] && (rc = capture_graphs(s))) return rc;
-  for (int i = 0; i < n_steps; ++i) {
+  for (int i = 0; i < n_steps;) {
+    if (graphs && n_steps - i >= kGraphSteps) {
+      HIPCHK(hipGraphLaunch(s->gexec[2 + (s->cur_A ? 0 : 1)], s->st));  // parity unchanged
+      s->step += kGraphSteps;
+      s->kdev_val += kGraphSteps;
+      i += kGraphSteps;
+      continue;
+    }
     ++s->step;
     if (graphs) {
       HIPCHK(hipGraphLaunch(s->gexec[s->cur_A ? 0 : 1], s->st));
       s->cur_A = !s->cur_A;
-    } else if ((rc = enqueue_evaluation(s, true, s->st))) {
+    } else if ((rc = enqueue_evaluation(s, true, s->st, can_fuse_kicks(s) && i > 0,
+                                        can_fuse_kicks(s) && i + 1 < n_steps))) {
       return rc;
     }
     ++s->kdev_val;
+    ++i;
   }
   return check_launch(s);
 }
