@@ -1,290 +1,27 @@
-// kernels_membrane.hip -- RBC membrane terms (Section 2.2), one workgroup per
-// cell, its vertices staged in LDS:
-//   1. K-Gather: per-triangle area and volume (FP32) summed in FP64 over the
-//      cell by a fixed-order tree, plus the centroid update;
-//   2. per bond, once: WLC + POW spring (Eqs. 13-14), viscosity (Eq. 15) and
-//      its random partner (Eq. 16), kept in LDS;
-//   3. per vertex: the signed sum of its bond forces, the global/local area
-//      and volume constraint forces over its incident triangles (K-Apply,
-//      Eqs. 17-18; each triangle recomputed by its three vertices as the
-//      paper does, Section 3.3) and bending over its incident dihedrals
-//      (Eq. 19), added into F.
-// No atomics; every sum has a fixed order.
-#include "launch.h"
+// kernels_membrane.hip -- RBC membrane terms (Section 2.2) as a kernel of
+// its own, one workgroup per cell (membrane_cell.h); used where the pair
+// kernel does not take the cells itself (surrogate runs, the simple pair
+// kernel).
+#include "membrane_cell.h"
 
 namespace tdpd {
 
 constexpr int kMemThreads = 512;
 
-__device__ __forceinline__ float3 sub(float3 a, float3 b) {
-  return make_float3(a.x - b.x, a.y - b.y, a.z - b.z);
-}
-__device__ __forceinline__ float3 crs(float3 a, float3 b) {
-  return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ float dt3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-// gradient of the signed normal angle of triangles (a,b,c), (d,c,b) with
-// respect to the vertex in `role` (0..3 = a,b,c,d); also returns sin/cos.
-__device__ __forceinline__ float3 dihedral_grad(float3 a, float3 b, float3 c, float3 d, int role,
-                                                float &sn, float &cs) {
-  const float3 n1 = crs(sub(b, a), sub(c, a));
-  const float3 n2 = crs(sub(c, d), sub(b, d));
-  const float3 e = sub(c, b);
-  const float le2 = dt3(e, e);
-  const float le = sqrtf(le2);
-  const float n11 = dt3(n1, n1), n22 = dt3(n2, n2);
-  const float inv = __builtin_amdgcn_rsqf(n11 * n22);
-  sn = dt3(crs(n1, n2), e) / le * inv;
-  cs = dt3(n1, n2) * inv;
-  const float f1 = -le / n11, f2 = -le / n22;
-  const float3 ga = make_float3(f1 * n1.x, f1 * n1.y, f1 * n1.z);
-  const float3 gd = make_float3(f2 * n2.x, f2 * n2.y, f2 * n2.z);
-  if (role == 0) return ga;
-  if (role == 3) return gd;
-  const float ta = dt3(sub(a, b), e) / le2, td = dt3(sub(d, b), e) / le2;
-  if (role == 1)
-    return make_float3((ta - 1.f) * ga.x + (td - 1.f) * gd.x, (ta - 1.f) * ga.y + (td - 1.f) * gd.y,
-                       (ta - 1.f) * ga.z + (td - 1.f) * gd.z);
-  return make_float3(-ta * ga.x - td * gd.x, -ta * ga.y - td * gd.y, -ta * ga.z - td * gd.z);
+size_t membrane_lds_bytes(int max_nv) { return membrane_cell_lds(max_nv, kMemThreads); }
+
+__global__ void __launch_bounds__(kMemThreads) k_membrane(MemArgs ma, const BoxDev *__restrict__ boxes,
+                                                          State s, const uint32_t *__restrict__ kdev,
+                                                          uint32_t *err) {
+  extern __shared__ double lds_d[];
+  membrane_cell(ma, boxes, s, *kdev, err, int(blockIdx.x), reinterpret_cast<char *>(lds_d));
 }
 
-size_t membrane_lds_bytes(int max_nv, int max_nbond) {
-  return size_t(max_nv) * (6 * sizeof(float) + sizeof(uint32_t)) +
-         size_t(max_nbond) * 3 * sizeof(float) + 64;
-}
-
-__global__ void __launch_bounds__(kMemThreads) k_membrane(
-    MembraneConst mc, const BoxDev *__restrict__ boxes, const MeshDev *__restrict__ meshes,
-    const int32_t *__restrict__ rbc_mesh, const int32_t *__restrict__ rbc_box,
-    const int64_t *__restrict__ rbc_first, const int64_t *__restrict__ rbc_voff, State s,
-    const uint32_t *__restrict__ slot_of_gid, double *__restrict__ av,
-    double *__restrict__ centroid, const uint32_t *__restrict__ kdev, float *__restrict__ Fm,
-    uint32_t *err, SurrUse su) {
-  extern __shared__ float lds[];
-  __shared__ double red[kMemThreads];
-  __shared__ double tot[5];
-  const int r = blockIdx.x, tid = threadIdx.x;
-  const uint32_t k = *kdev;
-  if (mc.gate > 0 && (k % uint32_t(mc.gate)) != 0u) return;
-  const MeshDev &M = meshes[rbc_mesh[r]];
-  const BoxDev &B = boxes[rbc_box[r]];
-  const int nv = M.nv;
-  float *px = lds, *py = px + nv, *pz = py + nv, *wx = pz + nv, *wy = wx + nv, *wz = wy + nv;
-  uint32_t *sl = reinterpret_cast<uint32_t *>(wz + nv);
-  float *fb = reinterpret_cast<float *>(sl + nv);  // [3][nbond]
-  const int64_t g0 = rbc_first[r];
-  for (int v = tid; v < nv; v += kMemThreads) {
-    const uint32_t q = slot_of_gid[g0 + v];
-    sl[v] = q;
-    px[v] = s.x[q];
-    py[v] = s.y[q];
-    pz[v] = s.z[q];
-    wx[v] = s.vx[q];
-    wy[v] = s.vy[q];
-    wz[v] = s.vz[q];
-  }
-  __syncthreads();
-  auto P = [&](int v) { return make_float3(px[v], py[v], pz[v]); };
-  const int terms = mc.terms;
-  // nearest image (sheared boxes: Lees-Edwards image of the step counter)
-  const LeOff le = le_offsets(B, k, mc.dt);
-  auto rel = [&](float3 a, float3 o) { return le_rel(B, a, o, le.delta, nullptr); };
-
-  // ---- 1. K-Gather
-  {
-    const float3 cf = make_float3(float(centroid[3 * r]), float(centroid[3 * r + 1]),
-                                  float(centroid[3 * r + 2]));
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int t = tid; t < M.ntri; t += kMemThreads) {
-      const float3 a = rel(P(M.tri[3 * t]), cf);
-      const float3 b = rel(P(M.tri[3 * t + 1]), cf);
-      const float3 c = rel(P(M.tri[3 * t + 2]), cf);
-      const float3 nn = crs(sub(b, a), sub(c, a));
-      acc[0] += double(0.5f * sqrtf(dt3(nn, nn)));
-      acc[1] += double(dt3(a, crs(b, c)) * (1.f / 6.f));
-    }
-    for (int v = tid; v < nv; v += kMemThreads) {
-      const float3 a = rel(P(v), cf);
-      acc[2] += a.x;
-      acc[3] += a.y;
-      acc[4] += a.z;
-    }
-    for (int f = 0; f < 5; ++f) {
-      red[tid] = acc[f];
-      __syncthreads();
-      for (int off = kMemThreads / 2; off > 0; off >>= 1) {
-        if (tid < off) red[tid] += red[tid + off];
-        __syncthreads();
-      }
-      if (tid == 0) tot[f] = red[0];
-      __syncthreads();
-    }
-    if (tid == 0 && !mc.local_only) {
-      av[2 * r] = tot[0];
-      av[2 * r + 1] = tot[1];
-      centroid[3 * r] = double(cf.x) + tot[2] / nv;
-      centroid[3 * r + 1] = double(cf.y) + tot[3] / nv;
-      centroid[3 * r + 2] = double(cf.z) + tot[4] / nv;
-    }
-  }
-
-  // ---- 2. bonds, Eqs. (13)-(16): force on the bond's first vertex a
-  if (terms & (TDPD_TERM_BOND | TDPD_TERM_BOND_VISCOUS | TDPD_TERM_BOND_RANDOM)) {
-    const float amp = sqrtf(2.f * mc.kT / mc.dt);
-    const float ct = sqrtf(2.f * M.gamma_t);
-    const float cc = sqrtf(fmaxf(3.f * M.gamma_c - M.gamma_t, 0.f)) * (1.f / 3.f);
-    for (int bnd = tid; bnd < M.nbond; bnd += kMemThreads) {
-      const int2 ab = M.bond_ab[bnd];
-      int nyb = 0;  // b taken in the sheared image below (-1) or above (+1) a
-      const float3 d = le_rel(B, P(ab.y), P(ab.x), le.delta, &nyb);  // a -> b
-      const float l = sqrtf(dt3(d, d));
-      const float il = 1.f / l;
-      float3 f = make_float3(0.f, 0.f, 0.f);
-      if (terms & TDPD_TERM_BOND) {
-        const float2 par = M.bond_par[bnd];  // (l_m, k_p)
-        const float x = l / par.x;
-        if (x >= 1.f) {
-          atomicOr(err, kErrOverext);
-        } else {
-          const float om = 1.f - x;
-          const float dwlc = mc.kT / M.p * (0.25f / (om * om) - 0.25f + x);
-          const float dpow = -par.y * powu_any(l, -M.m_pow);
-          const float fs = (dwlc + dpow) * il;
-          f.x += fs * d.x;
-          f.y += fs * d.y;
-          f.z += fs * d.z;
-        }
-      }
-      // e points from b to a (the paper's e_ij with i = a)
-      const float3 e = make_float3(-d.x * il, -d.y * il, -d.z * il);
-      if (terms & TDPD_TERM_BOND_VISCOUS) {
-        const float3 vr = make_float3(wx[ab.x] - wx[ab.y] - float(nyb) * le.u, wy[ab.x] - wy[ab.y],
-                                      wz[ab.x] - wz[ab.y]);
-        const float ve = dt3(vr, e);
-        f.x += -M.gamma_t * vr.x - M.gamma_c * ve * e.x;
-        f.y += -M.gamma_t * vr.y - M.gamma_c * ve * e.y;
-        f.z += -M.gamma_t * vr.z - M.gamma_c * ve * e.z;
-      }
-      if (terms & TDPD_TERM_BOND_RANDOM) {
-        // a < b locally and gids are consecutive, so (g0+a, g0+b) is ordered;
-        // the counter takes box-local gids
-        const uint32_t ga = uint32_t(g0 + ab.x) - B.gid_base, gb = uint32_t(g0 + ab.y) - B.gid_base;
-        float W[12];  // streams 64..66: (cos, sin) of words (0,1) then (2,3); first 9 used
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const u32x4 z = philox10(k, ga, gb, B.ctr3 | uint32_t(64 + q), B.seed_lo, B.seed_hi);
-          gauss2(z.a, z.b, W[4 * q], W[4 * q + 1]);
-          gauss2(z.c, z.d, W[4 * q + 2], W[4 * q + 3]);
-        }
-        const float trW = W[0] + W[4] + W[8];  // trace of W and of its symmetric part
-        const float ex[3] = {e.x, e.y, e.z};
-        float o[3];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          float acc = 0.f;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            float m = ct * (0.5f * (W[3 * i + j] + W[3 * j + i]) - (i == j ? trW * (1.f / 3.f) : 0.f));
-            if (i == j) m += cc * trW;
-            acc += m * ex[j];
-          }
-          o[i] = amp * acc;
-        }
-        f.x += o[0];
-        f.y += o[1];
-        f.z += o[2];
-      }
-      fb[bnd] = f.x;
-      fb[M.nbond + bnd] = f.y;
-      fb[2 * M.nbond + bnd] = f.z;
-    }
-  }
-  __syncthreads();
-
-  // ---- 3. per vertex
-  const float cg = mc.local_only ? 0.f : float(M.kg * (tot[0] - M.A0) / M.A0);
-  const float cv = mc.local_only ? 0.f : float(M.kv * (tot[1] - M.V0) / M.V0);
-  const float s0 = sinf(M.theta0), c0 = cosf(M.theta0);
-  for (int v = tid; v < nv; v += kMemThreads) {
-    const float3 pv = P(v);
-    float3 f = make_float3(0.f, 0.f, 0.f);
-    // bending and local area of this vertex come from the surrogate
-    const bool sv = su.flag && su.flag[rbc_voff[r] + v];
-    if (terms & (TDPD_TERM_BOND | TDPD_TERM_BOND_VISCOUS | TDPD_TERM_BOND_RANDOM)) {
-      for (int q = M.bond_off[v]; q < M.bond_off[v + 1]; ++q) {
-        const int inc = M.bond_inc[q];
-        const int bnd = inc >> 1;
-        const float sg = (inc & 1) ? -1.f : 1.f;
-        f.x += sg * fb[bnd];
-        f.y += sg * fb[M.nbond + bnd];
-        f.z += sg * fb[2 * M.nbond + bnd];
-      }
-    }
-    if (terms & (TDPD_TERM_AREA | TDPD_TERM_VOLUME)) {
-      for (int q = M.tri_off[v]; q < M.tri_off[v + 1]; ++q) {
-        const int4 tr = M.tri_inc[q];  // (b, c, triangle, -), v first, counter-clockwise
-        const float3 rb = rel(P(tr.x), pv);
-        const float3 rc = rel(P(tr.y), pv);
-        const float3 nn = crs(rb, rc);
-        if (terms & TDPD_TERM_AREA) {
-          const float nl = sqrtf(dt3(nn, nn));
-          const float At = 0.5f * nl;
-          const float a0 = M.A0t[tr.z];
-          const float cl = sv ? 0.f : M.kl * (At - a0) / a0;
-          const float coef = -(cg + cl) * 0.5f / nl;
-          const float3 g = crs(nn, sub(rc, rb));  // |n| * (n_hat x (c - b))
-          f.x += coef * g.x;
-          f.y += coef * g.y;
-          f.z += coef * g.z;
-        }
-        if (terms & TDPD_TERM_VOLUME) {
-          const float coef = -cv * (1.f / 6.f);  // dV/dv = (b - v) x (c - v) / 6
-          f.x += coef * nn.x;
-          f.y += coef * nn.y;
-          f.z += coef * nn.z;
-        }
-      }
-    }
-    if ((terms & TDPD_TERM_BENDING) && !sv) {
-      const float3 zero3 = make_float3(0.f, 0.f, 0.f);
-      for (int q = M.dih_off[v]; q < M.dih_off[v + 1]; ++q) {
-        const int4 D = M.dih_inc[q];
-        const int role = M.dih_role[q];
-        const float3 a = role == 0 ? zero3 : rel(P(D.x), pv);
-        const float3 b = role == 1 ? zero3 : rel(P(D.y), pv);
-        const float3 c = role == 2 ? zero3 : rel(P(D.z), pv);
-        const float3 d = role == 3 ? zero3 : rel(P(D.w), pv);
-        float sn, cs;
-        const float3 g = dihedral_grad(a, b, c, d, role, sn, cs);
-        const float coef = -M.kb * (sn * c0 - cs * s0);  // -kb sin(theta - theta0)
-        f.x += coef * g.x;
-        f.y += coef * g.y;
-        f.z += coef * g.z;
-      }
-    }
-    const int64_t o = 3 * (rbc_voff[r] + v);
-    if (sv) {
-      f.x += su.Fs[o];
-      f.y += su.Fs[o + 1];
-      f.z += su.Fs[o + 2];
-    }
-    Fm[o] = f.x;
-    Fm[o + 1] = f.y;
-    Fm[o + 2] = f.z;
-    if (!(isfinite(f.x) && isfinite(f.y) && isfinite(f.z))) atomicOr(err, kErrNonfinite);
-  }
-}
-
-void launch_membrane(const MembraneConst &mc, const BoxDev *boxes, const MeshDev *meshes,
-                     const int32_t *rbc_mesh, const int32_t *rbc_box, const int64_t *rbc_first,
-                     const int64_t *rbc_voff, int nrbc, State s,
-                     const uint32_t *slot_of_gid, double *av, double *centroid,
-                     const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
-                     SurrUse su, hipStream_t st) {
-  if (nrbc <= 0) return;
-  hipLaunchKernelGGL(k_membrane, dim3(nrbc), dim3(kMemThreads), lds_bytes, st, mc, boxes, meshes,
-                     rbc_mesh, rbc_box, rbc_first, rbc_voff, s, slot_of_gid, av, centroid, kdev, Fm,
-                     err, su);
+void launch_membrane(const MemArgs &ma, const BoxDev *boxes, State s, const uint32_t *kdev,
+                     uint32_t *err, size_t lds_bytes, hipStream_t st) {
+  if (ma.nrbc <= 0) return;
+  hipLaunchKernelGGL(k_membrane, dim3(ma.nrbc), dim3(kMemThreads), lds_bytes, st, ma, boxes, s,
+                     kdev, err);
 }
 
 }  // namespace tdpd

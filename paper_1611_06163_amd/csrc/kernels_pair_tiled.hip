@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "launch.h"
+#include "membrane_cell.h"
 #include "pair_terms.h"
 
 namespace tdpd {
@@ -156,13 +157,20 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
                                                             float *__restrict__ F,
                                                             float *__restrict__ Q,
                                                             unsigned long long *nzero,
-                                                            uint32_t *err) {
+                                                            uint32_t *err, MemArgs ma, int nmemb) {
   __shared__ TiledShared<NS, W, SH> sh;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t k = *kdev;  // random-number step counter
+  // the first nmemb workgroups (a multiple of 8) take the membrane terms of
+  // one cell each, in this workgroup's LDS; they run beside the pair work
+  if (int(blockIdx.x) < nmemb) {
+    if (int(blockIdx.x) < ma.nrbc)
+      membrane_cell(ma, boxes, s, k, err, int(blockIdx.x), reinterpret_cast<char *>(&sh));
+    return;
+  }
   // consecutive workgroups go to different XCDs; give each XCD a contiguous
   // slab of cells so neighbouring cells share that XCD's L2
-  const int64_t b = blockIdx.x;
+  const int64_t b = int64_t(blockIdx.x) - nmemb;
   const int64_t item = (b & 7) * per_xcd + (b >> 3);
   if (item >= ncell * split) return;
   const int64_t cell = item / split;
@@ -571,27 +579,30 @@ static void launch_shape(const PairConst &pc, const BoxDev *boxes, State s,
                          const uint32_t *cell_start, int64_t ncell, int split, int filter,
                          int64_t n,
                          const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
-                         uint32_t *err, bool sheared, hipStream_t st) {
+                         uint32_t *err, bool sheared, const MemArgs &ma, hipStream_t st) {
   const int64_t per_xcd = (ncell * split + 7) / 8;
-  const dim3 grid(unsigned(per_xcd * 8)), block(64 * W);
+  const int nmemb = (ma.nrbc + 7) / 8 * 8;
+  const dim3 grid(unsigned(per_xcd * 8 + nmemb)), block(64 * W);
   // the sheared-row variant costs registers: only systems with a sheared box get it
   if (sheared)
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, true>), grid, block, 0, st, pc, boxes, s,
-                       cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err);
+                       cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err, ma,
+                       nmemb);
   else
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, false>), grid, block, 0, st, pc, boxes, s,
-                       cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err);
+                       cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err, ma,
+                       nmemb);
 }
 
 template <int NS>
 static bool launch_ns(const PairConst &pc, const BoxDev *boxes, State s, const uint32_t *cell_start,
                       int64_t ncell, int64_t n, const uint32_t *kdev, float *F, float *Q,
                       unsigned long long *nzero, uint32_t *err, const PairTile &t,
-                      bool sheared, hipStream_t st) {
+                      bool sheared, const MemArgs &ma, hipStream_t st) {
 #define TDPD_SHAPE(W, KC)                                                                    \
   if (t.waves == W && t.chunks == KC) {                                                      \
     launch_shape<NS, W, KC>(pc, boxes, s, cell_start, ncell, t.split, t.filter, n, kdev, F, Q, \
-                            nzero, err, sheared, st);                                        \
+                            nzero, err, sheared, ma, st);                                    \
     return true;                                                                             \
   }
   TDPD_SHAPE(4, 2)
@@ -616,16 +627,32 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
                        const uint32_t *cell_start, int64_t ncell,
                        int64_t n, const uint32_t *kdev, float *F, float *Q,
                        unsigned long long *nzero, uint32_t *err, const PairTile &tile,
-                       bool sheared, hipStream_t st) {
+                       bool sheared, const MemArgs &ma, hipStream_t st) {
   if (n <= 0 || ncell <= 0) return true;
   if (tile.split < 1 || tile.split > 8 || tile.filter < 0 || tile.filter > 1) return false;
   if (pc.n_species <= 1)
-    return launch_ns<1>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
+    return launch_ns<1>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
   if (pc.n_species == 2)
-    return launch_ns<2>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
+    return launch_ns<2>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
   if (pc.n_species <= 4)
-    return launch_ns<4>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
-  return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, st);
+    return launch_ns<4>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
+  return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
+}
+
+// LDS of one workgroup of the shape, which the membrane workgroups reuse.
+template <int NS>
+static size_t lds_ns(const PairTile &t, bool sheared) {
+  if (t.waves == 2) return sheared ? sizeof(TiledShared<NS, 2, true>) : sizeof(TiledShared<NS, 2, false>);
+  return sheared ? sizeof(TiledShared<NS, 4, true>) : sizeof(TiledShared<NS, 4, false>);
+}
+
+bool pair_tiled_takes_membrane(const PairTile &t, int n_species, bool sheared, int max_nv) {
+  if (t.waves != 2 && t.waves != 4) return false;
+  const size_t have = n_species <= 1   ? lds_ns<1>(t, sheared)
+                      : n_species == 2 ? lds_ns<2>(t, sheared)
+                      : n_species <= 4 ? lds_ns<4>(t, sheared)
+                                       : lds_ns<8>(t, sheared);
+  return membrane_cell_lds(max_nv, 64 * t.waves) <= have;
 }
 
 }  // namespace tdpd

@@ -77,13 +77,6 @@ struct PairTile {
 };
 extern const PairTile kPairTiles[];  // the shapes the kernel is built for
 extern const int kNumPairTiles;
-// Pair forces and fluxes, cell-tiled kernel (sheared: some box has
-// Lees-Edwards boundaries).  Returns false for a shape that is not built.
-bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
-                       const uint32_t *cell_start, int64_t ncell,
-                       int64_t n, const uint32_t *kdev, float *F, float *Q,
-                       unsigned long long *nzero, uint32_t *err, const PairTile &tile,
-                       bool sheared, hipStream_t st);
 // Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
 void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
                       const uint32_t *cell_keys,
@@ -133,20 +126,42 @@ struct SurrUse {
   const float *Fs;
 };
 
+// Everything the membrane terms of a set of cells read and write.
+struct MemArgs {
+  MembraneConst mc;
+  const MeshDev *meshes;
+  const int32_t *rbc_mesh, *rbc_box;     // [nrbc]
+  const int64_t *rbc_first, *rbc_voff;   // [nrbc]
+  const uint32_t *slot_of_gid;
+  double *av, *centroid;                 // [nrbc][2], [nrbc][3] (FP64 totals)
+  float *Fm;                             // [nvert][3] output
+  float *Fb;                             // [nrbc][3][bond_stride] per-bond scratch
+  int64_t bond_stride;                   // >= nbond of every mesh
+  SurrUse su;
+  int nrbc;
+};
 // All membrane terms of every cell, one workgroup per cell: per-cell FP64
 // totals A^t, V^t and centroid (the K-Gather), then per bond the spring,
 // viscous and random forces, then per vertex the sum of its bond forces, the
-// area/volume constraint forces (K-Apply) and bending, added into F (sorted
-// order) written to Fm[rbc_voff[r] + v] (overwritten, not accumulated), so
-// the kernel can run beside the pair kernel.  lds_bytes =
-// membrane_lds_bytes(max nv, max nbond).
-size_t membrane_lds_bytes(int max_nv, int max_nbond);
-void launch_membrane(const MembraneConst &mc, const BoxDev *boxes, const MeshDev *meshes,
-                     const int32_t *rbc_mesh, const int32_t *rbc_box, const int64_t *rbc_first,
-                     const int64_t *rbc_voff, int nrbc, State s,
-                     const uint32_t *slot_of_gid, double *av, double *centroid,
-                     const uint32_t *kdev, float *Fm, uint32_t *err, size_t lds_bytes,
-                     SurrUse su, hipStream_t st);
+// area/volume constraint forces (K-Apply) and bending, written to
+// Fm[rbc_voff[r] + v] (overwritten, not accumulated), so the kernel can run
+// beside the pair kernel.  lds_bytes = membrane_lds_bytes(max nv).
+size_t membrane_lds_bytes(int max_nv);
+void launch_membrane(const MemArgs &ma, const BoxDev *boxes, State s, const uint32_t *kdev,
+                     uint32_t *err, size_t lds_bytes, hipStream_t st);
+
+// Pair forces and fluxes, cell-tiled kernel (sheared: some box has
+// Lees-Edwards boundaries).  With ma.nrbc > 0 the launch also takes the
+// membrane terms of every cell, one cell per extra workgroup (only if
+// pair_tiled_takes_membrane for the shape).  Returns false for a shape that
+// is not built.
+bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
+                       const uint32_t *cell_start, int64_t ncell,
+                       int64_t n, const uint32_t *kdev, float *F, float *Q,
+                       unsigned long long *nzero, uint32_t *err, const PairTile &tile,
+                       bool sheared, const MemArgs &ma, hipStream_t st);
+// Whether a workgroup of the shape has the LDS for one cell of max_nv vertices.
+bool pair_tiled_takes_membrane(const PairTile &t, int n_species, bool sheared, int max_nv);
 
 // ------------------------------------------------------------ surrogate
 constexpr int kSurrIn = 20, kSurrHid = 128, kSurrOut = 3;

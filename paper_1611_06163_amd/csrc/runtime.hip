@@ -116,10 +116,14 @@ struct tdpd_sys {
   PairTile tile{4, 2, 1, 1};  // shape of the cell-tiled kernel
   int bin_mode = 0;     // 0: counting (one-digit stable) sort, 1: LSD radix sort
   bool use_graph = true;
+  bool fuse_membrane = true;  // cells handled by the first workgroups of the pair kernel
   uint32_t *kdev = nullptr;       // device step counter read by the kernels
   uint32_t kdev_val = 0;          // host mirror of *kdev
   uint32_t *cell_count = nullptr, *bin_tmp = nullptr, *tile_sum = nullptr;
   float *Fm = nullptr;            // membrane forces by global vertex [nvert][3]
+  float *Fb = nullptr;            // per-bond membrane forces [nrbc][3][bond_stride]
+  int64_t bond_stride = 0;
+  int max_nv = 0;
   // membrane surrogate (bending + local area from the network)
   bool surr_on = false;
   int surr_every = 0;             // fallback check interval (steps)
@@ -330,6 +334,7 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
   if (const char *e = std::getenv("TDPD_PAIR_KERNEL")) s->pair_kernel = std::atoi(e);
   if (const char *e = std::getenv("TDPD_BIN")) s->bin_mode = std::atoi(e);
   if (const char *e = std::getenv("TDPD_GRAPH")) s->use_graph = std::atoi(e) != 0;
+  if (const char *e = std::getenv("TDPD_FUSE_MEMBRANE")) s->fuse_membrane = std::atoi(e) != 0;
   if (const char *e = std::getenv("TDPD_TILE")) {  // "waves,chunks,split,filter"
     PairTile t{};
     if (std::sscanf(e, "%d,%d,%d,%d", &t.waves, &t.chunks, &t.split, &t.filter) == 4 &&
@@ -614,7 +619,7 @@ extern "C" int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref, int32_t
     for (int q = 0; q < 3; ++q) r2 += (ref[3 * v + q] - cen[q]) * (ref[3 * v + q] - cen[q]);
     M.max_radius = std::max(M.max_radius, std::sqrt(r2));
   }
-  if (membrane_lds_bytes(M.nv, int(M.bond_ab.size())) > 60 * 1024)
+  if (membrane_lds_bytes(M.nv) > 60 * 1024)
     return s->fail(TDPD_ERR_UNSUPPORTED, "add_mesh: mesh too large for one workgroup's LDS");
   s->meshes.push_back(std::move(M));
   if (mesh_id) *mesh_id = int32_t(s->meshes.size() - 1);
@@ -777,7 +782,9 @@ static int prepare(tdpd_sys *s) {
       D.dih_inc = di;
       D.dih_role = dr;
       D.A0t = a0t;
-      s->mem_lds = std::max(s->mem_lds, membrane_lds_bytes(M.nv, D.nbond));
+      s->mem_lds = std::max(s->mem_lds, membrane_lds_bytes(M.nv));
+      s->bond_stride = std::max<int64_t>(s->bond_stride, D.nbond);
+      s->max_nv = std::max(s->max_nv, M.nv);
       D.A0 = float(M.A0);
       D.V0 = float(M.V0);
       D.theta0 = float(M.theta0);
@@ -833,7 +840,8 @@ static int prepare(tdpd_sys *s) {
       return rc;
     s->d_av = dallocT<double>(s, 2 * size_t(nrbc));
     s->Fm = dallocT<float>(s, 3 * size_t(s->nvert));
-    if (!s->d_av || !s->Fm) return s->fail(TDPD_ERR_OOM, "device allocation failed");
+    s->Fb = dallocT<float>(s, 3 * size_t(nrbc) * size_t(s->bond_stride));
+    if (!s->d_av || !s->Fm || !s->Fb) return s->fail(TDPD_ERR_OOM, "device allocation failed");
     if (!s->st2) {
       HIPCHK(hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
@@ -866,6 +874,29 @@ static int prepare(tdpd_sys *s) {
   HIPCHK(hipStreamSynchronize(s->st));  // host vectors may be released after this
   s->uploaded = true;
   return TDPD_OK;
+}
+
+// Cells from which the pair kernel takes the membrane terms itself.
+constexpr int kFuseMinCells = 16;
+
+// Membrane arguments of all cells (nrbc 0 when the system has none).
+static MemArgs mem_args(const tdpd_sys *s, const MembraneConst &mc, float *Fm_out, SurrUse su) {
+  MemArgs m{};
+  m.mc = mc;
+  m.meshes = s->d_meshes;
+  m.rbc_mesh = s->d_rbc_mesh;
+  m.rbc_box = s->d_rbc_box;
+  m.rbc_first = s->d_rbc_first;
+  m.rbc_voff = s->d_rbc_voff;
+  m.slot_of_gid = s->slot_of_gid;
+  m.av = s->d_av;
+  m.centroid = s->d_centroid;
+  m.Fm = Fm_out;
+  m.Fb = s->Fb;
+  m.bond_stride = s->bond_stride;
+  m.su = su;
+  m.nrbc = int(s->rbc_mesh.size());
+  return m;
 }
 
 // Whether consecutive integrated steps may fold one step's closing kick
@@ -906,8 +937,20 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   }
   s->phase_end(1, tb, st);
   s->cur_A = !s->cur_A;
-  // membrane terms on the second stream, beside the pair kernel
-  if (nrbc > 0) {
+  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
+  // one-thread-per-particle kernel; it also packs a slot into 26 bits
+  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
+  const bool tiled = !(s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26));
+  // Many cells are taken by the first workgroups of the tiled pair kernel
+  // (one launch, no second stream).  A cell's workgroup then shares its CU
+  // with pair workgroups and takes longer than the pair work when it is one
+  // of a few, so few cells, the surrogate, the simple pair kernel, a timed
+  // membrane phase or a mesh too large for the pair kernel's LDS take the
+  // separate membrane kernel on the second stream beside the pair kernel.
+  const bool fused = nrbc >= kFuseMinCells && tiled && s->fuse_membrane && !s->surr_on &&
+                     !(s->timing_mask & (1 << 2)) &&
+                     pair_tiled_takes_membrane(s->tile, s->S, s->any_shear, s->max_nv);
+  if (nrbc > 0 && !fused) {
     (void)hipEventRecord(s->ev_fork, st);
     (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
     const bool tm = s->phase_begin(2, s->st2);
@@ -924,32 +967,28 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
       ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
       ml.local_only = 1;
       ml.gate = s->surr_every;
-      launch_membrane(ml, s->d_boxes, s->d_meshes, s->d_rbc_mesh, s->d_rbc_box, s->d_rbc_first,
-                      s->d_rbc_voff, nrbc, s->cur(), s->slot_of_gid, s->d_av, s->d_centroid,
-                      s->kdev, s->sd.Fp, s->errw, s->mem_lds, SurrUse{nullptr, nullptr}, s->st2);
+      launch_membrane(mem_args(s, ml, s->sd.Fp, SurrUse{nullptr, nullptr}), s->d_boxes, s->cur(),
+                      s->kdev, s->errw, s->mem_lds, s->st2);
       launch_surr_check(s->sd, nrbc, s->kdev, s->surr_every, s->st2);
       su = SurrUse{s->sd.flag, s->sd.Fs};
     }
-    launch_membrane(s->mc, s->d_boxes, s->d_meshes, s->d_rbc_mesh, s->d_rbc_box, s->d_rbc_first,
-                    s->d_rbc_voff, nrbc,
-                    s->cur(), s->slot_of_gid, s->d_av, s->d_centroid, s->kdev, s->Fm, s->errw,
-                    s->mem_lds, su, s->st2);
+    launch_membrane(mem_args(s, s->mc, s->Fm, su), s->d_boxes, s->cur(), s->kdev, s->errw,
+                    s->mem_lds, s->st2);
     s->phase_end(2, tm, s->st2);
     (void)hipEventRecord(s->ev_join, s->st2);
   }
   const bool tp = s->phase_begin(0, st);
-  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
-  // one-thread-per-particle kernel; it also packs a slot into 26 bits
-  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
-  if (s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26)) {
+  if (!tiled) {
     launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
                        s->Q, s->nzero, s->errw, st);
   } else {
+    MemArgs ma = mem_args(s, s->mc, s->Fm, SurrUse{nullptr, nullptr});
+    if (!fused) ma.nrbc = 0;
     (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, n, s->kdev,
-                            s->F, s->Q, s->nzero, s->errw, s->tile, s->any_shear, st);
+                            s->F, s->Q, s->nzero, s->errw, s->tile, s->any_shear, ma, st);
   }
   s->phase_end(0, tp, st);
-  if (nrbc > 0) (void)hipStreamWaitEvent(st, s->ev_join, 0);
+  if (nrbc > 0 && !fused) (void)hipStreamWaitEvent(st, s->ev_join, 0);
   if (!fuse_next) {
     const bool tk = s->phase_begin(3, st);
     launch_postkick(s->pc, s->cur(), s->F, s->Q, n, vmap, integrate, s->kdev, st);
@@ -1388,8 +1427,10 @@ extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
     for (int i = 0; i < kNumPairTiles; ++i) {
       const PairTile &t = kPairTiles[i];
       auto launch = [&]() {
+        MemArgs none{};  // the shapes are timed on the pair work alone
         (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, s->n,
-                                s->kdev, s->F, s->Q, s->nzero, s->errw, t, s->any_shear, s->st);
+                                s->kdev, s->F, s->Q, s->nzero, s->errw, t, s->any_shear, none,
+                                s->st);
       };
       launch();  // warm-up
       (void)hipEventRecord(e0, s->st);
@@ -1498,7 +1539,6 @@ extern "C" int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *o
   if (rc) return rc;
   if (s->rbc_mesh.empty()) return s->fail(TDPD_ERR_STATE, "surrogate_sample: no cells");
   if ((rc = surr_alloc(s))) return rc;
-  const int nrbc = int(s->rbc_mesh.size());
   const int64_t nv = s->nvert;
   // the state is that of the last evaluation (counter kdev_val); the device
   // counter already holds the next step's
@@ -1509,9 +1549,8 @@ extern "C" int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *o
   ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
   ml.local_only = 1;
   ml.gate = 0;
-  launch_membrane(ml, s->d_boxes, s->d_meshes, s->d_rbc_mesh, s->d_rbc_box, s->d_rbc_first,
-                  s->d_rbc_voff, nrbc, s->cur(), s->slot_of_gid, s->d_av, s->d_centroid, s->kdev,
-                  s->sd.Fp, s->errw, s->mem_lds, SurrUse{nullptr, nullptr}, s->st);
+  launch_membrane(mem_args(s, ml, s->sd.Fp, SurrUse{nullptr, nullptr}), s->d_boxes, s->cur(),
+                  s->kdev, s->errw, s->mem_lds, s->st);
   // targets go through Fs, which the next step's surrogate pass rewrites
   launch_surr_targets(s->sd, s->sd.Fs, nv, s->st);
   launch_set_counter(s->kdev, s->kdev_val + 1u, s->st);

@@ -58,7 +58,7 @@ def test_pair_sets_bit_exact(name, which):
 
 
 @pytest.mark.parametrize("kernel", [0, 1])
-@pytest.mark.parametrize("name", ["c1", "cluster", "c1_randflux", "c2", "c3_small"])
+@pytest.mark.parametrize("name", ["c1", "cluster", "c1_randflux", "c2", "c3_small", "c3_cells"])
 def test_teacher_forced_forces(kernel, name):
     if name == "c1":
         cfg = I.c1()
@@ -69,6 +69,8 @@ def test_teacher_forced_forces(kernel, name):
         cfg.m_s = 0.05
     elif name == "c2":
         cfg = I.c2()
+    elif name == "c3_cells":  # enough cells for the pair kernel to take them
+        cfg = I.c3(scale=0.25, n_cells=20)
     else:
         cfg = I.c3(scale=0.25, n_cells=2)
     sysg = gpu_system(cfg, kernel=kernel)
@@ -218,6 +220,31 @@ def test_empty_and_single_particle():
     s.step(3)
     F, Q = s.get_forces()
     assert np.all(F == 0) and np.all(Q == 0)
+
+
+def test_membrane_in_pair_kernel_equals_separate_kernel():
+    """With 20 cells the tiled pair kernel's first workgroups take the
+    membrane terms; the separate membrane kernel on the second stream gives
+    the same forces up to the order of the FP64 cell sums, and both runs
+    step alike."""
+    cfg = I.c3(scale=0.25, n_cells=20)
+    out = []
+    for fuse in ("1", "0"):
+        s = gpu_system(cfg, kernel=1, env={"TDPD_FUSE_MEMBRANE": fuse})
+        s.tile = (2, 2, 1, 0)
+        s.compute_forces(5)
+        F, Q = s.get_forces()
+        d = s.diagnostics()
+        s.step(3)
+        x, _, _ = s.get_state()
+        out.append((F, Q, d["av"], x))
+        s.close()
+    (F1, Q1, av1, x1), (F0, Q0, av0, x0) = out
+    scale = np.abs(F0).max()
+    assert np.abs(F1 - F0).max() <= 1e-5 * scale
+    assert np.array_equal(Q1, Q0)
+    assert np.allclose(av1, av0, rtol=1e-12, atol=0)
+    assert np.abs(x1.astype(np.float64) - x0).max() < 1e-4
 
 
 def test_full_size_sampled_c3():
