@@ -1,6 +1,7 @@
 // kernels_core.hip -- binning (LSD radix sort of cell keys), reordering,
 // velocity-Verlet kicks, diagnostics and gid-order gathers.
 #include "launch.h"
+#include "membrane_cell.h"
 
 namespace tdpd {
 
@@ -331,15 +332,26 @@ __global__ void __launch_bounds__(kScanThreads) k_count_tiles(const uint32_t *__
 
 // Exclusive scan of the cell counts into cell_start (tile prefix from the
 // tile sums, then a block scan of the tile); clears the counts.
+// Workgroups past the scan tiles take the membrane K-Gather and bond forces
+// of one cell share each (membrane_elements).
 __global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restrict__ count,
-                                                             int64_t ncell,
+                                                             int64_t ncell, int ntiles,
                                                              const uint32_t *__restrict__ tile_sum,
                                                              uint32_t *__restrict__ start,
-                                                             uint32_t *__restrict__ advance) {
-  if (advance && blockIdx.x == 0 && threadIdx.x == 0) *advance += 1u;  // nothing here reads it
+                                                             MemArgs ma, int eparts,
+                                                             const BoxDev *__restrict__ boxes,
+                                                             State s,
+                                                             const uint32_t *__restrict__ kdev,
+                                                             int kofs, uint32_t *err) {
   __shared__ uint32_t sh[kScanThreads];
   __shared__ uint32_t tile[kCellTile];
   const int t = threadIdx.x;
+  if (int(blockIdx.x) >= ntiles) {
+    const int q = int(blockIdx.x) - ntiles;
+    membrane_elements(ma, boxes, s, *kdev + uint32_t(kofs), err, q / eparts, q % eparts, eparts,
+                      reinterpret_cast<char *>(tile));
+    return;
+  }
   const int64_t c0 = int64_t(blockIdx.x) * kCellTile;
   // prefix of the earlier tiles
   uint32_t pre = 0;
@@ -373,16 +385,26 @@ __global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restric
     const int64_t c = c0 + q * kScanThreads + t;
     if (c < ncell) start[c] = tile[q * kScanThreads + t];
   }
-  if (blockIdx.x == gridDim.x - 1 && t == kScanThreads - 1) start[ncell] = ex + a0 + a1 + a2 + a3;
+  if (int(blockIdx.x) == ntiles - 1 && t == kScanThreads - 1) start[ncell] = ex + a0 + a1 + a2 + a3;
 }
 
 int64_t count_scan_tiles(int64_t ncell) { return ncell > 0 ? (ncell + kCellTile - 1) / kCellTile : 1; }
 
+int membrane_element_parts(int64_t max_nbond) {
+  return max_nbond > kScanThreads ? int((max_nbond + kScanThreads - 1) / kScanThreads) : 1;
+}
+
+bool scan_takes_membrane(int max_nv) {
+  return membrane_cell_lds(max_nv, kScanThreads) <= sizeof(uint32_t) * kCellTile;
+}
+
 __global__ void __launch_bounds__(256) k_scatter_rank(const uint32_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ rank,
                                                       const uint32_t *__restrict__ start, int64_t n,
-                                                      uint32_t *__restrict__ tmp) {
+                                                      uint32_t *__restrict__ tmp,
+                                                      uint32_t *__restrict__ advance) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (advance && i == 0) *advance += 1u;  // nothing in this launch reads it
   if (i >= n) return;
   tmp[start[keys[i]] + rank[i]] = uint32_t(i);
 }
@@ -425,16 +447,21 @@ __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uin
 void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
                          uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
                          uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
-                         uint32_t *keys_sorted, uint32_t *advance, hipStream_t st) {
+                         uint32_t *keys_sorted, uint32_t *advance, const MemArgs &membrane,
+                         const BoxDev *boxes, const uint32_t *kdev, int kofs, uint32_t *err,
+                         hipStream_t st) {
   const int64_t nt = count_scan_tiles(ncell);
   if (nt > 1)  // one tile needs no tile prefix
     hipLaunchKernelGGL(k_count_tiles, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count,
                        ncell, tile_sum);
-  hipLaunchKernelGGL(k_count_scan, dim3(unsigned(nt)), dim3(kScanThreads), 0, st, cell_count, ncell,
-                     tile_sum, cell_start, advance);
+  const int eparts = membrane_element_parts(membrane.bond_stride);
+  const int64_t nmem = membrane.nrbc > 0 ? int64_t(membrane.nrbc) * eparts : 0;
+  hipLaunchKernelGGL(k_count_scan, dim3(unsigned(nt + nmem)), dim3(kScanThreads), 0, st, cell_count,
+                     ncell, int(nt), tile_sum, cell_start, membrane, eparts, boxes, src, kdev, kofs,
+                     err);
   if (n <= 0) return;
   const dim3 g(unsigned((n + 255) / 256));
-  hipLaunchKernelGGL(k_scatter_rank, g, dim3(256), 0, st, keys, rank, cell_start, n, tmp);
+  hipLaunchKernelGGL(k_scatter_rank, g, dim3(256), 0, st, keys, rank, cell_start, n, tmp, advance);
   hipLaunchKernelGGL(k_rank_gather, g, dim3(256), 0, st, src, dst, tmp, keys, cell_start, n, nspec,
                      slot_of_gid, keys_sorted);
 }

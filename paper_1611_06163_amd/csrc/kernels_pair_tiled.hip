@@ -157,15 +157,20 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
                                                             float *__restrict__ F,
                                                             float *__restrict__ Q,
                                                             unsigned long long *nzero,
-                                                            uint32_t *err, MemArgs ma, int nmemb) {
+                                                            uint32_t *err, MemArgs ma, int nmemb,
+                                                            int vparts) {
   __shared__ TiledShared<NS, W, SH> sh;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t k = *kdev;  // random-number step counter
-  // the first nmemb workgroups (a multiple of 8) take the membrane terms of
-  // one cell each, in this workgroup's LDS; they run beside the pair work
+  // the first nmemb workgroups (a multiple of 8) take the per-vertex
+  // membrane terms of a share of one cell each (K-Gather and bond forces
+  // came from the binning launch), in this workgroup's LDS, beside the pair
+  // work
   if (int(blockIdx.x) < nmemb) {
-    if (int(blockIdx.x) < ma.nrbc)
-      membrane_cell(ma, boxes, s, k, err, int(blockIdx.x), reinterpret_cast<char *>(&sh));
+    const int q = int(blockIdx.x);
+    if (q < ma.nrbc * vparts)
+      membrane_vertices(ma, boxes, s, k, err, q / vparts, q % vparts, vparts,
+                        reinterpret_cast<char *>(&sh));
     return;
   }
   // consecutive workgroups go to different XCDs; give each XCD a contiguous
@@ -581,17 +586,19 @@ static void launch_shape(const PairConst &pc, const BoxDev *boxes, State s,
                          const uint32_t *kdev, float *F, float *Q, unsigned long long *nzero,
                          uint32_t *err, bool sheared, const MemArgs &ma, hipStream_t st) {
   const int64_t per_xcd = (ncell * split + 7) / 8;
-  const int nmemb = (ma.nrbc + 7) / 8 * 8;
+  // one thread per vertex in the membrane workgroups
+  const int vparts = ma.nrbc > 0 ? (ma.max_nv + 64 * W - 1) / (64 * W) : 0;
+  const int nmemb = (ma.nrbc * vparts + 7) / 8 * 8;
   const dim3 grid(unsigned(per_xcd * 8 + nmemb)), block(64 * W);
   // the sheared-row variant costs registers: only systems with a sheared box get it
   if (sheared)
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, true>), grid, block, 0, st, pc, boxes, s,
                        cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err, ma,
-                       nmemb);
+                       nmemb, vparts);
   else
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, false>), grid, block, 0, st, pc, boxes, s,
                        cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err, ma,
-                       nmemb);
+                       nmemb, vparts);
 }
 
 template <int NS>

@@ -8,89 +8,6 @@
 
 namespace tdpd {
 
-// Radix sort of (key, value) u32 pairs; keys < 2^key_bits.  tmp buffers of
-// the same length; hist needs radix_hist_words(n) words.  Result in
-// keys_out/vals_out.  Stable.
-size_t radix_hist_words(int64_t n);
-void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
-                uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, uint32_t *hist,
-                int64_t n, int key_bits, hipStream_t st);
-
-// Membrane forces of an evaluation, indexed by global vertex (launch_membrane).
-struct VertexMap {
-  const float *Fm;          // [nvert][3] or null
-  const int64_t *rbc_first; // [nrbc]
-  const int64_t *rbc_voff;  // [nrbc]
-};
-// First half kick + drift + walls + wrap + cell key (one thread per particle).
-// With cell_count, vals gets the particle's unordered rank in its cell (the
-// counting binning); else vals = index (the radix binning).  *kdev is the
-// counter of this evaluation (sheared boxes take its image offsets).
-// finish: the previous step's closing work (launch_postkick's, with `prev`
-// its membrane forces) is done first, per particle, with the same
-// arithmetic; the counter is then not yet advanced, so this evaluation's is
-// *kdev + 1 (the binning advances it: launch_bin_counting's advance).
-void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
-                    const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
-                    uint32_t *cell_count, uint32_t *kdev, bool finish, VertexMap prev,
-                    hipStream_t st);
-// Counting binning after launch_prekick: scan of the cell counts into
-// cell_start (counts zeroed for the next step; tile_sum holds
-// count_scan_tiles(ncell) words), scatter, and the rank fix-up fused with
-// the reorder of every state plane into dst (slot_of_gid and the sorted keys
-// updated).  Same permutation as the stable radix sort.
-int64_t count_scan_tiles(int64_t ncell);
-// With advance, the scan also advances the step counter *advance by one.
-void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
-                         uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
-                         uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
-                         uint32_t *keys_sorted, uint32_t *advance, hipStream_t st);
-// cell_start[c] = first sorted index of cell c, cell_start[ncell] = n.
-void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
-                        uint32_t *cell_start, hipStream_t st);
-// dst[p] = src[perm[p]] for every state plane; slot_of_gid[gid] = p.
-void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
-                    uint32_t *slot_of_gid, hipStream_t st);
-// Adds the membrane forces Fm (indexed by global vertex, see launch_membrane)
-// into F, then (integrate) the second half kick of mobile particles; ends
-// the evaluation by advancing the device step counter *kdev by one (the
-// kernels of an evaluation at counter k all read k; the next step reads
-// k + 1).
-void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,
-                     VertexMap vm, bool integrate, uint32_t *kdev, hipStream_t st);
-// Sets *kdev = k.
-void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st);
-
-// Pair forces and fluxes, one thread per particle (sorted order).
-// The random-number step counter k is read from device memory (*kdev) so a
-// captured graph of a step stays valid from step to step.
-void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
-                        const uint32_t *cell_keys,
-                        const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
-                        float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st);
-// Tile shape of the cell-tiled pair kernel: wavefronts per workgroup,
-// 64-candidate chunks per wavefront held in registers, workgroups per cell,
-// and whether the 27-cell stencil is first filtered against the home cell's
-// box (1) or tested whole (0).
-struct PairTile {
-  int waves, chunks, split, filter;
-};
-extern const PairTile kPairTiles[];  // the shapes the kernel is built for
-extern const int kNumPairTiles;
-// Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
-void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
-                      const uint32_t *cell_keys,
-                      const uint32_t *cell_start, int64_t n, float rcut2, uint32_t k,
-                      int32_t *out, int64_t cap, unsigned long long *count, hipStream_t st);
-
-// FP64 diagnostics in fixed order: [P0,P1,P2, sum v^2, n_mobile, C_0..C_{S-1}]
-void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hipStream_t st);
-
-// Copy (AoS <-> SoA) in gid order.
-void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, int nspec,
-                             const float *F, const float *Q, float *pos, float *vel, float *conc,
-                             float *Fo, float *Qo, hipStream_t st);
-
 // ------------------------------------------------------------- membrane
 struct MeshDev {
   int nv, ntri, nbond;
@@ -139,7 +56,103 @@ struct MemArgs {
   int64_t bond_stride;                   // >= nbond of every mesh
   SurrUse su;
   int nrbc;
+  int max_nv;                            // largest mesh
 };
+
+// Radix sort of (key, value) u32 pairs; keys < 2^key_bits.  tmp buffers of
+// the same length; hist needs radix_hist_words(n) words.  Result in
+// keys_out/vals_out.  Stable.
+size_t radix_hist_words(int64_t n);
+void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_tmp,
+                uint32_t *vals_tmp, uint32_t *keys_out, uint32_t *vals_out, uint32_t *hist,
+                int64_t n, int key_bits, hipStream_t st);
+
+// Membrane forces of an evaluation, indexed by global vertex (launch_membrane).
+struct VertexMap {
+  const float *Fm;          // [nvert][3] or null
+  const int64_t *rbc_first; // [nrbc]
+  const int64_t *rbc_voff;  // [nrbc]
+};
+// First half kick + drift + walls + wrap + cell key (one thread per particle).
+// With cell_count, vals gets the particle's unordered rank in its cell (the
+// counting binning); else vals = index (the radix binning).  *kdev is the
+// counter of this evaluation (sheared boxes take its image offsets).
+// finish: the previous step's closing work (launch_postkick's, with `prev`
+// its membrane forces) is done first, per particle, with the same
+// arithmetic; the counter is then not yet advanced, so this evaluation's is
+// *kdev + 1 (the binning advances it: launch_bin_counting's advance).
+void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
+                    const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
+                    uint32_t *cell_count, uint32_t *kdev, bool finish, VertexMap prev,
+                    hipStream_t st);
+// Counting binning after launch_prekick: scan of the cell counts into
+// cell_start (counts zeroed for the next step; tile_sum holds
+// count_scan_tiles(ncell) words), scatter, and the rank fix-up fused with
+// the reorder of every state plane into dst (slot_of_gid and the sorted keys
+// updated).  Same permutation as the stable radix sort.
+int64_t count_scan_tiles(int64_t ncell);
+// With advance, the scatter also advances the step counter *advance by one.
+// With membrane (nrbc > 0), the scan's launch also takes the K-Gather and the
+// bond forces of every cell (membrane_elements, `eparts` workgroups per
+// cell, counter *kdev + kofs), on the state before the reorder; the pair
+// kernel then takes the per-vertex part (launch_pair_tiled).
+void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint32_t *rank,
+                         uint32_t *cell_count, int64_t ncell, uint32_t *cell_start, uint32_t *tmp,
+                         uint32_t *tile_sum, int64_t n, int nspec, uint32_t *slot_of_gid,
+                         uint32_t *keys_sorted, uint32_t *advance, const MemArgs &membrane,
+                         const BoxDev *boxes, const uint32_t *kdev, int kofs, uint32_t *err,
+                         hipStream_t st);
+// Workgroups per cell of the scan launch's membrane part; whether its LDS
+// holds a cell of max_nv vertices.
+int membrane_element_parts(int64_t max_nbond);
+bool scan_takes_membrane(int max_nv);
+// cell_start[c] = first sorted index of cell c, cell_start[ncell] = n.
+void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
+                        uint32_t *cell_start, hipStream_t st);
+// dst[p] = src[perm[p]] for every state plane; slot_of_gid[gid] = p.
+void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
+                    uint32_t *slot_of_gid, hipStream_t st);
+// Adds the membrane forces Fm (indexed by global vertex, see launch_membrane)
+// into F, then (integrate) the second half kick of mobile particles; ends
+// the evaluation by advancing the device step counter *kdev by one (the
+// kernels of an evaluation at counter k all read k; the next step reads
+// k + 1).
+void launch_postkick(const PairConst &pc, State s, float *F, const float *Q, int64_t n,
+                     VertexMap vm, bool integrate, uint32_t *kdev, hipStream_t st);
+// Sets *kdev = k.
+void launch_set_counter(uint32_t *kdev, uint32_t k, hipStream_t st);
+
+// Pair forces and fluxes, one thread per particle (sorted order).
+// The random-number step counter k is read from device memory (*kdev) so a
+// captured graph of a step stays valid from step to step.
+void launch_pair_simple(const PairConst &pc, const BoxDev *boxes, State s,
+                        const uint32_t *cell_keys,
+                        const uint32_t *cell_start, int64_t n, const uint32_t *kdev, float *F,
+                        float *Q, unsigned long long *nzero, uint32_t *err, hipStream_t st);
+// Tile shape of the cell-tiled pair kernel: wavefronts per workgroup,
+// 64-candidate chunks per wavefront held in registers, workgroups per cell,
+// and whether the 27-cell stencil is first filtered against the home cell's
+// box (1) or tested whole (0).
+struct PairTile {
+  int waves, chunks, split, filter;
+};
+extern const PairTile kPairTiles[];  // the shapes the kernel is built for
+extern const int kNumPairTiles;
+// Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
+void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
+                      const uint32_t *cell_keys,
+                      const uint32_t *cell_start, int64_t n, float rcut2, uint32_t k,
+                      int32_t *out, int64_t cap, unsigned long long *count, hipStream_t st);
+
+// FP64 diagnostics in fixed order: [P0,P1,P2, sum v^2, n_mobile, C_0..C_{S-1}]
+void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hipStream_t st);
+
+// Copy (AoS <-> SoA) in gid order.
+void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, int nspec,
+                             const float *F, const float *Q, float *pos, float *vel, float *conc,
+                             float *Fo, float *Qo, hipStream_t st);
+
+
 // All membrane terms of every cell, one workgroup per cell: per-cell FP64
 // totals A^t, V^t and centroid (the K-Gather), then per bond the spring,
 // viscous and random forces, then per vertex the sum of its bond forces, the

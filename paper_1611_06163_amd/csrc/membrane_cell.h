@@ -1,17 +1,19 @@
-// membrane_cell.h -- the RBC membrane terms of one cell (Section 2.2), for
-// one workgroup of any multiple of 64 threads:
+// membrane_cell.h -- the RBC membrane terms of one cell (Section 2.2) for
+// workgroups of any multiple of 64 threads, in three parts:
 //   1. K-Gather: per-triangle area and volume (FP32) summed in FP64 over the
-//      cell in a fixed order, plus the centroid update;
+//      cell in a fixed order (A^t, V^t into av), plus the centroid update;
 //   2. per bond, once: WLC + POW spring (Eqs. 13-14), viscosity (Eq. 15) and
-//      its random partner (Eq. 16), kept in a per-cell scratch row;
+//      its random partner (Eq. 16), into the cell's scratch row;
 //   3. per vertex: the signed sum of its bond forces, the global/local area
 //      and volume constraint forces over its incident triangles (K-Apply,
 //      Eqs. 17-18; each triangle recomputed by its three vertices as the
 //      paper does, Section 3.3) and bending over its incident dihedrals
 //      (Eq. 19), written to Fm.
-// No atomics; every sum has a fixed order for a given workgroup size.  Run
-// by the standalone membrane kernel and by the first workgroups of the
-// cell-tiled pair kernel.
+// membrane_cell runs all three in one workgroup (the membrane kernel);
+// membrane_elements runs 1 and a share of 2 (extra workgroups of the cell
+// count scan) and membrane_vertices a share of 3 (extra workgroups of the
+// pair kernel), the launch boundary between them ordering the parts.
+// No atomics; every sum has a fixed order for a given workgroup size.
 #pragma once
 
 #include "launch.h"
@@ -60,170 +62,193 @@ __host__ __device__ constexpr size_t membrane_cell_lds(int nv, int threads) {
   return (size_t(nv) * 16 + 7) / 8 * 8 + (size_t(threads / 64) * 5 + 5) * sizeof(double);
 }
 
-__device__ __forceinline__ void membrane_cell(const MemArgs &ma, const BoxDev *__restrict__ boxes,
-                                              const State &s, uint32_t k, uint32_t *err, int r,
-                                              char *lds) {
-  using namespace mem;
+namespace mem {
+
+// One cell as seen by a workgroup: mesh, box, staged positions.
+struct Cell {
+  const MeshDev *M;
+  const BoxDev *B;
+  int nv;
+  int64_t g0;
+  LeOff le;
+  const uint32_t *sl;
+  const float *px, *py, *pz;
+  __device__ float3 P(int v) const { return make_float3(px[v], py[v], pz[v]); }
+  __device__ float3 rel(float3 a, float3 o) const { return le_rel(*B, a, o, le.delta, nullptr); }
+};
+
+// Stage the cell's vertex slots and positions in LDS (every thread calls it).
+__device__ __forceinline__ Cell stage_cell(const MemArgs &ma, const BoxDev *__restrict__ boxes,
+                                           const State &s, uint32_t k, int r, char *lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const MembraneConst &mc = ma.mc;
-  if (mc.gate > 0 && (k % uint32_t(mc.gate)) != 0u) return;
   const MeshDev &M = ma.meshes[ma.rbc_mesh[r]];
   const BoxDev &B = boxes[ma.rbc_box[r]];
   const int nv = M.nv;
   uint32_t *sl = reinterpret_cast<uint32_t *>(lds);
   float *px = reinterpret_cast<float *>(sl + nv), *py = px + nv, *pz = py + nv;
-  double *red = reinterpret_cast<double *>(lds + (size_t(nv) * 16 + 7) / 8 * 8);
-  double *tot = red + (nt / 64) * 5;
-  float *fb = ma.Fb + 3 * ma.bond_stride * r;  // [3][nbond] of this cell
   const int64_t g0 = ma.rbc_first[r];
-  const uint32_t *__restrict__ slot_of_gid = ma.slot_of_gid;
-  double *__restrict__ av = ma.av;
-  double *__restrict__ centroid = ma.centroid;
-  const int64_t *__restrict__ rbc_voff = ma.rbc_voff;
-  const SurrUse su = ma.su;
-  float *__restrict__ Fm = ma.Fm;
   for (int v = tid; v < nv; v += nt) {
-    const uint32_t q = slot_of_gid[g0 + v];
+    const uint32_t q = ma.slot_of_gid[g0 + v];
     sl[v] = q;
     px[v] = s.x[q];
     py[v] = s.y[q];
     pz[v] = s.z[q];
   }
   __syncthreads();
-  auto P = [&](int v) { return make_float3(px[v], py[v], pz[v]); };
-  const int terms = mc.terms;
   // nearest image (sheared boxes: Lees-Edwards image of the step counter)
-  const LeOff le = le_offsets(B, k, mc.dt);
-  auto rel = [&](float3 a, float3 o) { return le_rel(B, a, o, le.delta, nullptr); };
+  return Cell{&M, &B, nv, g0, le_offsets(B, k, ma.mc.dt), sl, px, py, pz};
+}
 
-  // ---- 1. K-Gather
-  {
-    const float3 cf = make_float3(float(centroid[3 * r]), float(centroid[3 * r + 1]),
-                                  float(centroid[3 * r + 2]));
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int t = tid; t < M.ntri; t += nt) {
-      const float3 a = rel(P(M.tri[3 * t]), cf);
-      const float3 b = rel(P(M.tri[3 * t + 1]), cf);
-      const float3 c = rel(P(M.tri[3 * t + 2]), cf);
-      const float3 nn = crs(sub(b, a), sub(c, a));
-      acc[0] += double(0.5f * sqrtf(dt3(nn, nn)));
-      acc[1] += double(dt3(a, crs(b, c)) * (1.f / 6.f));
-    }
-    for (int v = tid; v < nv; v += nt) {
-      const float3 a = rel(P(v), cf);
-      acc[2] += a.x;
-      acc[3] += a.y;
-      acc[4] += a.z;
-    }
-    // fixed-order sums: a butterfly inside each wavefront (partners add the
-    // same two values, so every lane ends with the same bits), then the
-    // wavefront totals in wavefront order
-#pragma unroll
-    for (int f = 0; f < 5; ++f) {
-      double a = acc[f];
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) a += __shfl_xor(a, off);
-      if ((tid & 63) == 0) red[(tid >> 6) * 5 + f] = a;
-    }
-    __syncthreads();
-    if (tid < 5) {
-      double a = 0.0;
-      for (int w = 0; w < nt / 64; ++w) a += red[w * 5 + tid];
-      tot[tid] = a;
-    }
-    __syncthreads();
-    if (tid == 0 && !mc.local_only) {
-      av[2 * r] = tot[0];
-      av[2 * r + 1] = tot[1];
-      centroid[3 * r] = double(cf.x) + tot[2] / nv;
-      centroid[3 * r + 1] = double(cf.y) + tot[3] / nv;
-      centroid[3 * r + 2] = double(cf.z) + tot[4] / nv;
-    }
+// 1. K-Gather: A^t, V^t into av[r], centroid[r] moved to the mean position.
+__device__ __forceinline__ void kgather(const MemArgs &ma, const Cell &C, int r, char *lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const MeshDev &M = *C.M;
+  double *red = reinterpret_cast<double *>(lds + (size_t(C.nv) * 16 + 7) / 8 * 8);
+  double *tot = red + (nt / 64) * 5;
+  const float3 cf = make_float3(float(ma.centroid[3 * r]), float(ma.centroid[3 * r + 1]),
+                                float(ma.centroid[3 * r + 2]));
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int t = tid; t < M.ntri; t += nt) {
+    const float3 a = C.rel(C.P(M.tri[3 * t]), cf);
+    const float3 b = C.rel(C.P(M.tri[3 * t + 1]), cf);
+    const float3 c = C.rel(C.P(M.tri[3 * t + 2]), cf);
+    const float3 nn = crs(sub(b, a), sub(c, a));
+    acc[0] += double(0.5f * sqrtf(dt3(nn, nn)));
+    acc[1] += double(dt3(a, crs(b, c)) * (1.f / 6.f));
   }
-
-  // ---- 2. bonds, Eqs. (13)-(16): force on the bond's first vertex a
-  if (terms & (TDPD_TERM_BOND | TDPD_TERM_BOND_VISCOUS | TDPD_TERM_BOND_RANDOM)) {
-    const float amp = sqrtf(2.f * mc.kT / mc.dt);
-    const float ct = sqrtf(2.f * M.gamma_t);
-    const float cc = sqrtf(fmaxf(3.f * M.gamma_c - M.gamma_t, 0.f)) * (1.f / 3.f);
-    for (int bnd = tid; bnd < M.nbond; bnd += nt) {
-      const int2 ab = M.bond_ab[bnd];
-      int nyb = 0;  // b taken in the sheared image below (-1) or above (+1) a
-      const float3 d = le_rel(B, P(ab.y), P(ab.x), le.delta, &nyb);  // a -> b
-      const float l = sqrtf(dt3(d, d));
-      const float il = 1.f / l;
-      float3 f = make_float3(0.f, 0.f, 0.f);
-      if (terms & TDPD_TERM_BOND) {
-        const float2 par = M.bond_par[bnd];  // (l_m, k_p)
-        const float x = l / par.x;
-        if (x >= 1.f) {
-          atomicOr(err, kErrOverext);
-        } else {
-          const float om = 1.f - x;
-          const float dwlc = mc.kT / M.p * (0.25f / (om * om) - 0.25f + x);
-          const float dpow = -par.y * powu_any(l, -M.m_pow);
-          const float fs = (dwlc + dpow) * il;
-          f.x += fs * d.x;
-          f.y += fs * d.y;
-          f.z += fs * d.z;
-        }
-      }
-      // e points from b to a (the paper's e_ij with i = a)
-      const float3 e = make_float3(-d.x * il, -d.y * il, -d.z * il);
-      if (terms & TDPD_TERM_BOND_VISCOUS) {
-        const uint32_t qa = sl[ab.x], qb = sl[ab.y];
-        const float3 vr = make_float3(s.vx[qa] - s.vx[qb] - float(nyb) * le.u, s.vy[qa] - s.vy[qb],
-                                      s.vz[qa] - s.vz[qb]);
-        const float ve = dt3(vr, e);
-        f.x += -M.gamma_t * vr.x - M.gamma_c * ve * e.x;
-        f.y += -M.gamma_t * vr.y - M.gamma_c * ve * e.y;
-        f.z += -M.gamma_t * vr.z - M.gamma_c * ve * e.z;
-      }
-      if (terms & TDPD_TERM_BOND_RANDOM) {
-        // a < b locally and gids are consecutive, so (g0+a, g0+b) is ordered;
-        // the counter takes box-local gids
-        const uint32_t ga = uint32_t(g0 + ab.x) - B.gid_base, gb = uint32_t(g0 + ab.y) - B.gid_base;
-        float W[12];  // streams 64..66: (cos, sin) of words (0,1) then (2,3); first 9 used
+  for (int v = tid; v < C.nv; v += nt) {
+    const float3 a = C.rel(C.P(v), cf);
+    acc[2] += a.x;
+    acc[3] += a.y;
+    acc[4] += a.z;
+  }
+  // fixed-order sums: a butterfly inside each wavefront (partners add the
+  // same two values, so every lane ends with the same bits), then the
+  // wavefront totals in wavefront order
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const u32x4 z = philox10(k, ga, gb, B.ctr3 | uint32_t(64 + q), B.seed_lo, B.seed_hi);
-          gauss2(z.a, z.b, W[4 * q], W[4 * q + 1]);
-          gauss2(z.c, z.d, W[4 * q + 2], W[4 * q + 3]);
-        }
-        const float trW = W[0] + W[4] + W[8];  // trace of W and of its symmetric part
-        const float ex[3] = {e.x, e.y, e.z};
-        float o[3];
+  for (int f = 0; f < 5; ++f) {
+    double a = acc[f];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          float acc = 0.f;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            float m = ct * (0.5f * (W[3 * i + j] + W[3 * j + i]) - (i == j ? trW * (1.f / 3.f) : 0.f));
-            if (i == j) m += cc * trW;
-            acc += m * ex[j];
-          }
-          o[i] = amp * acc;
-        }
-        f.x += o[0];
-        f.y += o[1];
-        f.z += o[2];
-      }
-      fb[bnd] = f.x;
-      fb[M.nbond + bnd] = f.y;
-      fb[2 * M.nbond + bnd] = f.z;
-    }
+    for (int off = 1; off < 64; off <<= 1) a += __shfl_xor(a, off);
+    if ((tid & 63) == 0) red[(tid >> 6) * 5 + f] = a;
   }
   __syncthreads();
+  if (tid < 5) {
+    double a = 0.0;
+    for (int w = 0; w < nt / 64; ++w) a += red[w * 5 + tid];
+    tot[tid] = a;
+  }
+  __syncthreads();
+  if (tid == 0 && !ma.mc.local_only) {
+    ma.av[2 * r] = tot[0];
+    ma.av[2 * r + 1] = tot[1];
+    ma.centroid[3 * r] = double(cf.x) + tot[2] / C.nv;
+    ma.centroid[3 * r + 1] = double(cf.y) + tot[3] / C.nv;
+    ma.centroid[3 * r + 2] = double(cf.z) + tot[4] / C.nv;
+  }
+}
 
-  // ---- 3. per vertex
-  const float cg = mc.local_only ? 0.f : float(M.kg * (tot[0] - M.A0) / M.A0);
-  const float cv = mc.local_only ? 0.f : float(M.kv * (tot[1] - M.V0) / M.V0);
+// 2. bonds [b0, b1), Eqs. (13)-(16): force on the bond's first vertex a,
+// into the cell's scratch row [3][nbond].
+__device__ __forceinline__ void bond_forces(const MemArgs &ma, const Cell &C, const State &s,
+                                            uint32_t k, uint32_t *err, int r, int b0, int b1) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const MeshDev &M = *C.M;
+  const BoxDev &B = *C.B;
+  const MembraneConst &mc = ma.mc;
+  const int terms = mc.terms;
+  if (!(terms & (TDPD_TERM_BOND | TDPD_TERM_BOND_VISCOUS | TDPD_TERM_BOND_RANDOM))) return;
+  float *fb = ma.Fb + 3 * ma.bond_stride * r;
+  const float amp = sqrtf(2.f * mc.kT / mc.dt);
+  const float ct = sqrtf(2.f * M.gamma_t);
+  const float cc = sqrtf(fmaxf(3.f * M.gamma_c - M.gamma_t, 0.f)) * (1.f / 3.f);
+  for (int bnd = b0 + tid; bnd < b1; bnd += nt) {
+    const int2 ab = M.bond_ab[bnd];
+    int nyb = 0;  // b taken in the sheared image below (-1) or above (+1) a
+    const float3 d = le_rel(B, C.P(ab.y), C.P(ab.x), C.le.delta, &nyb);  // a -> b
+    const float l = sqrtf(dt3(d, d));
+    const float il = 1.f / l;
+    float3 f = make_float3(0.f, 0.f, 0.f);
+    if (terms & TDPD_TERM_BOND) {
+      const float2 par = M.bond_par[bnd];  // (l_m, k_p)
+      const float x = l / par.x;
+      if (x >= 1.f) {
+        atomicOr(err, kErrOverext);
+      } else {
+        const float om = 1.f - x;
+        const float dwlc = mc.kT / M.p * (0.25f / (om * om) - 0.25f + x);
+        const float dpow = -par.y * powu_any(l, -M.m_pow);
+        const float fs = (dwlc + dpow) * il;
+        f.x += fs * d.x;
+        f.y += fs * d.y;
+        f.z += fs * d.z;
+      }
+    }
+    // e points from b to a (the paper's e_ij with i = a)
+    const float3 e = make_float3(-d.x * il, -d.y * il, -d.z * il);
+    if (terms & TDPD_TERM_BOND_VISCOUS) {
+      const uint32_t qa = C.sl[ab.x], qb = C.sl[ab.y];
+      const float3 vr = make_float3(s.vx[qa] - s.vx[qb] - float(nyb) * C.le.u, s.vy[qa] - s.vy[qb],
+                                    s.vz[qa] - s.vz[qb]);
+      const float ve = dt3(vr, e);
+      f.x += -M.gamma_t * vr.x - M.gamma_c * ve * e.x;
+      f.y += -M.gamma_t * vr.y - M.gamma_c * ve * e.y;
+      f.z += -M.gamma_t * vr.z - M.gamma_c * ve * e.z;
+    }
+    if (terms & TDPD_TERM_BOND_RANDOM) {
+      // a < b locally and gids are consecutive, so (g0+a, g0+b) is ordered;
+      // the counter takes box-local gids
+      const uint32_t ga = uint32_t(C.g0 + ab.x) - B.gid_base, gb = uint32_t(C.g0 + ab.y) - B.gid_base;
+      float W[12];  // streams 64..66: (cos, sin) of words (0,1) then (2,3); first 9 used
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const u32x4 z = philox10(k, ga, gb, B.ctr3 | uint32_t(64 + q), B.seed_lo, B.seed_hi);
+        gauss2(z.a, z.b, W[4 * q], W[4 * q + 1]);
+        gauss2(z.c, z.d, W[4 * q + 2], W[4 * q + 3]);
+      }
+      const float trW = W[0] + W[4] + W[8];  // trace of W and of its symmetric part
+      const float ex[3] = {e.x, e.y, e.z};
+      float o[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          float m = ct * (0.5f * (W[3 * i + j] + W[3 * j + i]) - (i == j ? trW * (1.f / 3.f) : 0.f));
+          if (i == j) m += cc * trW;
+          acc += m * ex[j];
+        }
+        o[i] = amp * acc;
+      }
+      f.x += o[0];
+      f.y += o[1];
+      f.z += o[2];
+    }
+    fb[bnd] = f.x;
+    fb[M.nbond + bnd] = f.y;
+    fb[2 * M.nbond + bnd] = f.z;
+  }
+}
+
+// 3. vertices [v0, v1): bond sums, area/volume constraints, bending, into Fm.
+// A^t, V^t come from av[r] (part 1, in this workgroup or an earlier launch).
+__device__ __forceinline__ void vertex_forces(const MemArgs &ma, const Cell &C, uint32_t *err,
+                                              int r, int v0, int v1) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const MeshDev &M = *C.M;
+  const MembraneConst &mc = ma.mc;
+  const int terms = mc.terms;
+  const float *fb = ma.Fb + 3 * ma.bond_stride * r;
+  const SurrUse su = ma.su;
+  const int64_t voff = ma.rbc_voff[r];
+  const float cg = mc.local_only ? 0.f : float(M.kg * (ma.av[2 * r] - M.A0) / M.A0);
+  const float cv = mc.local_only ? 0.f : float(M.kv * (ma.av[2 * r + 1] - M.V0) / M.V0);
   const float s0 = sinf(M.theta0), c0 = cosf(M.theta0);
-  for (int v = tid; v < nv; v += nt) {
-    const float3 pv = P(v);
+  for (int v = v0 + tid; v < v1; v += nt) {
+    const float3 pv = C.P(v);
     float3 f = make_float3(0.f, 0.f, 0.f);
     // bending and local area of this vertex come from the surrogate
-    const bool sv = su.flag && su.flag[rbc_voff[r] + v];
+    const bool sv = su.flag && su.flag[voff + v];
     if (terms & (TDPD_TERM_BOND | TDPD_TERM_BOND_VISCOUS | TDPD_TERM_BOND_RANDOM)) {
       for (int q = M.bond_off[v]; q < M.bond_off[v + 1]; ++q) {
         const int inc = M.bond_inc[q];
@@ -237,8 +262,8 @@ __device__ __forceinline__ void membrane_cell(const MemArgs &ma, const BoxDev *_
     if (terms & (TDPD_TERM_AREA | TDPD_TERM_VOLUME)) {
       for (int q = M.tri_off[v]; q < M.tri_off[v + 1]; ++q) {
         const int4 tr = M.tri_inc[q];  // (b, c, triangle, -), v first, counter-clockwise
-        const float3 rb = rel(P(tr.x), pv);
-        const float3 rc = rel(P(tr.y), pv);
+        const float3 rb = C.rel(C.P(tr.x), pv);
+        const float3 rc = C.rel(C.P(tr.y), pv);
         const float3 nn = crs(rb, rc);
         if (terms & TDPD_TERM_AREA) {
           const float nl = sqrtf(dt3(nn, nn));
@@ -264,10 +289,10 @@ __device__ __forceinline__ void membrane_cell(const MemArgs &ma, const BoxDev *_
       for (int q = M.dih_off[v]; q < M.dih_off[v + 1]; ++q) {
         const int4 D = M.dih_inc[q];
         const int role = M.dih_role[q];
-        const float3 a = role == 0 ? zero3 : rel(P(D.x), pv);
-        const float3 b = role == 1 ? zero3 : rel(P(D.y), pv);
-        const float3 c = role == 2 ? zero3 : rel(P(D.z), pv);
-        const float3 d = role == 3 ? zero3 : rel(P(D.w), pv);
+        const float3 a = role == 0 ? zero3 : C.rel(C.P(D.x), pv);
+        const float3 b = role == 1 ? zero3 : C.rel(C.P(D.y), pv);
+        const float3 c = role == 2 ? zero3 : C.rel(C.P(D.z), pv);
+        const float3 d = role == 3 ? zero3 : C.rel(C.P(D.w), pv);
         float sn, cs;
         const float3 g = dihedral_grad(a, b, c, d, role, sn, cs);
         const float coef = -M.kb * (sn * c0 - cs * s0);  // -kb sin(theta - theta0)
@@ -276,17 +301,55 @@ __device__ __forceinline__ void membrane_cell(const MemArgs &ma, const BoxDev *_
         f.z += coef * g.z;
       }
     }
-    const int64_t o = 3 * (rbc_voff[r] + v);
+    const int64_t o = 3 * (voff + v);
     if (sv) {
       f.x += su.Fs[o];
       f.y += su.Fs[o + 1];
       f.z += su.Fs[o + 2];
     }
-    Fm[o] = f.x;
-    Fm[o + 1] = f.y;
-    Fm[o + 2] = f.z;
+    ma.Fm[o] = f.x;
+    ma.Fm[o + 1] = f.y;
+    ma.Fm[o + 2] = f.z;
     if (!(isfinite(f.x) && isfinite(f.y) && isfinite(f.z))) atomicOr(err, kErrNonfinite);
   }
+}
+
+}  // namespace mem
+
+// All three parts for cell r in one workgroup.
+__device__ __forceinline__ void membrane_cell(const MemArgs &ma, const BoxDev *__restrict__ boxes,
+                                              const State &s, uint32_t k, uint32_t *err, int r,
+                                              char *lds) {
+  if (ma.mc.gate > 0 && (k % uint32_t(ma.mc.gate)) != 0u) return;
+  const mem::Cell C = mem::stage_cell(ma, boxes, s, k, r, lds);
+  if (ma.mc.local_only) {  // no K-Gather writes: A^t, V^t are not used
+  } else {
+    mem::kgather(ma, C, r, lds);
+  }
+  mem::bond_forces(ma, C, s, k, err, r, 0, C.M->nbond);
+  __syncthreads();
+  mem::vertex_forces(ma, C, err, r, 0, C.nv);
+}
+
+// Parts 1 (in part 0) and 2 (bonds [p nbond / parts, (p+1) nbond / parts))
+// of cell r; the state is the one before this evaluation's reorder.
+__device__ __forceinline__ void membrane_elements(const MemArgs &ma, const BoxDev *__restrict__ boxes,
+                                                  const State &s, uint32_t k, uint32_t *err, int r,
+                                                  int p, int parts, char *lds) {
+  const mem::Cell C = mem::stage_cell(ma, boxes, s, k, r, lds);
+  if (p == 0) mem::kgather(ma, C, r, lds);
+  const int nb = C.M->nbond;
+  mem::bond_forces(ma, C, s, k, err, r, int(int64_t(nb) * p / parts),
+                   int(int64_t(nb) * (p + 1) / parts));
+}
+
+// Part 3 for vertices [g nv / parts, (g+1) nv / parts) of cell r.
+__device__ __forceinline__ void membrane_vertices(const MemArgs &ma, const BoxDev *__restrict__ boxes,
+                                                  const State &s, uint32_t k, uint32_t *err, int r,
+                                                  int g, int parts, char *lds) {
+  const mem::Cell C = mem::stage_cell(ma, boxes, s, k, r, lds);
+  mem::vertex_forces(ma, C, err, r, int(int64_t(C.nv) * g / parts),
+                     int(int64_t(C.nv) * (g + 1) / parts));
 }
 
 }  // namespace tdpd

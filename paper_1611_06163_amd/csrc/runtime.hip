@@ -876,9 +876,6 @@ static int prepare(tdpd_sys *s) {
   return TDPD_OK;
 }
 
-// Cells from which the pair kernel takes the membrane terms itself.
-constexpr int kFuseMinCells = 16;
-
 // Membrane arguments of all cells (nrbc 0 when the system has none).
 static MemArgs mem_args(const tdpd_sys *s, const MembraneConst &mc, float *Fm_out, SurrUse su) {
   MemArgs m{};
@@ -896,6 +893,7 @@ static MemArgs mem_args(const tdpd_sys *s, const MembraneConst &mc, float *Fm_ou
   m.bond_stride = s->bond_stride;
   m.su = su;
   m.nrbc = int(s->rbc_mesh.size());
+  m.max_nv = s->max_nv;
   return m;
 }
 
@@ -925,10 +923,26 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
                     s->kdev, st);  // advances the counter
     return TDPD_OK;
   }
+  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
+  // one-thread-per-particle kernel; it also packs a slot into 26 bits
+  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
+  const bool tiled = !(s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26));
+  // The membrane terms normally ride along in two launches the step makes
+  // anyway: the K-Gather and bond forces in the binning scan's launch, the
+  // per-vertex part in the pair kernel's (no second stream, nothing
+  // serialised).  The surrogate, the simple pair kernel, the radix binning,
+  // a timed membrane phase or a mesh too large for either launch's LDS take
+  // the membrane kernel on a second stream beside the pair kernel instead.
+  const bool split = nrbc > 0 && tiled && s->bin_mode == 0 && s->fuse_membrane && !s->surr_on &&
+                     !(s->timing_mask & (1 << 2)) && scan_takes_membrane(s->max_nv) &&
+                     pair_tiled_takes_membrane(s->tile, s->S, s->any_shear, s->max_nv);
+  MemArgs ma_split = mem_args(s, s->mc, s->Fm, SurrUse{nullptr, nullptr});
+  if (!split) ma_split.nrbc = 0;
   if (s->bin_mode == 0) {
     launch_bin_counting(s->cur(), s->nxt(), s->keys, s->vals, s->cell_count, s->ncell,
                         s->cell_start, s->bin_tmp, s->tile_sum, n, s->S, s->slot_of_gid, s->keys_s,
-                        fuse_prev ? s->kdev : nullptr, st);
+                        fuse_prev ? s->kdev : nullptr, ma_split, s->d_boxes, s->kdev,
+                        fuse_prev ? 1 : 0, s->errw, st);
   } else {
     radix_sort(s->keys, s->vals, s->keys_tmp, s->vals_tmp, s->keys_s, s->perm, s->hist, n,
                s->key_bits, st);
@@ -937,20 +951,7 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   }
   s->phase_end(1, tb, st);
   s->cur_A = !s->cur_A;
-  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
-  // one-thread-per-particle kernel; it also packs a slot into 26 bits
-  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
-  const bool tiled = !(s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26));
-  // Many cells are taken by the first workgroups of the tiled pair kernel
-  // (one launch, no second stream).  A cell's workgroup then shares its CU
-  // with pair workgroups and takes longer than the pair work when it is one
-  // of a few, so few cells, the surrogate, the simple pair kernel, a timed
-  // membrane phase or a mesh too large for the pair kernel's LDS take the
-  // separate membrane kernel on the second stream beside the pair kernel.
-  const bool fused = nrbc >= kFuseMinCells && tiled && s->fuse_membrane && !s->surr_on &&
-                     !(s->timing_mask & (1 << 2)) &&
-                     pair_tiled_takes_membrane(s->tile, s->S, s->any_shear, s->max_nv);
-  if (nrbc > 0 && !fused) {
+  if (nrbc > 0 && !split) {
     (void)hipEventRecord(s->ev_fork, st);
     (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
     const bool tm = s->phase_begin(2, s->st2);
@@ -982,13 +983,11 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
     launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
                        s->Q, s->nzero, s->errw, st);
   } else {
-    MemArgs ma = mem_args(s, s->mc, s->Fm, SurrUse{nullptr, nullptr});
-    if (!fused) ma.nrbc = 0;
     (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, n, s->kdev,
-                            s->F, s->Q, s->nzero, s->errw, s->tile, s->any_shear, ma, st);
+                            s->F, s->Q, s->nzero, s->errw, s->tile, s->any_shear, ma_split, st);
   }
   s->phase_end(0, tp, st);
-  if (nrbc > 0 && !fused) (void)hipStreamWaitEvent(st, s->ev_join, 0);
+  if (nrbc > 0 && !split) (void)hipStreamWaitEvent(st, s->ev_join, 0);
   if (!fuse_next) {
     const bool tk = s->phase_begin(3, st);
     launch_postkick(s->pc, s->cur(), s->F, s->Q, n, vmap, integrate, s->kdev, st);

@@ -69,7 +69,7 @@ def test_teacher_forced_forces(kernel, name):
         cfg.m_s = 0.05
     elif name == "c2":
         cfg = I.c2()
-    elif name == "c3_cells":  # enough cells for the pair kernel to take them
+    elif name == "c3_cells":  # twenty cells
         cfg = I.c3(scale=0.25, n_cells=20)
     else:
         cfg = I.c3(scale=0.25, n_cells=2)
@@ -223,10 +223,10 @@ def test_empty_and_single_particle():
 
 
 def test_membrane_in_pair_kernel_equals_separate_kernel():
-    """With 20 cells the tiled pair kernel's first workgroups take the
-    membrane terms; the separate membrane kernel on the second stream gives
-    the same forces up to the order of the FP64 cell sums, and both runs
-    step alike."""
+    """By default the membrane terms ride along in the binning scan's launch
+    (K-Gather, bond forces) and the tiled pair kernel's (per-vertex terms);
+    the separate membrane kernel on the second stream gives the same forces
+    up to the order of the FP64 cell sums, and both runs step alike."""
     cfg = I.c3(scale=0.25, n_cells=20)
     out = []
     for fuse in ("1", "0"):
