@@ -35,13 +35,14 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the factors a 256 MiB copy gives;
 # profiles/pair_tiled_single_rbc_20cube_hbm.md).  Valid only for the kernel
 # sources and tile shape they were taken with: reported when both match.
-PAIR_SOURCES = ("kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h", "launch.h")
+PAIR_SOURCES = ("kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h", "launch.h",
+                "membrane_cell.h")
 PAIR_TRAFFIC = {
-    "c2": {"sha256": "69b7220fc97ba25179d7c6e54b95d242085c63c8d3930f859901f1ea520f0bd2",
-           "tiles": {"4,2,2,0": [2.77e+06, 4.904e+05],
-                     "2,3,2,0": [2.825e+06, 4.904e+05],
-                     "4,2,2,1": [2.774e+06, 4.904e+05],
-                     "2,3,2,1": [2.844e+06, 4.904e+05]}},
+    "c2": {"sha256": "d128a8411ace0f498468d31aa59efed7845208f412146de1e78689bfe8381c4c",
+           "tiles": {"4,2,2,0": [3.047e+06, 4.964e+05],
+                     "2,3,2,0": [3.181e+06, 4.965e+05],
+                     "4,2,2,1": [3.052e+06, 4.964e+05],
+                     "2,3,2,1": [3.183e+06, 4.965e+05]}},
 }
 
 

@@ -390,8 +390,12 @@ __global__ void __launch_bounds__(kScanThreads) k_count_scan(uint32_t *__restric
 
 int64_t count_scan_tiles(int64_t ncell) { return ncell > 0 ? (ncell + kCellTile - 1) / kCellTile : 1; }
 
+// the K-Gather in one workgroup, the bonds in workgroups of up to
+// kBondsPerPart (most lanes then carry one bond, with its three Philox
+// blocks, on the critical path)
+constexpr int64_t kBondsPerPart = 384;
 int membrane_element_parts(int64_t max_nbond) {
-  return max_nbond > kScanThreads ? int((max_nbond + kScanThreads - 1) / kScanThreads) : 1;
+  return 1 + int(max_nbond > 0 ? (max_nbond + kBondsPerPart - 1) / kBondsPerPart : 1);
 }
 
 bool scan_takes_membrane(int max_nv) {

@@ -331,16 +331,19 @@ __device__ __forceinline__ void membrane_cell(const MemArgs &ma, const BoxDev *_
   mem::vertex_forces(ma, C, err, r, 0, C.nv);
 }
 
-// Parts 1 (in part 0) and 2 (bonds [p nbond / parts, (p+1) nbond / parts))
-// of cell r; the state is the one before this evaluation's reorder.
+// Part 1 (p = 0) or a share of part 2 (p >= 1: bonds [(p-1) nbond / (parts-1),
+// p nbond / (parts-1))) of cell r; the state is the one before this
+// evaluation's reorder.
 __device__ __forceinline__ void membrane_elements(const MemArgs &ma, const BoxDev *__restrict__ boxes,
                                                   const State &s, uint32_t k, uint32_t *err, int r,
                                                   int p, int parts, char *lds) {
   const mem::Cell C = mem::stage_cell(ma, boxes, s, k, r, lds);
-  if (p == 0) mem::kgather(ma, C, r, lds);
-  const int nb = C.M->nbond;
-  mem::bond_forces(ma, C, s, k, err, r, int(int64_t(nb) * p / parts),
-                   int(int64_t(nb) * (p + 1) / parts));
+  if (p == 0) {
+    mem::kgather(ma, C, r, lds);
+    return;
+  }
+  const int64_t nb = C.M->nbond, q = parts - 1;
+  mem::bond_forces(ma, C, s, k, err, r, int(nb * (p - 1) / q), int(nb * p / q));
 }
 
 // Part 3 for vertices [g nv / parts, (g+1) nv / parts) of cell r.
