@@ -410,18 +410,21 @@ __global__ void __launch_bounds__(256) k_scatter_rank(const uint32_t *__restrict
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (advance && i == 0) *advance += 1u;  // nothing in this launch reads it
   if (i >= n) return;
-  tmp[start[keys[i]] + rank[i]] = uint32_t(i);
+  // the slot's particle, and (in the second half) its cell, so that the
+  // fix-up reads both at once
+  const uint32_t c = keys[i];
+  const uint32_t pos = start[c] + rank[i];
+  tmp[pos] = uint32_t(i);
+  tmp[n + pos] = c;
 }
 
 __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uint32_t *__restrict__ tmp,
-                                                     const uint32_t *__restrict__ keys,
                                                      const uint32_t *__restrict__ start, int64_t n,
                                                      int nspec, uint32_t *__restrict__ slot_of_gid,
                                                      uint32_t *__restrict__ keys_sorted) {
   const int64_t p0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p0 >= n) return;
-  const uint32_t q = tmp[p0];
-  const uint32_t c = keys[q];
+  const uint32_t q = tmp[p0], c = tmp[n + p0];
   const uint32_t s0 = start[c], s1 = start[c + 1];
   // rank among the cell's entries by previous slot; eight independent loads
   // per round so that their latencies overlap (past the cell end: no entry)
@@ -466,7 +469,7 @@ void launch_bin_counting(State src, State dst, const uint32_t *keys, const uint3
   if (n <= 0) return;
   const dim3 g(unsigned((n + 255) / 256));
   hipLaunchKernelGGL(k_scatter_rank, g, dim3(256), 0, st, keys, rank, cell_start, n, tmp, advance);
-  hipLaunchKernelGGL(k_rank_gather, g, dim3(256), 0, st, src, dst, tmp, keys, cell_start, n, nspec,
+  hipLaunchKernelGGL(k_rank_gather, g, dim3(256), 0, st, src, dst, tmp, cell_start, n, nspec,
                      slot_of_gid, keys_sorted);
 }
 

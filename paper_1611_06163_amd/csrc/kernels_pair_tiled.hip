@@ -625,9 +625,11 @@ static bool launch_ns(const PairConst &pc, const BoxDev *boxes, State s, const u
 // (each shape is built with and without the stencil filter)
 const PairTile kPairTiles[] = {
     {4, 2, 1, 1}, {4, 1, 1, 1}, {4, 3, 1, 1}, {2, 2, 1, 1}, {2, 3, 1, 1}, {2, 4, 1, 1},
-    {4, 2, 2, 1}, {4, 1, 2, 1}, {2, 2, 2, 1}, {2, 3, 2, 1}, {2, 2, 4, 1}, {4, 1, 4, 1},
+    {4, 2, 2, 1}, {4, 1, 2, 1}, {2, 2, 2, 1}, {2, 3, 2, 1}, {2, 4, 2, 1}, {2, 2, 4, 1},
+    {2, 3, 4, 1}, {4, 1, 4, 1}, {4, 2, 4, 1},
     {4, 2, 1, 0}, {4, 1, 1, 0}, {4, 3, 1, 0}, {2, 2, 1, 0}, {2, 3, 1, 0}, {2, 4, 1, 0},
-    {4, 2, 2, 0}, {4, 1, 2, 0}, {2, 2, 2, 0}, {2, 3, 2, 0}, {2, 2, 4, 0}, {4, 1, 4, 0}};
+    {4, 2, 2, 0}, {4, 1, 2, 0}, {2, 2, 2, 0}, {2, 3, 2, 0}, {2, 4, 2, 0}, {2, 2, 4, 0},
+    {2, 3, 4, 0}, {4, 1, 4, 0}, {4, 2, 4, 0}};
 const int kNumPairTiles = int(sizeof(kPairTiles) / sizeof(kPairTiles[0]));
 
 bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,

@@ -87,7 +87,8 @@ void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
                     hipStream_t st);
 // Counting binning after launch_prekick: scan of the cell counts into
 // cell_start (counts zeroed for the next step; tile_sum holds
-// count_scan_tiles(ncell) words), scatter, and the rank fix-up fused with
+// count_scan_tiles(ncell) words; tmp holds 2n words), scatter, and the rank
+// fix-up fused with
 // the reorder of every state plane into dst (slot_of_gid and the sorted keys
 // updated).  Same permutation as the stable radix sort.
 int64_t count_scan_tiles(int64_t ncell);

@@ -707,7 +707,7 @@ static int prepare(tdpd_sys *s) {
   s->errw = dallocT<uint32_t>(s, 1);
   s->kdev = dallocT<uint32_t>(s, 1);
   s->cell_count = dallocT<uint32_t>(s, size_t(s->ncell));
-  s->bin_tmp = dallocT<uint32_t>(s, n);
+  s->bin_tmp = dallocT<uint32_t>(s, 2 * size_t(n));
   s->tile_sum = dallocT<uint32_t>(s, size_t(count_scan_tiles(s->ncell)));
   if (!s->kdev || !s->cell_count || !s->bin_tmp || !s->tile_sum)
     return s->fail(TDPD_ERR_OOM, "device allocation failed");
