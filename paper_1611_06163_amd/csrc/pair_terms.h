@@ -36,11 +36,11 @@ __device__ __forceinline__ float3 force_term(const PairConst &pc, const BoxDev &
   return make_float3(fs * ex, fs * ey, fs * ez);
 }
 
-// Fickian flux weight w_DC(r) for 0 < d2 < rcc2
+// Fickian flux weight w_DC(r) for 0 < d2 < rcc2 (inside the cutoff 1 - r/rcc
+// is at worst a rounding step below zero, which the square leaves harmless)
 __device__ __forceinline__ float flux_weight(const PairConst &pc, float d2) {
-  const float r = d2 * __builtin_amdgcn_rsqf(d2);
-  const float wq = fmaxf(1.f - r * pc.inv_rcc, 0.f);
-  return pc.sc_exp == 2.f ? wq * wq : powu(wq, pc.sc_exp);
+  const float wq = 1.f - __builtin_amdgcn_sqrtf(d2) * pc.inv_rcc;
+  return pc.sc_exp == 2.f ? wq * wq : powu(fmaxf(wq, 0.f), pc.sc_exp);
 }
 
 }  // namespace tdpd
