@@ -180,6 +180,29 @@ def batched_leg(torch, tdpd, steps, warmup, n_boxes=256):
                                      "at the same tile shape (tests/test_gpu_batch.py)")
 
 
+def species_leg(torch, tdpd, steps, warmup, n_species=10):
+    """The single-RBC workload with ten species instead of two (the paper's
+    many-species regime), on the same default path."""
+    from paper_1611_06163_amd import inputs as I
+    cfg = I.c2_species(n_species)
+    sysg = tdpd.System(cfg)
+    sysg.compute_forces(0)
+    sysg.autotune(reps=3)
+    sysg.step(warmup)
+    sysg.sync()
+    el = _timed_steps(torch, sysg, steps)
+    sysg.set_timing(tdpd.PHASE["pair"])
+    sysg.step(steps)
+    pair_ms, pair_n = sysg.get_timing(tdpd.PHASE["pair"])
+    sysg.set_timing(0)
+    tile = list(sysg.tile)
+    sysg.close()
+    return dict(workload=f"single RBC (500 vertices) in 20^3 periodic tDPD solvent, rho=3, "
+                         f"{n_species} species", n_species=n_species, particles=cfg.n,
+                value=cfg.n * steps / el, unit="particle-steps/s", ms_per_step=el * 1e3 / steps,
+                pair_us=pair_ms * 1e3 / max(pair_n, 1), tile=tile)
+
+
 def surrogate_leg(torch, tdpd, steps, warmup, workload):
     """Train the membrane surrogate on samples of plain channel runs, then run
     the evaluation workload plain and with the network (fallback tolerance
@@ -241,6 +264,7 @@ def main():
                     help="keep the default tile shape of the pair kernel")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-species", action="store_true", help="skip the ten-species leg")
     ap.add_argument("--surrogate-workload", default="c3", choices=["c3", "c5"])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device with torch (a plain "
@@ -329,6 +353,10 @@ def main():
         out["copy_calibration_bytes"] = nbytes
     if not args.no_batched:
         out["batched"] = batched_leg(torch, tdpd, steps=20, warmup=5)
+    if not args.no_species and args.workload == "c2":
+        sp = species_leg(torch, tdpd, steps=args.steps, warmup=args.warmup)
+        sp["vs_two_species"] = sp["value"] / value
+        out["species"] = sp
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(torch, tdpd, steps=200, warmup=20,
                                          workload=args.surrogate_workload)

@@ -51,7 +51,7 @@ typedef enum {
 } tdpd_status;
 
 #define TDPD_MAX_TYPES 4
-#define TDPD_MAX_SPECIES 8
+#define TDPD_MAX_SPECIES 16
 
 /* Terms bitmask (tdpd_params.terms); all set by default. */
 #define TDPD_TERM_CONSERVATIVE 1    /* Eq. (3) */

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tdpd_oracle.c")
 LIB = os.path.join(HERE, "libtdpd_oracle.so")
 
-MAXT, MAXS = 4, 8
+MAXT, MAXS = 4, 16
 TERM = dict(cons=1, diss=2, rand=4, fick=8, frand=16, bond=32, bvisc=64, brand=128,
             area=256, vol=512, bend=1024, body=2048)
 TERMS_ALL = sum(TERM.values())

@@ -47,7 +47,7 @@
 #include <string.h>
 
 #define ORC_MAXT 4
-#define ORC_MAXS 8
+#define ORC_MAXS 16
 #define ORC_MAXMESH 16
 
 /* terms bitmask */

@@ -321,8 +321,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
   const int h0 = c0 + int(int64_t(cnt) * part / split);
   const int h1 = c0 + int(int64_t(cnt) * (part + 1) / split);
   uint32_t zero = 0;  // coincident (home, candidate) tests of this wave (wave-uniform)
-  if (tid < NS * kMaxT * kMaxT) {
-    const int sp = tid / (kMaxT * kMaxT), tt = tid % (kMaxT * kMaxT);
+  // (16 species x 16 type pairs outnumber the threads of a two-wave workgroup)
+  for (int e = tid; e < NS * kMaxT * kMaxT; e += 64 * W) {
+    const int sp = e / (kMaxT * kMaxT), tt = e % (kMaxT * kMaxT);
     sh.kap[sp][tt] = (sp < S && tt < T * T) ? pc.kappa[sp * T * T + tt] : 0.f;
   }
 
@@ -496,8 +497,10 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
             const float wdc = d2m1 < rcc2m1 ? flux_weight(pc, d2) : 0.f;
             const int tt = trow + ct[kk];
 #pragma unroll
-            for (int sp = 0; sp < NS; ++sp)
+            for (int sp = 0; sp < NS; ++sp) {
+              if (NS > 2 && sp >= S) break;  // a build for more species than used
               qp[sp] = fmaf(sh.kap[sp][tt] * wdc, cc[kk][sp] - ci[sp], qp[sp]);
+            }
           }
           // homes outside any cell body test the cutoff alone
           const bool hitf = bq == -3 ? d2m1 < rc2m1 : (d2m1 < rc2m1) & (cbody[kk] != bq);
@@ -518,6 +521,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
         if (fick) {
 #pragma unroll
           for (int sp = 0; sp < NS; ++sp) {
+            if (NS > 2 && sp >= S) break;
             const float t = wave_sum(qp[sp]);
             if (lane == 0) sh.qa[w][sp][i] += t;
           }
@@ -606,11 +610,15 @@ static bool launch_ns(const PairConst &pc, const BoxDev *boxes, State s, const u
                       int64_t ncell, int64_t n, const uint32_t *kdev, float *F, float *Q,
                       unsigned long long *nzero, uint32_t *err, const PairTile &t,
                       bool sheared, const MemArgs &ma, hipStream_t st) {
+// (16 species: one or two register chunks only, the rest is registers for
+// the species)
 #define TDPD_SHAPE(W, KC)                                                                    \
-  if (t.waves == W && t.chunks == KC) {                                                      \
-    launch_shape<NS, W, KC>(pc, boxes, s, cell_start, ncell, t.split, t.filter, n, kdev, F, Q, \
-                            nzero, err, sheared, ma, st);                                    \
-    return true;                                                                             \
+  if constexpr (NS < 16 || KC <= 2) {                                                        \
+    if (t.waves == W && t.chunks == KC) {                                                    \
+      launch_shape<NS, W, KC>(pc, boxes, s, cell_start, ncell, t.split, t.filter, n, kdev, F, \
+                              Q, nzero, err, sheared, ma, st);                               \
+      return true;                                                                           \
+    }                                                                                        \
   }
   TDPD_SHAPE(4, 2)
   TDPD_SHAPE(4, 1)
@@ -645,7 +653,17 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
     return launch_ns<2>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
   if (pc.n_species <= 4)
     return launch_ns<4>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
-  return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
+  if (pc.n_species <= 8)
+    return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
+  return launch_ns<16>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
+}
+
+bool pair_tile_built(const PairTile &t, int n_species) {
+  for (int i = 0; i < kNumPairTiles; ++i)
+    if (kPairTiles[i].waves == t.waves && kPairTiles[i].chunks == t.chunks &&
+        kPairTiles[i].split == t.split && kPairTiles[i].filter == t.filter)
+      return n_species <= 8 || t.chunks <= 2;
+  return false;
 }
 
 // LDS of one workgroup of the shape, which the membrane workgroups reuse.
@@ -660,7 +678,8 @@ bool pair_tiled_takes_membrane(const PairTile &t, int n_species, bool sheared, i
   const size_t have = n_species <= 1   ? lds_ns<1>(t, sheared)
                       : n_species == 2 ? lds_ns<2>(t, sheared)
                       : n_species <= 4 ? lds_ns<4>(t, sheared)
-                                       : lds_ns<8>(t, sheared);
+                      : n_species <= 8 ? lds_ns<8>(t, sheared)
+                                       : lds_ns<16>(t, sheared);
   return membrane_cell_lds(max_nv, 64 * t.waves) <= have;
 }
 

@@ -139,6 +139,8 @@ struct PairTile {
 };
 extern const PairTile kPairTiles[];  // the shapes the kernel is built for
 extern const int kNumPairTiles;
+// Whether the shape is built for n_species species.
+bool pair_tile_built(const PairTile &t, int n_species);
 // Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
 void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
                       const uint32_t *cell_keys,

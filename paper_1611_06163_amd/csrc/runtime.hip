@@ -276,13 +276,7 @@ static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
   return TDPD_OK;
 }
 
-static bool tile_built(const PairTile &t) {
-  for (int i = 0; i < kNumPairTiles; ++i)
-    if (kPairTiles[i].waves == t.waves && kPairTiles[i].chunks == t.chunks &&
-        kPairTiles[i].split == t.split && kPairTiles[i].filter == t.filter)
-      return true;
-  return false;
-}
+
 
 static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void *hip_stream,
                          tdpd_alloc_fn alloc, tdpd_free_fn free_fn, void *user, tdpd_sys **out) {
@@ -338,7 +332,7 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
   if (const char *e = std::getenv("TDPD_TILE")) {  // "waves,chunks,split,filter"
     PairTile t{};
     if (std::sscanf(e, "%d,%d,%d,%d", &t.waves, &t.chunks, &t.split, &t.filter) == 4 &&
-        tile_built(t))
+        pair_tile_built(t, s->S))
       s->tile = t;
   }
   *out = s;
@@ -1381,7 +1375,7 @@ std::string tune_signature(const tdpd_sys *s) {
   return buf;
 }
 
-bool cache_lookup(const char *path, const std::string &sig, PairTile *t) {
+bool cache_lookup(const char *path, const std::string &sig, int n_species, PairTile *t) {
   FILE *fp = path ? std::fopen(path, "r") : nullptr;
   if (!fp) return false;
   char line[512];
@@ -1391,7 +1385,7 @@ bool cache_lookup(const char *path, const std::string &sig, PairTile *t) {
     if (!bar || std::string(line, bar - line) != sig) continue;
     PairTile c{};
     if (std::sscanf(bar + 1, "%d %d %d %d", &c.waves, &c.chunks, &c.split, &c.filter) == 4 &&
-        tile_built(c)) {
+        pair_tile_built(c, n_species)) {
       *t = c;
       found = true;  // the last matching line wins
     }
@@ -1415,7 +1409,7 @@ extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
     if (best_ms) *best_ms = 0.0;
     return TDPD_OK;  // the tiled kernel is not used for this system
   }
-  if (!cache_lookup(cache_path, sig, &best)) {
+  if (!cache_lookup(cache_path, sig, s->S, &best)) {
     // the pair kernel is a pure function of the binned state: time every
     // shape on the current state, keeping the coincident-pair counters
     unsigned long long saved[2] = {0, 0};
@@ -1425,6 +1419,7 @@ extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
     HIPCHK(hipEventCreate(&e1));
     for (int i = 0; i < kNumPairTiles; ++i) {
       const PairTile &t = kPairTiles[i];
+      if (!pair_tile_built(t, s->S)) continue;
       auto launch = [&]() {
         MemArgs none{};  // the shapes are timed on the pair work alone
         (void)launch_pair_tiled(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, s->n,
@@ -1470,7 +1465,7 @@ extern "C" int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t
                              int32_t filter) {
   if (!s) return TDPD_ERR_INVALID_ARG;
   const PairTile t{waves, chunks, split, filter};
-  if (!tile_built(t)) return s->fail(TDPD_ERR_UNSUPPORTED, "set_tile: shape not built");
+  if (!pair_tile_built(t, s->S)) return s->fail(TDPD_ERR_UNSUPPORTED, "set_tile: shape not built");
   s->tile = t;
   s->destroy_graphs();
   return TDPD_OK;

@@ -335,6 +335,14 @@ def c2(seed=2):
     return _suspension("single_rbc", (20.0, 20.0, 20.0), 3.0, 1, seed, steps=1000)
 
 
+def c2_species(n_species=10, seed=2):
+    """The single-RBC box with n_species species (the paper's many-species
+    regime); the membrane permeability alternates 1.0, 0.1 over species."""
+    perm = tuple(1.0 if sp % 2 == 0 else 0.1 for sp in range(n_species))
+    return _suspension("single_rbc_species", (20.0, 20.0, 20.0), 3.0, 1, seed,
+                       n_species=n_species, permeability=perm, steps=1000)
+
+
 def c3(seed=3, scale=1.0, n_cells=None, steps=10000):
     """RBC suspension in a wall-bounded channel: 64x32x32 at density 3,
     100 cells, frozen walls in y, body force 0.02 along x.  `scale` shrinks

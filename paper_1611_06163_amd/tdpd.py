@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtdpd.so")
 
-MAX_TYPES, MAX_SPECIES = 4, 8
+MAX_TYPES, MAX_SPECIES = 4, 16
 TERM = dict(cons=1, diss=2, rand=4, fick=8, frand=16, bond=32, bvisc=64, brand=128,
             area=256, vol=512, bend=1024, body=2048)
 TERMS_ALL = 4095

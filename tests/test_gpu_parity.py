@@ -318,6 +318,46 @@ def test_tile_shapes_match_oracle(tile, name):
     assert rep["excluded"] <= 5 + cfg.n // 20
 
 
+def _ten_species():
+    cfg = I.make_fluid(box=(8.0, 8.0, 8.0), rho=3.0, n_species=10, seed=23)
+    for sp in range(10):
+        cfg.kappa[sp] *= 1.0 + 0.25 * sp
+    return cfg
+
+
+@pytest.mark.parametrize("kernel,tile", [(0, None), (1, (4, 2, 1, 1)), (1, (4, 1, 2, 0)),
+                                         (1, (2, 2, 1, 0)), (1, (4, 2, 4, 1))])
+def test_ten_species_match_oracle(kernel, tile):
+    """Ten species (the 16-species build of the tiled kernel, two register
+    chunks at most): forces and all ten fluxes against the oracle."""
+    cfg = _ten_species()
+    sysg = gpu_system(cfg, kernel=kernel)
+    if tile is not None:
+        sysg.tile = tile
+    k = 6
+    sysg.compute_forces(k)
+    F, Q = sysg.get_forces()
+    assert Q.shape == (cfg.n, 10)
+    pos, vel, conc = sysg.get_state()
+    o = Oracle(cfg)
+    ref = o.forces(pos, vel, conc, k=k)
+    excl = near_cutoff_mask(o, cfg, pos, vel, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, label=f"10 species/k{kernel}/{tile}")
+    assert rep["badF"] == 0 and rep["badQ"] == 0
+    assert rep["excluded"] <= 5 + cfg.n // 20
+
+
+def test_ten_species_refuses_three_chunk_shapes_and_tunes():
+    sysg = gpu_system(_ten_species(), kernel=1)
+    with pytest.raises(tdpd.TdpdError):
+        sysg.tile = (4, 3, 1, 0)
+    sysg.step(2)
+    sysg.autotune(reps=2)
+    assert sysg.tile[1] <= 2
+    sysg.step(3)
+    sysg.sync()
+
+
 def test_autotune_picks_a_built_shape_and_caches(tmp_path):
     cfg = I.c2()
     a = gpu_system(cfg, kernel=1)

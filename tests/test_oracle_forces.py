@@ -102,3 +102,33 @@ def test_random_force_antisymmetric_and_scaled():
     expect = cfg.sigma[0, 0] ** 2 * w ** cfg.s_exp / cfg.dt
     assert abs(xs.var() / expect - 1.0) < 0.1
     assert abs(xs.mean()) < 5 * np.sqrt(expect / xs.size)
+
+
+def _many_species(n_species, seed=21):
+    cfg = I.make_fluid(box=(6.0, 6.0, 6.0), rho=3.0, n_species=n_species, seed=seed)
+    for sp in range(n_species):
+        cfg.kappa[sp] *= 1.0 + 0.25 * sp
+    return cfg
+
+
+def test_many_species_independent_linear_and_conserved():
+    """Ten species (the paper's many-species regime, Eqs. 7-10): a species'
+    flux depends only on its own concentrations and kappa, so the first two
+    equal a two-species run on the same particles; with equal concentrations
+    the fluxes scale with kappa; every species' total vanishes; the forces
+    do not depend on the species count."""
+    c10 = _many_species(10)
+    c2 = _many_species(2)
+    c2.pos, c2.vel, c2.conc = c10.pos.copy(), c10.vel.copy(), c10.conc[:, :2].copy()
+    r10 = Oracle(c10).forces(c10.pos, c10.vel, c10.conc, k=4)
+    r2 = Oracle(c2).forces(c2.pos, c2.vel, c2.conc, k=4)
+    assert r10["err"] == 0 and r2["err"] == 0
+    assert np.array_equal(r10["F"], r2["F"])
+    scale = np.abs(r2["Q"]).max()
+    assert np.abs(r10["Q"][:, :2] - r2["Q"]).max() <= 1e-13 * scale
+    assert np.abs(r10["Q"].sum(axis=0)).max() <= 1e-12 * np.abs(r10["Q"]).sum()
+    # the same concentrations in every species: Q_s = (1 + s/4) Q_0
+    conc = np.repeat(c10.conc[:, :1], 10, axis=1)
+    q = Oracle(c10).forces(c10.pos, c10.vel, conc, k=4)["Q"]
+    for sp in range(10):
+        assert np.allclose(q[:, sp], (1.0 + 0.25 * sp) * q[:, 0], rtol=1e-12, atol=1e-14 * scale)
