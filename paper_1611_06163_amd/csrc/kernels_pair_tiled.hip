@@ -43,15 +43,16 @@ __device__ __forceinline__ float dpp(float v) {
 
 // Sum over the 64 lanes with DPP: inclusive scans inside each 16-lane row
 // (row_shr 1, 2, 4, 8), then row_bcast 15 and 31 carry row totals upward;
-// lane 63 ends with the total, which is broadcast.  Fixed order, registers only.
-__device__ __forceinline__ float wave_sum(float v) {
+// lane 63 ends with the total (other lanes hold partial sums).  Fixed
+// order, registers only.
+__device__ __forceinline__ float wave_sum_to_last(float v) {
   v += dpp<0x111, 0xf>(v);
   v += dpp<0x112, 0xf>(v);
   v += dpp<0x114, 0xf>(v);
   v += dpp<0x118, 0xf>(v);
   v += dpp<0x142, 0xa>(v);
   v += dpp<0x143, 0xc>(v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+  return v;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -522,8 +523,8 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
 #pragma unroll
           for (int sp = 0; sp < NS; ++sp) {
             if (NS > 2 && sp >= S) break;
-            const float t = wave_sum(qp[sp]);
-            if (lane == 0) sh.qa[w][sp][i] += t;
+            const float t = wave_sum_to_last(qp[sp]);
+            if (lane == 63) sh.qa[w][sp][i] += t;
           }
         }
       }
