@@ -38,11 +38,11 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 PAIR_SOURCES = ("kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h", "launch.h",
                 "membrane_cell.h")
 PAIR_TRAFFIC = {
-    "c2": {"sha256": "8355468b2caa952f33e28b7d1425683c6eb16ba4901697fd2948508089f55b19",
-           "tiles": {"4,2,2,0": [3.021e+06, 4.964e+05],
-                     "2,3,2,0": [3.181e+06, 4.965e+05],
-                     "4,2,2,1": [3.022e+06, 4.964e+05],
-                     "2,3,2,1": [3.183e+06, 4.965e+05]}},
+    "c2": {"sha256": "59dc66a822af5242516ac95286b8168f93d17401f5cd557e331bda8f01b0a829",
+           "tiles": {"4,2,2,0": [3.048e+06, 4.964e+05],
+                     "2,3,2,0": [3.182e+06, 4.965e+05],
+                     "4,2,2,1": [3.052e+06, 4.964e+05],
+                     "2,3,2,1": [3.184e+06, 4.965e+05]}},
 }
 
 
