@@ -203,6 +203,30 @@ def species_leg(torch, tdpd, steps, warmup, n_species=10):
                 pair_us=pair_ms * 1e3 / max(pair_n, 1), tile=tile)
 
 
+def verlet_leg(torch, tdpd, steps, warmup, wl, skin, every):
+    """The same workload on Verlet neighbour lists (radius max(rc, rcc) +
+    skin, rebuilt with the binning every `every` steps) instead of per-step
+    cell scans; the pair kernel is timed as in the main run."""
+    cfg, desc = workload(wl)
+    sysg = tdpd.System(cfg)
+    sysg.set_verlet(skin, every)
+    sysg.compute_forces(0)
+    sysg.step(warmup)
+    sysg.sync()
+    el = _timed_steps(torch, sysg, steps)
+    sysg.set_timing(tdpd.PHASE["pair"] | tdpd.PHASE["bin"])
+    sysg.step(steps)
+    pair_ms, pair_n = sysg.get_timing(tdpd.PHASE["pair"])
+    bin_ms, bin_n = sysg.get_timing(tdpd.PHASE["bin"])
+    sysg.set_timing(0)
+    cap = sysg.verlet[2]
+    sysg.close()
+    return dict(workload=desc, skin=skin, every=every, capacity=cap, particles=cfg.n,
+                value=cfg.n * steps / el, unit="particle-steps/s", ms_per_step=el * 1e3 / steps,
+                pair_us=pair_ms * 1e3 / max(pair_n, 1),
+                kick_bin_list_us_per_step=bin_ms * 1e3 / max(bin_n, 1))
+
+
 def surrogate_leg(torch, tdpd, steps, warmup, workload):
     """Train the membrane surrogate on samples of plain channel runs, then run
     the evaluation workload plain and with the network (fallback tolerance
@@ -266,6 +290,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-species", action="store_true", help="skip the ten-species leg")
     ap.add_argument("--surrogate-workload", default="c3", choices=["c3", "c5"])
+    ap.add_argument("--no-verlet", action="store_true", help="skip the neighbour-list leg")
+    ap.add_argument("--verlet", default="0.45,4", metavar="SKIN,EVERY",
+                    help="skin and rebuild interval of the neighbour-list leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device with torch (a plain "
                          "copy of known size, to scale hardware byte counters)")
@@ -353,6 +380,15 @@ def main():
         out["copy_calibration_bytes"] = nbytes
     if not args.no_batched:
         out["batched"] = batched_leg(torch, tdpd, steps=20, warmup=5)
+    if not args.no_verlet:
+        skin, every = args.verlet.split(",")
+        try:
+            vl = verlet_leg(torch, tdpd, steps=args.steps, warmup=args.warmup,
+                            wl=args.workload, skin=float(skin), every=int(every))
+            vl["vs_cells"] = vl["value"] / value
+        except tdpd.TdpdError as e:  # e.g. the skin was too small for the interval
+            vl = {"skin": float(skin), "every": int(every), "error": str(e)}
+        out["verlet"] = vl
     if not args.no_species and args.workload == "c2":
         sp = species_leg(torch, tdpd, steps=args.steps, warmup=args.warmup)
         sp["vs_two_species"] = sp["value"] / value

@@ -47,7 +47,8 @@ typedef enum {
   TDPD_ERR_STATE = -7,         /* call out of order (e.g. step before set_state) */
   TDPD_ERR_UNSUPPORTED = -8,   /* valid request outside what the library handles */
   TDPD_ERR_CAPACITY = -9,      /* an output buffer was too small */
-  TDPD_ERR_IO = -10            /* a checkpoint file could not be read or written, or does not match */
+  TDPD_ERR_IO = -10,           /* a checkpoint file could not be read or written, or does not match */
+  TDPD_ERR_LIST = -11          /* a neighbour list was invalidated (skin exceeded or list full) */
 } tdpd_status;
 
 #define TDPD_MAX_TYPES 4
@@ -248,6 +249,34 @@ int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps, double *bes
 int tdpd_set_tile(tdpd_sys *s, int32_t waves, int32_t chunks, int32_t split, int32_t filter);
 int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *split,
                   int32_t *filter);
+
+/* ---------------------------------------------------------------------
+   Verlet neighbour lists (the paper's performance section: its GPU code
+   keeps per-particle neighbour lists, rebuilt every few steps, instead of
+   scanning cells every step).  With every > 0 and skin > 0, each particle
+   keeps the list of every other particle closer than max(r_c, r_cc) + skin;
+   the lists are rebuilt, together with the cell binning, on every
+   every-th force evaluation (the first evaluation after set_state or
+   load without stored lists always rebuilds), and the other evaluations
+   test only the list entries with the same FP32 pair rule as the cell
+   path, so the pair set of every step is the same as the cell path's as
+   long as no particle moves more than skin / 2 between rebuilds.  That is
+   checked every step: a larger displacement, or a particle with more
+   than capacity list entries, makes the next tdpd_sync (and every call
+   that syncs) return TDPD_ERR_LIST; the forces of that step are then
+   not to be trusted.  capacity 0 picks twice the mean count at the
+   nominal density rho plus 64 (at most 4096).  Cells are made at least
+   max(r_c, r_cc) + skin wide (TDPD_ERR_BOX_TOO_SMALL under 3 per side).
+   Call after tdpd_create or tdpd_set_state and before the first step or
+   force evaluation of that state (TDPD_ERR_STATE otherwise); skin 0 or
+   every 0 switches back to per-step cells.  Not with Lees-Edwards boxes or
+   the random flux (TDPD_ERR_UNSUPPORTED).  Device memory: 4 * capacity + 52
+   bytes per particle.  Results differ from the cell path's only in
+   summation order; tdpd_get_pairs then lists pairs from the lists, and
+   checkpoints hold the lists, so a resumed run is bit-for-bit the
+   uninterrupted one. */
+int tdpd_set_verlet(tdpd_sys *s, float skin, int32_t every, int32_t capacity);
+int tdpd_get_verlet(const tdpd_sys *s, float *skin, int32_t *every, int32_t *capacity);
 
 /* ---------------------------------------------------------------------
    Membrane surrogate.  Not part of the paper's method: a learned stand-in

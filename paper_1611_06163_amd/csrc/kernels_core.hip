@@ -1,6 +1,6 @@
 // kernels_core.hip -- binning (LSD radix sort of cell keys), reordering,
 // velocity-Verlet kicks, diagnostics and gid-order gathers.
-#include "launch.h"
+#include "launch_list.h"
 #include "membrane_cell.h"
 
 namespace tdpd {
@@ -172,6 +172,66 @@ __device__ __forceinline__ float3 close_step(const PairConst &pc, State s, float
   return make_float3(fx, fy, fz);
 }
 
+// Half kick and drift of mobile particle i under force f: velocity and
+// concentration kick, drift, wall reflection, sheared-boundary crossing (at
+// the offsets of counter *kdev + finish) and wrap; stores the new x and v
+// and returns them.
+__device__ __forceinline__ void kick_drift(const PairConst &pc, const BoxDev &B, State s, float3 f,
+                                           const float *__restrict__ Q, int64_t n, int64_t i,
+                                           const uint32_t *__restrict__ kdev, int finish,
+                                           float &x, float &y, float &z, float &vx, float &vy,
+                                           float &vz) {
+  const float h = pc.half_dt;
+  vx = s.vx[i] + h * f.x;
+  vy = s.vy[i] + h * f.y;
+  vz = s.vz[i] + h * f.z;
+  for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+  x += pc.dt * vx;
+  y += pc.dt * vy;
+  z += pc.dt * vz;
+  if (pc.wall_axis >= 0) {
+    float *c = pc.wall_axis == 0 ? &x : (pc.wall_axis == 1 ? &y : &z);
+    const float L = B.L[pc.wall_axis], w = pc.wall_w;
+    bool hit = false;
+    if (*c < w) {
+      *c = 2.f * w - *c;
+      hit = true;
+    } else if (*c > L - w) {
+      *c = 2.f * (L - w) - *c;
+      hit = true;
+    }
+    if (hit) {
+      vx = -vx;
+      vy = -vy;
+      vz = -vz;
+    }
+  }
+  if (B.shear != 0.f) {
+    // crossing the y boundary of a sheared box: into the image below
+    // (above), x by -delta (+delta), x velocity by -u (+u), with the
+    // offsets of this step's counter (the positions are at that time)
+    const LeOff le = le_offsets(B, *kdev + uint32_t(finish), pc.dt);
+    if (y >= B.L[1]) {
+      y -= B.L[1];
+      x -= le.delta;
+      vx -= le.u;
+    } else if (y < 0.f) {
+      y += B.L[1];
+      x += le.delta;
+      vx += le.u;
+    }
+  }
+  x = wrap_coord(x, B.L[0]);
+  y = wrap_coord(y, B.L[1]);
+  z = wrap_coord(z, B.L[2]);
+  s.x[i] = x;
+  s.y[i] = y;
+  s.z[i] = z;
+  s.vx[i] = vx;
+  s.vy[i] = vy;
+  s.vz[i] = vz;
+}
+
 __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__restrict__ boxes,
                                                  State s, float *__restrict__ F,
                                                  const float *__restrict__ Q, int64_t n,
@@ -194,55 +254,8 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
       f = make_float3(F[3 * i], F[3 * i + 1], F[3 * i + 2]);
     }
     if (integrate && !info_frozen(info)) {
-      const float h = pc.half_dt;
-      float vx = s.vx[i] + h * f.x;
-      float vy = s.vy[i] + h * f.y;
-      float vz = s.vz[i] + h * f.z;
-      for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
-      x += pc.dt * vx;
-      y += pc.dt * vy;
-      z += pc.dt * vz;
-      if (pc.wall_axis >= 0) {
-        float *c = pc.wall_axis == 0 ? &x : (pc.wall_axis == 1 ? &y : &z);
-        const float L = B.L[pc.wall_axis], w = pc.wall_w;
-        bool hit = false;
-        if (*c < w) {
-          *c = 2.f * w - *c;
-          hit = true;
-        } else if (*c > L - w) {
-          *c = 2.f * (L - w) - *c;
-          hit = true;
-        }
-        if (hit) {
-          vx = -vx;
-          vy = -vy;
-          vz = -vz;
-        }
-      }
-      if (B.shear != 0.f) {
-        // crossing the y boundary of a sheared box: into the image below
-        // (above), x by -delta (+delta), x velocity by -u (+u), with the
-        // offsets of this step's counter (the positions are at that time)
-        const LeOff le = le_offsets(B, *kdev + uint32_t(finish), pc.dt);
-        if (y >= B.L[1]) {
-          y -= B.L[1];
-          x -= le.delta;
-          vx -= le.u;
-        } else if (y < 0.f) {
-          y += B.L[1];
-          x += le.delta;
-          vx += le.u;
-        }
-      }
-      x = wrap_coord(x, B.L[0]);
-      y = wrap_coord(y, B.L[1]);
-      z = wrap_coord(z, B.L[2]);
-      s.x[i] = x;
-      s.y[i] = y;
-      s.z[i] = z;
-      s.vx[i] = vx;
-      s.vy[i] = vy;
-      s.vz[i] = vz;
+      float vx, vy, vz;
+      kick_drift(pc, B, s, f, Q, n, i, kdev, finish, x, y, z, vx, vy, vz);
     }
     const int cx = cell_coord(x, B.inv_h[0], B.nc[0]);
     const int cy = cell_coord(y, B.inv_h[1], B.nc[1]);
@@ -277,6 +290,47 @@ void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
   const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
   hipLaunchKernelGGL(k_prekick, dim3(unsigned(nb)), dim3(256), 0, st, pc, boxes, s, F, Q, n, keys,
                      vals, int(integrate), cell_count, kdev, int(finish), prev);
+}
+
+// First half of a step on the neighbour-list path (no binning): half kick
+// and drift, then the check that the particle has not moved more than half
+// the skin from its position at the last list build, and the packed copies
+// the list pair kernel gathers.
+__global__ void __launch_bounds__(256) k_prekick_list(PairConst pc,
+                                                      const BoxDev *__restrict__ boxes, State s,
+                                                      const float *__restrict__ F,
+                                                      const float *__restrict__ Q, int64_t n,
+                                                      int integrate,
+                                                      const uint32_t *__restrict__ kdev,
+                                                      ListDev L, uint32_t *err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t info = s.info[i];
+  const BoxDev &B = boxes[info_box(info)];
+  float x = s.x[i], y = s.y[i], z = s.z[i];
+  float vx, vy, vz;
+  if (integrate && !info_frozen(info)) {
+    const float3 f = make_float3(F[3 * i], F[3 * i + 1], F[3 * i + 2]);
+    kick_drift(pc, B, s, f, Q, n, i, kdev, 0, x, y, z, vx, vy, vz);
+  } else {
+    vx = s.vx[i];
+    vy = s.vy[i];
+    vz = s.vz[i];
+  }
+  const float4 r = L.xref[i];
+  const float dx = pair_disp(x, r.x, B.L[0]), dy = pair_disp(y, r.y, B.L[1]),
+              dz = pair_disp(z, r.z, B.L[2]);
+  if (dist2(dx, dy, dz) > L.drift2) atomicOr(err, kErrSkin);
+  L.p4[i] = make_float4(x, y, z, __uint_as_float(info));
+  L.v4[i] = make_float4(vx, vy, vz, __uint_as_float(s.gid[i] - B.gid_base));
+}
+
+void launch_prekick_list(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
+                         const float *Q, int64_t n, bool integrate, const uint32_t *kdev,
+                         const ListDev &L, uint32_t *err, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_prekick_list, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, boxes,
+                     s, F, Q, n, int(integrate), kdev, L, err);
 }
 
 // ------------------------------------------------------------- counting binning

@@ -10,7 +10,7 @@
 #include <utility>
 #include <vector>
 
-#include "launch.h"
+#include "launch_list.h"
 
 using namespace tdpd;
 
@@ -117,6 +117,13 @@ struct tdpd_sys {
   int bin_mode = 0;     // 0: counting (one-digit stable) sort, 1: LSD radix sort
   bool use_graph = true;
   bool fuse_membrane = true;  // cells handled by the first workgroups of the pair kernel
+  // Verlet neighbour lists (verlet_every > 0): rebuilt with the binning on
+  // every verlet_every-th evaluation, pairs taken from them in between
+  int verlet_every = 0;
+  float verlet_skin = 0.f;
+  bool list_valid = false;
+  int list_age = 0;  // evaluations made with the current lists
+  ListDev ld{};
   uint32_t *kdev = nullptr;       // device step counter read by the kernels
   uint32_t kdev_val = 0;          // host mirror of *kdev
   uint32_t *cell_count = nullptr, *bin_tmp = nullptr, *tile_sum = nullptr;
@@ -705,6 +712,16 @@ static int prepare(tdpd_sys *s) {
   s->tile_sum = dallocT<uint32_t>(s, size_t(count_scan_tiles(s->ncell)));
   if (!s->kdev || !s->cell_count || !s->bin_tmp || !s->tile_sum)
     return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  s->list_valid = false;
+  if (s->verlet_every > 0) {
+    s->ld.nbr = dallocT<uint32_t>(s, size_t(s->ld.cap) * size_t(n));
+    s->ld.ncnt = dallocT<uint32_t>(s, n);
+    s->ld.xref = dallocT<float4>(s, n);
+    s->ld.p4 = dallocT<float4>(s, n);
+    s->ld.v4 = dallocT<float4>(s, n);
+    if (!s->ld.nbr || !s->ld.ncnt || !s->ld.xref || !s->ld.p4 || !s->ld.v4)
+      return s->fail(TDPD_ERR_OOM, "device allocation failed");
+  }
   HIPCHK(hipMemsetAsync(s->kdev, 0, sizeof(uint32_t), s->st));
   HIPCHK(hipMemsetAsync(s->cell_count, 0, sizeof(uint32_t) * s->ncell, s->st));
   s->kdev_val = 0;
@@ -894,7 +911,9 @@ static MemArgs mem_args(const tdpd_sys *s, const MembraneConst &mc, float *Fm_ou
 // Whether consecutive integrated steps may fold one step's closing kick
 // into the next step's first kick (counting binning, which then advances
 // the counter).
-static bool can_fuse_kicks(const tdpd_sys *s) { return s->bin_mode == 0 && s->n > 0; }
+static bool can_fuse_kicks(const tdpd_sys *s) {
+  return s->bin_mode == 0 && s->n > 0 && s->verlet_every == 0;
+}
 
 // Enqueue one force evaluation on stream `st`, optionally wrapped in the two
 // velocity-Verlet half kicks.  The random-number counter is *kdev (set by the
@@ -908,9 +927,22 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   const int64_t n = s->n;
   const int nrbc = int(s->rbc_mesh.size());
   const VertexMap vmap{nrbc > 0 ? s->Fm : nullptr, s->d_rbc_first, s->d_rbc_voff};
+  // neighbour-list mode: the binning (and a list build) only on every
+  // verlet_every-th evaluation
+  const bool verlet = s->verlet_every > 0;
+  const bool rebuild = !verlet || !s->list_valid || s->list_age >= s->verlet_every;
   const bool tb = s->phase_begin(1, st);
-  launch_prekick(s->pc, s->d_boxes, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate,
-                 s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, fuse_prev, vmap, st);
+  if (rebuild) {
+    launch_prekick(s->pc, s->d_boxes, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate,
+                   s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, fuse_prev, vmap, st);
+  } else {
+    launch_prekick_list(s->pc, s->d_boxes, s->cur(), s->F, s->Q, n, integrate, s->kdev, s->ld,
+                        s->errw, st);
+  }
+  if (verlet) {
+    s->list_age = rebuild ? 1 : s->list_age + 1;
+    s->list_valid = true;
+  }
   if (n == 0) {
     s->phase_end(1, tb, st);
     launch_postkick(s->pc, s->cur(), s->F, s->Q, 0, VertexMap{nullptr, nullptr, nullptr}, false,
@@ -927,12 +959,14 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   // serialised).  The surrogate, the simple pair kernel, the radix binning,
   // a timed membrane phase or a mesh too large for either launch's LDS take
   // the membrane kernel on a second stream beside the pair kernel instead.
-  const bool split = nrbc > 0 && tiled && s->bin_mode == 0 && s->fuse_membrane && !s->surr_on &&
+  const bool split = nrbc > 0 && tiled && !verlet && s->bin_mode == 0 && s->fuse_membrane && !s->surr_on &&
                      !(s->timing_mask & (1 << 2)) && scan_takes_membrane(s->max_nv) &&
                      pair_tiled_takes_membrane(s->tile, s->S, s->any_shear, s->max_nv);
   MemArgs ma_split = mem_args(s, s->mc, s->Fm, SurrUse{nullptr, nullptr});
   if (!split) ma_split.nrbc = 0;
-  if (s->bin_mode == 0) {
+  if (!rebuild) {
+    // the particle order of the last rebuild stays
+  } else if (s->bin_mode == 0) {
     launch_bin_counting(s->cur(), s->nxt(), s->keys, s->vals, s->cell_count, s->ncell,
                         s->cell_start, s->bin_tmp, s->tile_sum, n, s->S, s->slot_of_gid, s->keys_s,
                         fuse_prev ? s->kdev : nullptr, ma_split, s->d_boxes, s->kdev,
@@ -943,8 +977,10 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
     launch_cell_bounds(s->keys_s, n, s->ncell, s->cell_start, st);
     launch_reorder(s->cur(), s->nxt(), s->perm, n, s->S, s->slot_of_gid, st);
   }
+  if (rebuild) s->cur_A = !s->cur_A;
+  if (verlet && rebuild)
+    launch_list_build(s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->ld, s->errw, st);
   s->phase_end(1, tb, st);
-  s->cur_A = !s->cur_A;
   if (nrbc > 0 && !split) {
     (void)hipEventRecord(s->ev_fork, st);
     (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
@@ -973,7 +1009,10 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
     (void)hipEventRecord(s->ev_join, s->st2);
   }
   const bool tp = s->phase_begin(0, st);
-  if (!tiled) {
+  if (verlet) {
+    launch_pair_list(s->pc, s->d_boxes, s->cur(), n, s->kdev, s->ld, s->F, s->Q, s->nzero,
+                     s->errw, st);
+  } else if (!tiled) {
     launch_pair_simple(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->kdev, s->F,
                        s->Q, s->nzero, s->errw, st);
   } else {
@@ -1012,8 +1051,36 @@ static int evaluate_at(tdpd_sys *s, uint32_t k) {
 // host-side parity advances, and it is restored).
 constexpr int kGraphSteps = 4;
 static_assert(kGraphSteps % 2 == 0, "a multi-step graph must end at its start parity");
+// Neighbour-list mode: one graph per buffer parity holding a whole rebuild
+// period (a rebuilding step and verlet_every - 1 list steps), which flips
+// the parity once; slots [0] and [1].
+static int capture_list_graphs(tdpd_sys *s) {
+  const bool start_A = s->cur_A;
+  const int age = s->list_age;
+  const bool valid = s->list_valid;
+  for (int q = 0; q < 2; ++q) {
+    const int slot = s->cur_A ? 0 : 1;
+    s->list_valid = true;
+    s->list_age = s->verlet_every;  // the first step of the period rebuilds
+    HIPCHK(hipStreamBeginCapture(s->gst, hipStreamCaptureModeThreadLocal));
+    int rc = TDPD_OK;
+    for (int r = 0; r < s->verlet_every && !rc; ++r) rc = enqueue_evaluation(s, true, s->gst);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->gst, &g);
+    if (rc) return rc;
+    if (e != hipSuccess) return s->fail(TDPD_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    s->graph[slot] = g;
+    HIPCHK(hipGraphInstantiate(&s->gexec[slot], g, nullptr, nullptr, 0));
+  }
+  s->list_age = age;
+  s->list_valid = valid;
+  if (s->cur_A != start_A) return s->fail(TDPD_ERR_HIP, "graph capture: parity mismatch");
+  return TDPD_OK;
+}
+
 static int capture_graphs(tdpd_sys *s) {
   if (!s->gst) HIPCHK(hipStreamCreateWithFlags(&s->gst, hipStreamNonBlocking));
+  if (s->verlet_every > 0) return capture_list_graphs(s);
   const bool start_A = s->cur_A;
   for (int q = 0; q < 4; ++q) {
     const int slot = (q < 2 ? 0 : 2) + (s->cur_A ? 0 : 1);
@@ -1059,7 +1126,24 @@ extern "C" int tdpd_step(tdpd_sys *s, int32_t n_steps) {
   }
   const bool graphs = s->use_graph && s->timing_mask == 0 && s->n > 0;
   if (graphs && !s->gexec[0] && (rc = capture_graphs(s))) return rc;
+  const bool verlet = s->verlet_every > 0;
   for (int i = 0; i < n_steps;) {
+    if (graphs && verlet) {
+      // whole rebuild periods from a rebuild on, single steps otherwise
+      if (s->list_valid && s->list_age >= s->verlet_every && n_steps - i >= s->verlet_every) {
+        HIPCHK(hipGraphLaunch(s->gexec[s->cur_A ? 0 : 1], s->st));
+        s->cur_A = !s->cur_A;
+        s->step += s->verlet_every;
+        s->kdev_val += uint32_t(s->verlet_every);
+        i += s->verlet_every;
+        continue;
+      }
+      ++s->step;
+      if ((rc = enqueue_evaluation(s, true, s->st))) return rc;
+      ++s->kdev_val;
+      ++i;
+      continue;
+    }
     if (graphs && n_steps - i >= kGraphSteps) {
       HIPCHK(hipGraphLaunch(s->gexec[2 + (s->cur_A ? 0 : 1)], s->st));  // parity unchanged
       s->step += kGraphSteps;
@@ -1091,6 +1175,12 @@ extern "C" int tdpd_sync(tdpd_sys *s) {
     HIPCHK(hipMemset(s->errw, 0, sizeof(uint32_t)));
     if (e & kErrOverext) return s->fail(TDPD_ERR_BOND_OVEREXTENDED, "a membrane bond reached its maximum extension");
     if (e & kErrNonfinite) return s->fail(TDPD_ERR_NONFINITE, "a force became non-finite");
+    if (e & kErrSkin)
+      return s->fail(TDPD_ERR_LIST, "neighbour list: a particle moved more than half the skin "
+                                    "between rebuilds (raise the skin or rebuild more often)");
+    if (e & kErrListFull)
+      return s->fail(TDPD_ERR_LIST, "neighbour list: a particle has more neighbours than the "
+                                    "list capacity");
   }
   return TDPD_OK;
 }
@@ -1149,8 +1239,12 @@ extern "C" int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *
   int32_t *dout = dallocT<int32_t>(s, 2 * size_t(cap > 0 ? cap : 1));
   if (!dout) return s->fail(TDPD_ERR_OOM, "device allocation failed");
   HIPCHK(hipMemsetAsync(s->pair_count, 0, sizeof(unsigned long long), s->st));
-  launch_pair_emit(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, s->n,
-                   which ? s->pc.rcc2 : s->pc.rc2, s->kdev_val, dout, cap, s->pair_count, s->st);
+  if (s->verlet_every > 0)  // the cells are those of the last rebuild: take the lists
+    launch_list_emit(s->d_boxes, s->cur(), s->n, s->ld, which ? s->pc.rcc2 : s->pc.rc2, dout, cap,
+                     s->pair_count, s->st);
+  else
+    launch_pair_emit(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, s->n,
+                     which ? s->pc.rcc2 : s->pc.rc2, s->kdev_val, dout, cap, s->pair_count, s->st);
   unsigned long long cnt = 0;
   hipError_t e = hipMemcpyAsync(&cnt, s->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -1253,6 +1347,7 @@ uint64_t fingerprint(const tdpd_sys *s) {
   f.bytes(p.body_force, sizeof(p.body_force)); f.val(p.wall_axis); f.val(p.wall_w);
   f.val(p.terms);
   f.val(s->n); f.val(s->S); f.val(uint64_t(s->boxes.size()));
+  f.val(s->verlet_every); f.val(s->verlet_skin); f.val(s->ld.cap);
   for (const HostBox &b : s->boxes) {
     f.bytes(b.L, sizeof(b.L)); f.val(b.n); f.val(b.seed); f.val(b.box_id);
   }
@@ -1272,6 +1367,7 @@ struct CkptHeader {
   int64_t n, step;
   int32_t S, nrbc;
   uint32_t kdev, forces_valid;
+  int32_t list_age, list_valid;
 };
 
 // The device regions of a checkpoint, in file order.
@@ -1285,6 +1381,13 @@ std::vector<std::pair<void *, size_t>> ckpt_regions(tdpd_sys *s) {
       {s->F, sizeof(float) * 3 * n},
       {s->Q, sizeof(float) * S * n}};
   if (nrbc) r.push_back({s->d_centroid, sizeof(double) * 3 * nrbc});
+  if (s->verlet_every > 0) {  // the lists, so that a resumed run takes the same pairs in the same order
+    r.push_back({s->ld.ncnt, sizeof(uint32_t) * n});
+    r.push_back({s->ld.nbr, sizeof(uint32_t) * n * s->ld.cap});
+    r.push_back({s->ld.xref, sizeof(float4) * n});
+    r.push_back({s->ld.p4, sizeof(float4) * n});
+    r.push_back({s->ld.v4, sizeof(float4) * n});
+  }
   return r;
 }
 
@@ -1303,6 +1406,8 @@ extern "C" int tdpd_save(tdpd_sys *s, const char *path) {
   h.nrbc = int32_t(s->rbc_mesh.size());
   h.kdev = s->kdev_val;
   h.forces_valid = s->forces_valid ? 1u : 0u;
+  h.list_age = s->list_age;
+  h.list_valid = s->list_valid ? 1 : 0;
   FILE *fp = std::fopen(path, "wb");
   if (!fp) return s->fail(TDPD_ERR_IO, std::string("save: cannot open ") + path);
   bool ok = std::fwrite(&h, sizeof(h), 1, fp) == 1;
@@ -1353,6 +1458,8 @@ extern "C" int tdpd_load(tdpd_sys *s, const char *path) {
   s->kdev_val = h.kdev;
   s->step = h.step;
   s->forces_valid = h.forces_valid != 0;
+  s->list_age = h.list_age;
+  s->list_valid = s->verlet_every > 0 && h.list_valid != 0;
   // captured graphs hold the A/B parity they were recorded at; A is current now
   s->destroy_graphs();
   return check_launch(s);
@@ -1478,6 +1585,67 @@ extern "C" int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks,
   *chunks = s->tile.chunks;
   *split = s->tile.split;
   *filter = s->tile.filter;
+  return TDPD_OK;
+}
+
+// ------------------------------------------------------------- neighbour lists
+constexpr int32_t kMaxListCap = 4096;
+
+extern "C" int tdpd_set_verlet(tdpd_sys *s, float skin, int32_t every, int32_t capacity) {
+  if (!s) return TDPD_ERR_INVALID_ARG;
+  if (!std::isfinite(skin) || skin < 0.f || every < 0 || capacity < 0 || capacity > kMaxListCap)
+    return s->fail(TDPD_ERR_INVALID_ARG, "set_verlet: bad skin, interval or capacity");
+  if (s->uploaded)
+    return s->fail(TDPD_ERR_STATE, "set_verlet: call after set_state, before the first step");
+  const bool on = every > 0 && skin > 0.f;
+  if (on && s->any_shear)
+    return s->fail(TDPD_ERR_UNSUPPORTED, "set_verlet: not with Lees-Edwards boxes");
+  if (on && s->prm.m_s > 0.f && (s->prm.terms & TDPD_TERM_FLUX_RANDOM))
+    return s->fail(TDPD_ERR_UNSUPPORTED, "set_verlet: not with the random flux");
+  const float rmax = std::max(s->prm.rc, s->prm.rcc);
+  const float rl = on ? rmax + skin : rmax;
+  // cells at least rl wide, so that the 27 around a particle hold its list
+  std::vector<HostBox> boxes = s->boxes;
+  int64_t ncell = 0;
+  for (HostBox &b : boxes) {
+    for (int a = 0; a < 3; ++a) {
+      b.nc[a] = int(std::floor(double(b.L[a]) / (double(rl) * (1.0 + 1e-4))));
+      if (b.nc[a] < 3)
+        return s->fail(TDPD_ERR_BOX_TOO_SMALL, "set_verlet: fewer than 3 cells of the list radius");
+    }
+    b.ncell = int64_t(b.nc[0]) * b.nc[1] * b.nc[2];
+    b.cell_base = ncell;
+    ncell += b.ncell;
+  }
+  s->boxes = std::move(boxes);
+  s->ncell = ncell;
+  s->key_bits = 1;
+  while ((int64_t(1) << s->key_bits) < s->ncell) ++s->key_bits;
+  s->verlet_every = on ? every : 0;
+  s->verlet_skin = on ? skin : 0.f;
+  s->ld = ListDev{};
+  if (on) {
+    int64_t cap = capacity;
+    if (cap == 0) {  // twice the mean count at the nominal density, with room
+      const double mean = 4.0 / 3.0 * M_PI * double(rl) * rl * rl * std::max(0.f, s->prm.rho);
+      cap = std::min<int64_t>(kMaxListCap, (int64_t(2.0 * mean) + 64 + 31) / 32 * 32);
+    }
+    s->ld.cap = uint32_t(cap);
+    s->ld.rl2 = rl * rl;
+    const float h = 0.5f * skin * (1.f - 1e-3f);  // half the skin, less a rounding margin
+    s->ld.drift2 = h * h;
+  }
+  s->list_valid = false;
+  s->list_age = 0;
+  s->destroy_graphs();
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_get_verlet(const tdpd_sys *s, float *skin, int32_t *every, int32_t *capacity) {
+  if (!s || !skin || !every || !capacity) return TDPD_ERR_INVALID_ARG;
+  *skin = s->verlet_skin;
+  *every = s->verlet_every;
+  *capacity = int32_t(s->ld.cap);
   return TDPD_OK;
 }
 

@@ -26,7 +26,7 @@ FLAG_FROZEN = 1 << 8
 PHASE = dict(pair=1, bin=2, membrane=4, kick=8)
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "BOX_TOO_SMALL", -3: "OOM", -4: "HIP",
           -5: "NONFINITE", -6: "BOND_OVEREXTENDED", -7: "STATE", -8: "UNSUPPORTED",
-          -9: "CAPACITY", -10: "IO"}
+          -9: "CAPACITY", -10: "IO", -11: "LIST"}
 
 
 class TdpdError(RuntimeError):
@@ -103,6 +103,8 @@ def lib():
             "tdpd_get_timing": (C.c_int, [P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
             "tdpd_autotune": (C.c_int, [P, C.c_char_p, I32, C.POINTER(C.c_double)]),
             "tdpd_set_tile": (C.c_int, [P, I32, I32, I32, I32]),
+            "tdpd_set_verlet": (C.c_int, [P, C.c_float, I32, I32]),
+            "tdpd_get_verlet": (C.c_int, [P, C.POINTER(C.c_float), C.POINTER(I32), C.POINTER(I32)]),
             "tdpd_get_tile": (C.c_int, [P, C.POINTER(I32), C.POINTER(I32), C.POINTER(I32),
                                         C.POINTER(I32)]),
             "tdpd_mlp_create": (C.c_int, [P, ALLOC_FN, FREE_FN, P, C.POINTER(P)]),
@@ -355,6 +357,17 @@ class System:
     @tile.setter
     def tile(self, t):
         self._check(lib().tdpd_set_tile(self.h, int(t[0]), int(t[1]), int(t[2]), int(t[3])))
+
+    def set_verlet(self, skin, every, capacity=0):
+        """Neighbour lists of radius max(rc, rcc) + skin, rebuilt every `every` steps."""
+        self._check(lib().tdpd_set_verlet(self.h, float(skin), int(every), int(capacity)))
+
+    @property
+    def verlet(self):
+        """(skin, every, capacity) of the neighbour lists; every 0: per-step cells."""
+        sk, ev, cap = C.c_float(), C.c_int32(), C.c_int32()
+        self._check(lib().tdpd_get_verlet(self.h, C.byref(sk), C.byref(ev), C.byref(cap)))
+        return (sk.value, ev.value, cap.value)
 
     def save(self, path):
         self._check(lib().tdpd_save(self.h, os.fsencode(path)))

@@ -1,0 +1,188 @@
+"""GPU parity of the Verlet neighbour-list path (tdpd_set_verlet): the same
+pair sets as the oracle's brute force at every step between rebuilds, forces
+and fluxes within the per-particle tolerance of the cell path's tests at
+rebuilding and list steps alike, graphs that replay the direct launches bit
+for bit, checkpoints that resume bit for bit, and the skin and capacity
+checks reported through tdpd_sync (forced from the host by settings that
+break them: every kernel still runs to its end)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import compare_forces, gpu_system, near_cutoff_mask
+from oracle import Oracle
+from paper_1611_06163_amd import inputs as I
+from paper_1611_06163_amd import tdpd
+
+pytestmark = pytest.mark.gpu
+
+# three drifts of dt = 0.01 between rebuilds stay inside half the skin up
+# to speeds of 7.4 (kT = 1: about one particle-step in 1e11 is faster)
+SKIN, EVERY = 0.45, 4
+
+
+def _sorted_pairs(p):
+    p = np.asarray(p)
+    if p.size == 0:
+        return p.reshape(0, 2)
+    p = np.sort(p, axis=1)
+    return p[np.lexsort((p[:, 1], p[:, 0]))]
+
+
+def _cluster_cfg():
+    """300 particles packed into a 1.2^3 corner of a 6.5^3 box (lists of
+    several hundred entries), with one coincident pair."""
+    cfg = I.make_fluid(box=(6.5, 6.5, 6.5), n=500, seed=13)
+    rng = np.random.default_rng(14)
+    cfg.pos[:300] = (6.0 + rng.random((300, 3)) * 1.2).astype(np.float32) % np.float32(6.5)
+    cfg.pos[300] = cfg.pos[301]
+    return cfg
+
+
+def _listed(cfg, skin=SKIN, every=EVERY, capacity=0, env=None):
+    s = gpu_system(cfg, env=env)
+    s.set_verlet(skin, every, capacity)
+    return s
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny", "cluster"])
+def test_list_pairs_bit_exact_between_rebuilds(name):
+    """After 0, 3 (list steps) and 5 (after a rebuild) steps the pairs taken from
+    the lists equal the oracle's brute-force pairs at the GPU's positions."""
+    cfg = {"c1": I.c1(), "tiny": I.make_fluid(box=(6.5, 6.6, 6.7), n=300, seed=3),
+           "cluster": _cluster_cfg()}[name]
+    # the packed cluster flies apart (tens of units per unit time): there the
+    # lists are rebuilt at every step
+    s = _listed(cfg, every=1, capacity=512) if name == "cluster" else _listed(cfg)
+    o = Oracle(cfg)
+    for steps in (0, 3, 2):  # list steps, then past the rebuild at step 4
+        s.step(steps)
+        s.sync()
+        pos, _, _ = s.get_state()
+        for which in (0, 1):
+            got = _sorted_pairs(s.pairs(which))
+            ref, _ = o.pairs(pos, which, brute=cfg.n <= 2000)
+            print(name, steps, which, len(got), len(ref), flush=True)
+            assert np.array_equal(got, _sorted_pairs(ref))
+    if name == "cluster":
+        assert s.coincident_pairs > 0
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3_small"])
+def test_list_ten_steps_teacher_forced(name):
+    """Free-running steps on the lists (rebuilds at steps 0, 4 and 8); after
+    each the oracle re-evaluates the forces at the GPU's own state."""
+    cfg = {"c1": I.c1(), "c2": I.c2(), "c3_small": I.c3(scale=0.25, n_cells=2)}[name]
+    sysg = _listed(cfg)
+    o = Oracle(cfg)
+    sysg.compute_forces(0)
+    x0, v0, _ = sysg.get_state()
+    F0, _ = sysg.get_forces()
+    frozen = (cfg.flags & I.FLAG_FROZEN) != 0
+    h = 0.5 * cfg.dt
+    L = np.asarray(cfg.box)
+    for n in range(1, 11):
+        sysg.step(1)
+        sysg.sync()
+        x, v, c = sysg.get_state()
+        F, Q = sysg.get_forces()
+        pred = x0.astype(np.float64) + cfg.dt * (v0 + h * F0)
+        dx = x.astype(np.float64) - pred
+        dx -= L * np.round(dx / L)
+        if cfg.wall_axis >= 0:
+            w = cfg.wall_w
+            y = pred[:, cfg.wall_axis] % L[cfg.wall_axis]
+            dx[(y < w) | (y > L[cfg.wall_axis] - w)] = 0.0
+        dx[frozen] = 0.0
+        assert np.abs(dx).max() < 2e-5, (n, np.abs(dx).max())
+        vh = v.astype(np.float64) - h * F
+        ch = c.astype(np.float64) - h * Q
+        vh[frozen] = 0.0
+        ch[frozen] = c[frozen]
+        ref = o.forces(x, vh, ch, k=n)
+        excl = near_cutoff_mask(o, cfg, x, vh, ref, n)
+        rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/list/step{n}")
+        assert rep["badF"] == 0 and rep["badQ"] == 0
+        x0, v0, F0 = x, v, F
+
+
+def test_list_path_close_to_cell_path():
+    """Same pairs, other summation order: one force evaluation of the list
+    path and of the cell path agree to FP32 rounding of the sums."""
+    cfg = I.c2()
+    out = []
+    for listed in (True, False):
+        s = _listed(cfg) if listed else gpu_system(cfg)
+        s.compute_forces(4)
+        out.append(s.get_forces())
+        s.close()
+    (F1, Q1), (F0, Q0) = out
+    assert np.abs(F1 - F0).max() <= 1e-5 * np.abs(F0).max()
+    assert np.abs(Q1 - Q0).max() <= 1e-5 * np.abs(Q0).max()
+
+
+@pytest.mark.parametrize("name", ["c2", "c3_small"])
+def test_list_graphs_replay_direct_launches(name):
+    """Whole rebuild periods run as captured graphs; partial ones and the
+    steps before the first rebuild boundary run directly.  Both give the
+    same bits, for step counts that start and end inside periods."""
+    cfg = I.c2() if name == "c2" else I.c3(scale=0.25, n_cells=2)
+    outs = []
+    for graph in ("0", "1"):
+        s = _listed(cfg, env={"TDPD_GRAPH": graph})
+        s.step(3)
+        s.step(13)
+        s.step(6)
+        assert s.step_counter == 22
+        outs.append(s.get_state() + s.get_forces())
+        s.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_list_checkpoint_resume_bitwise(tmp_path):
+    cfg = I.small_suspension(seed=31, box=(14.0, 14.0, 14.0), n_cells=1)
+    a = _listed(cfg)
+    a.step(7)  # mid-period: the checkpoint holds the lists
+    path = str(tmp_path / "ck.bin")
+    a.save(path)
+    a.step(9)
+    ref = a.get_state() + a.get_forces()
+    b = _listed(cfg)
+    b.load(path)
+    assert b.step_counter == 7
+    b.step(9)
+    got = b.get_state() + b.get_forces()
+    for nm, x, y in zip(("pos", "vel", "conc", "F", "Q"), got, ref):
+        assert np.array_equal(x, y), nm
+    # another list setting is another system
+    with pytest.raises(tdpd.TdpdError):
+        _listed(cfg, skin=0.4).load(path)
+
+
+def test_skin_exceeded_is_reported():
+    """A skin of 1e-3 with rebuilds every 40 steps: thermal motion (about
+    0.017 per step) leaves it within a few steps, and tdpd_sync says so."""
+    s = _listed(I.c1(), skin=1e-3, every=40)
+    with pytest.raises(tdpd.TdpdError) as e:
+        s.step(20)
+        s.sync()
+    assert e.value.code == -11
+    s.close()
+
+
+def test_list_capacity_overflow_is_reported():
+    s = _listed(I.c1(), capacity=16)  # about 110 neighbours each at rho = 4
+    with pytest.raises(tdpd.TdpdError) as e:
+        s.compute_forces(0)
+        s.sync()
+    assert e.value.code == -11
+    s.close()
+
+
+def test_list_setting_refused_after_first_step():
+    s = gpu_system(I.c1())
+    s.step(1)
+    with pytest.raises(tdpd.TdpdError) as e:
+        s.set_verlet(SKIN, EVERY)
+    assert e.value.code == -7
+    s.close()

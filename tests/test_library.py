@@ -97,3 +97,42 @@ def test_set_state_and_mesh_validation_on_host():
     assert L.tdpd_add_rbc(h, mid.value, 2, C.byref(rid)) == 0
     assert L.tdpd_add_rbc(h, mid.value, 4, C.byref(rid)) == -1   # overlaps the first
     L.tdpd_destroy(h)
+
+
+def test_set_verlet_validation_on_host():
+    """Neighbour-list settings: checked and applied before any upload."""
+    from paper_1611_06163_amd import tdpd
+    L = tdpd.lib()
+    L.tdpd_set_verlet.argtypes = [C.c_void_p, C.c_float, C.c_int32, C.c_int32]
+    L.tdpd_get_verlet.argtypes = [C.c_void_p] + [C.c_void_p] * 3
+    cfg = I.c1()  # 10^3 box, r_max = 1.58
+    rc, h = _create(cfg)
+    assert rc == 0
+    assert L.tdpd_set_verlet(h, -0.1, 5, 0) == -1
+    assert L.tdpd_set_verlet(h, float("nan"), 5, 0) == -1
+    assert L.tdpd_set_verlet(h, 0.3, -1, 0) == -1
+    assert L.tdpd_set_verlet(h, 0.3, 5, 5000) == -1
+    # 10 / (1.58 + 2.0) < 3 cells of the list radius
+    assert L.tdpd_set_verlet(h, 2.0, 5, 0) == -2
+    assert L.tdpd_set_verlet(h, 0.3, 5, 0) == 0
+    sk, ev, cap = C.c_float(), C.c_int32(), C.c_int32()
+    assert L.tdpd_get_verlet(h, C.byref(sk), C.byref(ev), C.byref(cap)) == 0
+    assert abs(sk.value - 0.3) < 1e-7 and ev.value == 5
+    # twice the mean count within 1.88 at rho = 4, plus 64, to a multiple of 32
+    mean = 4.0 / 3.0 * np.pi * np.float32(1.88) ** 3 * 4.0
+    assert cap.value == (int(2 * mean) + 64 + 31) // 32 * 32
+    assert L.tdpd_set_verlet(h, 0.0, 0, 0) == 0  # back to per-step cells
+    assert L.tdpd_get_verlet(h, C.byref(sk), C.byref(ev), C.byref(cap)) == 0
+    assert ev.value == 0 and cap.value == 0
+    L.tdpd_destroy(h)
+    # sheared boxes and the random flux are not taken
+    cfgs = I.c1()
+    cfgs.shear_rate = 0.5
+    rc, h = _create(cfgs, shear_rate=0.5)
+    assert rc == 0
+    assert L.tdpd_set_verlet(h, 0.3, 5, 0) == -8
+    L.tdpd_destroy(h)
+    rc, h = _create(cfg, m_s=0.05)
+    assert rc == 0
+    assert L.tdpd_set_verlet(h, 0.3, 5, 0) == -8
+    L.tdpd_destroy(h)
