@@ -264,13 +264,16 @@ int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *s
    checked every step: a larger displacement, or a particle with more
    than capacity list entries, makes the next tdpd_sync (and every call
    that syncs) return TDPD_ERR_LIST; the forces of that step are then
-   not to be trusted.  capacity 0 picks twice the mean count at the
-   nominal density rho plus 64 (at most 4096).  Cells are made at least
+   not to be trusted.  The capacity is rounded up to a multiple of 8 and
+   split evenly over the 8 sub-lists a particle's neighbours are dealt
+   into (the error is raised when one of them is full); capacity 0 picks
+   three times the mean count at the nominal density rho plus 128 (at most
+   4096).  Cells are made at least
    max(r_c, r_cc) + skin wide (TDPD_ERR_BOX_TOO_SMALL under 3 per side).
    Call after tdpd_create or tdpd_set_state and before the first step or
    force evaluation of that state (TDPD_ERR_STATE otherwise); skin 0 or
    every 0 switches back to per-step cells.  Not with Lees-Edwards boxes or
-   the random flux (TDPD_ERR_UNSUPPORTED).  Device memory: 4 * capacity + 52
+   the random flux (TDPD_ERR_UNSUPPORTED).  Device memory: 4 * capacity + 80
    bytes per particle.  Results differ from the cell path's only in
    summation order; tdpd_get_pairs then lists pairs from the lists, and
    checkpoints hold the lists, so a resumed run is bit-for-bit the

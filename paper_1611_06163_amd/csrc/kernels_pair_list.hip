@@ -4,22 +4,25 @@
 // and between rebuilds the pair kernel tests only those (about a quarter of
 // a 27-cell scan at the paper's densities).  The paper's GPU code keeps such
 // lists, rebuilt every few steps, in a transposed layout (performance
-// section); here entry k of particle i sits at nbr[k * n + i] so that a
-// wave's loads of one entry index are contiguous.
+// section); here a particle's list is dealt into kListLanes sub-lists in
+// such a layout, so that a wavefront's loads of one entry index are
+// contiguous.
 //
-// One thread per particle, full lists (each pair in both lists, each
-// particle sums its own row: no atomics, deterministic).  The flux is
-// accumulated while the list is walked; force pairs (about one entry in
-// seven) are appended to a per-lane queue in LDS and evaluated in a second
-// loop, so the Philox noise and the force arithmetic run on queued pairs
-// only instead of on every entry of the walk.
+// kListLanes lanes per particle, one per sub-list, and full lists (each pair
+// in both lists, each particle sums its own row: no atomics, deterministic;
+// the lanes' partial sums are added by shuffles in a fixed order).  Eight
+// lanes per particle give even the 24,500-particle single-cell system
+// 3,000 wavefronts.  The flux is accumulated while a sub-list is walked;
+// force pairs (about one entry in seven) are appended to a per-lane queue in
+// LDS and evaluated in a second loop, so the Philox noise and the force
+// arithmetic run on queued pairs only instead of on every entry.
 #include "launch_list.h"
 #include "pair_terms.h"
 
 namespace tdpd {
 
 constexpr int kListThreads = 256;
-constexpr int kForceQueue = 32;  // queued force pairs per lane before a flush
+constexpr int kForceQueue = 16;  // queued force pairs per lane before a flush
 
 template <int NS>
 struct ListShared {
@@ -91,15 +94,18 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
     sh.sigma[e] = pc.sigma[e];
   }
   __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * kListThreads + tid;
+  const int64_t t = int64_t(blockIdx.x) * kListThreads + tid;
+  const int64_t i = t / kListLanes;  // the kListLanes lanes of i are adjacent in one wavefront
+  const int lane = int(t % kListLanes);
   if (i >= n) return;
   const float4 pi = L.p4[i];
   const uint32_t infoi = __float_as_uint(pi.w);
+  const bool mobile = !info_frozen(infoi);
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float q[NS];
 #pragma unroll
   for (int sp = 0; sp < NS; ++sp) q[sp] = 0.f;
-  if (!info_frozen(infoi)) {
+  if (mobile) {
     const BoxDev &B = boxes[info_box(infoi)];
     const uint32_t k = *kdev;
     const float4 vi = L.v4[i];
@@ -108,12 +114,13 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
     for (int sp = 0; sp < NS; ++sp) ci[sp] = sp < S ? s.C[sp * n + i] : 0.f;
     const int ti = info_type(infoi), bi = info_body(infoi);
     const bool fick = (pc.terms & TDPD_TERM_FLUX_FICK) != 0;
-    const int cnt = int(L.ncnt[i]);
-    const uint32_t *row = L.nbr + i;
+    const int cnt = int(L.ncnt[t]);
+    const uint32_t *row = L.nbr + t;
+    const int64_t stride = n * kListLanes;
     int m = 0;
     unsigned zero = 0;
     for (int e = 0; e < cnt; ++e) {
-      const uint32_t j = row[int64_t(e) * n];
+      const uint32_t j = row[int64_t(e) * stride];
       const float4 pj = L.p4[j];
       const float dx = pair_disp(pj.x, pi.x, B.L[0]);
       const float dy = pair_disp(pj.y, pi.y, B.L[1]);
@@ -142,6 +149,19 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
     }
     flush_forces<NS>(pc, B, sh, tid, m, L.p4, L.v4, pi, vi, ti, k, fx, fy, fz);
     if (zero) atomicAdd(nzero, (unsigned long long)zero);
+  }
+  // the lanes of i hold the same i, so they all reach the shuffles
+#pragma unroll
+  for (int off = kListLanes / 2; off > 0; off >>= 1) {
+    fx += __shfl_xor(fx, off);
+    fy += __shfl_xor(fy, off);
+    fz += __shfl_xor(fz, off);
+#pragma unroll
+    for (int sp = 0; sp < NS; ++sp)
+      if (sp < S) q[sp] += __shfl_xor(q[sp], off);
+  }
+  if (lane != 0) return;
+  if (mobile) {
     if (pc.terms & TDPD_TERM_BODY_FORCE) {
       fx += pc.body_force[0];
       fy += pc.body_force[1];
@@ -161,7 +181,8 @@ void launch_pair_list(const PairConst &pc, const BoxDev *boxes, State s, int64_t
                       const uint32_t *kdev, const ListDev &L, float *F, float *Q,
                       unsigned long long *nzero, uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
-  const dim3 g(unsigned((n + kListThreads - 1) / kListThreads)), b(kListThreads);
+  const int64_t lanes = n * kListLanes;
+  const dim3 g(unsigned((lanes + kListThreads - 1) / kListThreads)), b(kListThreads);
   const int S = pc.n_species;
   if (S <= 1)
     hipLaunchKernelGGL(k_pair_list<1>, g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q, nzero, err);
@@ -175,72 +196,117 @@ void launch_pair_list(const PairConst &pc, const BoxDev *boxes, State s, int64_t
 }
 
 // ------------------------------------------------------------- list build
-// One thread per particle in the sorted order of the binning just done: the
-// 27 cells around its own (at least rl wide, so they hold every neighbour
-// within rl), each entry tested with the pair rule's displacement.
-__global__ void __launch_bounds__(256) k_list_build(const BoxDev *__restrict__ boxes, State s,
-                                                    const uint32_t *__restrict__ keys_sorted,
-                                                    const uint32_t *__restrict__ cell_start,
-                                                    int64_t n, ListDev L, uint32_t *err) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t info = s.info[i];
-  const BoxDev &B = boxes[info_box(info)];
-  const float xi = s.x[i], yi = s.y[i], zi = s.z[i];
-  L.p4[i] = make_float4(xi, yi, zi, __uint_as_float(info));
-  L.v4[i] = make_float4(s.vx[i], s.vy[i], s.vz[i], __uint_as_float(s.gid[i] - B.gid_base));
-  L.xref[i] = make_float4(xi, yi, zi, 0.f);
-  uint32_t cnt = 0;
-  {  // frozen particles too: their rows are not summed, but list pairs
-     // between two of them (tdpd_get_pairs)
+// One workgroup per cell (cells at least rl wide, so the 27 around a cell
+// hold every neighbour within rl of its particles).  The stencil's
+// positions, shifted into the cell's periodic image, are staged in LDS in
+// chunks of kStageMax; the cell's particles, kListLanes lanes each, test
+// them there.  A stencil's entries are dealt round the lanes in one
+// sequence (lane l takes entries l, l + kListLanes, ...), so the sub-lists
+// stay within one candidate of each other.  Frozen particles get lists too
+// (their rows are never summed, but tdpd_get_pairs lists pairs between two
+// of them).
+constexpr int kBuildThreads = 256;
+constexpr int kBuildHomes = kBuildThreads / kListLanes;  // particles per pass
+constexpr int kStageMax = 2048;                          // staged entries per chunk
+
+__global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__restrict__ boxes,
+                                                              int nbox, State s,
+                                                              const uint32_t *__restrict__ cell_start,
+                                                              int64_t n, ListDev L,
+                                                              uint32_t *err) {
+  __shared__ float4 stage[kStageMax];
+  __shared__ uint32_t cstart[27], cpref[28];
+  __shared__ float cshift[27][3];
+  const int tid = int(threadIdx.x);
+  const uint32_t c = blockIdx.x;
+  const BoxDev &B = boxes[box_of_cell(boxes, nbox, c)];
+  const uint32_t h0 = cell_start[c], h1 = cell_start[c + 1];
+  if (h0 == h1) return;  // uniform over the workgroup
+  if (tid < 27) {
     const int nx = B.nc[0], ny = B.nc[1], nz = B.nc[2];
-    const uint32_t key = keys_sorted[i] - B.cell_base;
+    const uint32_t key = c - B.cell_base;
     const int cx = int(key % uint32_t(nx));
     const int cy = int((key / uint32_t(nx)) % uint32_t(ny));
     const int cz = int(key / uint32_t(nx * ny));
-    for (int oz = -1; oz <= 1; ++oz) {
-      int qz = cz + oz;
-      float sz = 0.f;
-      if (qz < 0) { qz += nz; sz = -B.L[2]; }
-      else if (qz >= nz) { qz -= nz; sz = B.L[2]; }
-      for (int oy = -1; oy <= 1; ++oy) {
-        int qy = cy + oy;
-        float sy = 0.f;
-        if (qy < 0) { qy += ny; sy = -B.L[1]; }
-        else if (qy >= ny) { qy -= ny; sy = B.L[1]; }
-        for (int ox = -1; ox <= 1; ++ox) {
-          int qx = cx + ox;
-          float sx = 0.f;
-          if (qx < 0) { qx += nx; sx = -B.L[0]; }
-          else if (qx >= nx) { qx -= nx; sx = B.L[0]; }
-          const uint32_t c = B.cell_base + uint32_t((qz * ny + qy) * nx + qx);
-          const uint32_t j1 = cell_start[c + 1];
-          for (uint32_t j = cell_start[c]; j < j1; ++j) {
-            if (j == uint32_t(i)) continue;
-            const float d2 = dist2(disp(s.x[j], sx, xi), disp(s.y[j], sy, yi),
-                                   disp(s.z[j], sz, zi));
-            if (d2 < L.rl2) {
-              if (cnt < L.cap) L.nbr[int64_t(cnt) * n + i] = j;
-              ++cnt;
-            }
+    int qx = cx + tid % 3 - 1, qy = cy + (tid / 3) % 3 - 1, qz = cz + tid / 9 - 1;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    if (qx < 0) { qx += nx; sx = -B.L[0]; } else if (qx >= nx) { qx -= nx; sx = B.L[0]; }
+    if (qy < 0) { qy += ny; sy = -B.L[1]; } else if (qy >= ny) { qy -= ny; sy = B.L[1]; }
+    if (qz < 0) { qz += nz; sz = -B.L[2]; } else if (qz >= nz) { qz -= nz; sz = B.L[2]; }
+    const uint32_t q = B.cell_base + uint32_t((qz * ny + qy) * nx + qx);
+    cstart[tid] = cell_start[q];
+    cpref[tid + 1] = cell_start[q + 1] - cell_start[q];
+    cshift[tid][0] = sx;
+    cshift[tid][1] = sy;
+    cshift[tid][2] = sz;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    cpref[0] = 0;
+    for (int u = 0; u < 27; ++u) cpref[u + 1] += cpref[u];
+  }
+  __syncthreads();
+  const uint32_t total = cpref[27];
+  const uint32_t capl = L.cap / kListLanes;
+  const int64_t stride = n * kListLanes;
+  const uint32_t lane = uint32_t(tid % kListLanes);
+  for (uint32_t hb = h0; hb < h1; hb += kBuildHomes) {
+    const uint32_t i = hb + uint32_t(tid / kListLanes);
+    const bool home = i < h1;
+    float xi = 0.f, yi = 0.f, zi = 0.f;
+    if (home) {
+      xi = s.x[i];
+      yi = s.y[i];
+      zi = s.z[i];
+      if (lane == 0) {
+        const uint32_t info = s.info[i];
+        L.p4[i] = make_float4(xi, yi, zi, __uint_as_float(info));
+        L.v4[i] = make_float4(s.vx[i], s.vy[i], s.vz[i],
+                              __uint_as_float(s.gid[i] - B.gid_base));
+        L.xref[i] = make_float4(xi, yi, zi, 0.f);
+      }
+    }
+    uint32_t cnt = 0;
+    for (uint32_t base = 0; base < total; base += kStageMax) {
+      const uint32_t m = total - base < uint32_t(kStageMax) ? total - base : uint32_t(kStageMax);
+      __syncthreads();  // the previous chunk has been read
+      for (uint32_t p = uint32_t(tid); p < m; p += kBuildThreads) {
+        const uint32_t g = base + p;
+        int u = 0;
+        while (cpref[u + 1] <= g) ++u;
+        const uint32_t j = cstart[u] + (g - cpref[u]);
+        stage[p] = make_float4(s.x[j] + cshift[u][0], s.y[j] + cshift[u][1],
+                               s.z[j] + cshift[u][2], __uint_as_float(j));
+      }
+      __syncthreads();
+      if (home) {
+        for (uint32_t p = (lane - base) & uint32_t(kListLanes - 1); p < m; p += kListLanes) {
+          const float4 e = stage[p];
+          const uint32_t j = __float_as_uint(e.w);
+          const float dx = e.x - xi, dy = e.y - yi, dz = e.z - zi;
+          if (j != i && dist2(dx, dy, dz) < L.rl2) {
+            if (cnt < capl) L.nbr[int64_t(cnt) * stride + int64_t(i) * kListLanes + lane] = j;
+            ++cnt;
           }
         }
       }
     }
+    if (home) {
+      if (cnt > capl) {
+        atomicOr(err, kErrListFull);
+        cnt = capl;
+      }
+      L.ncnt[int64_t(i) * kListLanes + lane] = cnt;
+    }
   }
-  if (cnt > L.cap) {
-    atomicOr(err, kErrListFull);
-    cnt = L.cap;
-  }
-  L.ncnt[i] = cnt;
 }
 
-void launch_list_build(const BoxDev *boxes, State s, const uint32_t *keys_sorted,
-                       const uint32_t *cell_start, int64_t n, const ListDev &L, uint32_t *err,
+void launch_list_build(const BoxDev *boxes, int nbox, State s, const uint32_t *cell_start,
+                       int64_t ncell, int64_t n, const ListDev &L, uint32_t *err,
                        hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_list_build, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, boxes, s,
-                     keys_sorted, cell_start, n, L, err);
+  hipLaunchKernelGGL(k_list_build, dim3(unsigned(ncell)), dim3(kBuildThreads), 0, st, boxes, nbox,
+                     s, cell_start, n, L, err);
 }
 
 // ------------------------------------------------------------- pair listing
@@ -253,19 +319,23 @@ __global__ void __launch_bounds__(256) k_list_emit(const BoxDev *__restrict__ bo
   const float4 pi = L.p4[i];
   const uint32_t gi = s.gid[i];
   const BoxDev &B = boxes[info_box(__float_as_uint(pi.w))];
-  const int cnt = int(L.ncnt[i]);
-  for (int e = 0; e < cnt; ++e) {
-    const uint32_t j = L.nbr[int64_t(e) * n + i];
-    const uint32_t gj = s.gid[j];
-    if (gj <= gi) continue;
-    const float4 pj = L.p4[j];
-    const float d2 = dist2(pair_disp(pj.x, pi.x, B.L[0]), pair_disp(pj.y, pi.y, B.L[1]),
-                           pair_disp(pj.z, pi.z, B.L[2]));
-    if (d2 > 0.f && d2 < rcut2) {
-      const unsigned long long pos = atomicAdd(count, 1ull);
-      if (int64_t(pos) < cap) {
-        out[2 * pos] = int32_t(gi);
-        out[2 * pos + 1] = int32_t(gj);
+  const int64_t stride = n * kListLanes;
+  for (int l = 0; l < kListLanes; ++l) {
+    const int64_t t = i * kListLanes + l;
+    const int cnt = int(L.ncnt[t]);
+    for (int e = 0; e < cnt; ++e) {
+      const uint32_t j = L.nbr[int64_t(e) * stride + t];
+      const uint32_t gj = s.gid[j];
+      if (gj <= gi) continue;
+      const float4 pj = L.p4[j];
+      const float d2 = dist2(pair_disp(pj.x, pi.x, B.L[0]), pair_disp(pj.y, pi.y, B.L[1]),
+                             pair_disp(pj.z, pi.z, B.L[2]));
+      if (d2 > 0.f && d2 < rcut2) {
+        const unsigned long long pos = atomicAdd(count, 1ull);
+        if (int64_t(pos) < cap) {
+          out[2 * pos] = int32_t(gi);
+          out[2 * pos + 1] = int32_t(gj);
+        }
       }
     }
   }

@@ -24,24 +24,31 @@ __device__ __forceinline__ float pair_disp(float xj, float xi, float L) {
   return raw;
 }
 
+// Lanes that share one particle's list: its neighbours are dealt round-robin
+// at the build into kListLanes sub-lists, each walked by its own lane, and
+// the lanes' partial sums are added by shuffles in a fixed order.
+constexpr int kListLanes = 8;
+
 // Buffers of the list path, all in the sorted particle order of the last
-// rebuild: neighbour j of particle i at nbr[k * n + i] (k < ncnt[i]), the
+// rebuild: entry m of sub-list l of particle i at
+// nbr[m * (n * kListLanes) + i * kListLanes + l] (m < ncnt[i * kListLanes + l]),
+// so that a wavefront's loads of one entry index are contiguous; the
 // positions at the rebuild (xref), and per-step packed copies of the
 // particle data the pair kernel gathers: p4 = (x, y, z, info bits),
 // v4 = (vx, vy, vz, box-local gid bits).
 struct ListDev {
   uint32_t *nbr, *ncnt;
   float4 *xref, *p4, *v4;
-  uint32_t cap;       // neighbours per particle
+  uint32_t cap;       // neighbours per particle (a multiple of kListLanes)
   float rl2;          // (max(rc, rcc) + skin)^2
   float drift2;       // squared displacement that invalidates the list
 };
 
-// After the binning: lists of every non-frozen particle, within rl of it,
-// from the 27 cells around its own (cells must be at least rl wide), and
-// xref, p4, v4 of the new order.
-void launch_list_build(const BoxDev *boxes, State s, const uint32_t *keys_sorted,
-                       const uint32_t *cell_start, int64_t n, const ListDev &L, uint32_t *err,
+// After the binning: lists of every particle, within rl of it, from the 27
+// cells around its own (cells must be at least rl wide), and xref, p4, v4
+// of the new order.
+void launch_list_build(const BoxDev *boxes, int nbox, State s, const uint32_t *cell_start,
+                       int64_t ncell, int64_t n, const ListDev &L, uint32_t *err,
                        hipStream_t st);
 
 // First half of a step without binning: half kick and drift as k_prekick,

@@ -715,7 +715,7 @@ static int prepare(tdpd_sys *s) {
   s->list_valid = false;
   if (s->verlet_every > 0) {
     s->ld.nbr = dallocT<uint32_t>(s, size_t(s->ld.cap) * size_t(n));
-    s->ld.ncnt = dallocT<uint32_t>(s, n);
+    s->ld.ncnt = dallocT<uint32_t>(s, size_t(n) * kListLanes);
     s->ld.xref = dallocT<float4>(s, n);
     s->ld.p4 = dallocT<float4>(s, n);
     s->ld.v4 = dallocT<float4>(s, n);
@@ -979,7 +979,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   }
   if (rebuild) s->cur_A = !s->cur_A;
   if (verlet && rebuild)
-    launch_list_build(s->d_boxes, s->cur(), s->keys_s, s->cell_start, n, s->ld, s->errw, st);
+    launch_list_build(s->d_boxes, int(s->boxes.size()), s->cur(), s->cell_start, s->ncell, n,
+                      s->ld, s->errw, st);
   s->phase_end(1, tb, st);
   if (nrbc > 0 && !split) {
     (void)hipEventRecord(s->ev_fork, st);
@@ -1382,7 +1383,7 @@ std::vector<std::pair<void *, size_t>> ckpt_regions(tdpd_sys *s) {
       {s->Q, sizeof(float) * S * n}};
   if (nrbc) r.push_back({s->d_centroid, sizeof(double) * 3 * nrbc});
   if (s->verlet_every > 0) {  // the lists, so that a resumed run takes the same pairs in the same order
-    r.push_back({s->ld.ncnt, sizeof(uint32_t) * n});
+    r.push_back({s->ld.ncnt, sizeof(uint32_t) * n * kListLanes});
     r.push_back({s->ld.nbr, sizeof(uint32_t) * n * s->ld.cap});
     r.push_back({s->ld.xref, sizeof(float4) * n});
     r.push_back({s->ld.p4, sizeof(float4) * n});
@@ -1626,11 +1627,12 @@ extern "C" int tdpd_set_verlet(tdpd_sys *s, float skin, int32_t every, int32_t c
   s->ld = ListDev{};
   if (on) {
     int64_t cap = capacity;
-    if (cap == 0) {  // twice the mean count at the nominal density, with room
+    if (cap == 0) {  // three times the mean count at the nominal density, with room
+      // for membranes, whose vertices pack more densely than the solvent
       const double mean = 4.0 / 3.0 * M_PI * double(rl) * rl * rl * std::max(0.f, s->prm.rho);
-      cap = std::min<int64_t>(kMaxListCap, (int64_t(2.0 * mean) + 64 + 31) / 32 * 32);
+      cap = std::min<int64_t>(kMaxListCap, (int64_t(3.0 * mean) + 128 + 31) / 32 * 32);
     }
-    s->ld.cap = uint32_t(cap);
+    s->ld.cap = uint32_t((cap + kListLanes - 1) / kListLanes * kListLanes);
     s->ld.rl2 = rl * rl;
     const float h = 0.5f * skin * (1.f - 1e-3f);  // half the skin, less a rounding margin
     s->ld.drift2 = h * h;

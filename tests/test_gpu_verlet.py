@@ -186,3 +186,4 @@ def test_list_setting_refused_after_first_step():
         s.set_verlet(SKIN, EVERY)
     assert e.value.code == -7
     s.close()
+

@@ -118,9 +118,9 @@ def test_set_verlet_validation_on_host():
     sk, ev, cap = C.c_float(), C.c_int32(), C.c_int32()
     assert L.tdpd_get_verlet(h, C.byref(sk), C.byref(ev), C.byref(cap)) == 0
     assert abs(sk.value - 0.3) < 1e-7 and ev.value == 5
-    # twice the mean count within 1.88 at rho = 4, plus 64, to a multiple of 32
+    # three times the mean count within 1.88 at rho = 4, plus 128, to a multiple of 32
     mean = 4.0 / 3.0 * np.pi * np.float32(1.88) ** 3 * 4.0
-    assert cap.value == (int(2 * mean) + 64 + 31) // 32 * 32
+    assert cap.value == (int(3 * mean) + 128 + 31) // 32 * 32
     assert L.tdpd_set_verlet(h, 0.0, 0, 0) == 0  # back to per-step cells
     assert L.tdpd_get_verlet(h, C.byref(sk), C.byref(ev), C.byref(cap)) == 0
     assert ev.value == 0 and cap.value == 0
