@@ -323,6 +323,11 @@ __global__ void __launch_bounds__(256) k_prekick_list(PairConst pc,
   if (dist2(dx, dy, dz) > L.drift2) atomicOr(err, kErrSkin);
   L.p4[i] = make_float4(x, y, z, __uint_as_float(info));
   L.v4[i] = make_float4(vx, vy, vz, __uint_as_float(s.gid[i] - B.gid_base));
+  if (L.c4) {
+    const int S = pc.n_species;
+    L.c4[i] = make_float4(s.C[i], S > 1 ? s.C[n + i] : 0.f, S > 2 ? s.C[2 * n + i] : 0.f,
+                          S > 3 ? s.C[3 * n + i] : 0.f);
+  }
 }
 
 void launch_prekick_list(const PairConst &pc, const BoxDev *boxes, State s, const float *F,

@@ -109,9 +109,18 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
     const BoxDev &B = boxes[info_box(infoi)];
     const uint32_t k = *kdev;
     const float4 vi = L.v4[i];
+    // up to four species the concentrations come packed with one load
+    constexpr bool kPacked = NS <= 4;
     float ci[NS];
+    if (kPacked) {
+      const float4 c = L.c4[i];
+      const float cc[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
-    for (int sp = 0; sp < NS; ++sp) ci[sp] = sp < S ? s.C[sp * n + i] : 0.f;
+      for (int sp = 0; sp < NS; ++sp) ci[sp] = cc[sp];
+    } else {
+#pragma unroll
+      for (int sp = 0; sp < NS; ++sp) ci[sp] = sp < S ? s.C[sp * n + i] : 0.f;
+    }
     const int ti = info_type(infoi), bi = info_body(infoi);
     const bool fick = (pc.terms & TDPD_TERM_FLUX_FICK) != 0;
     const int cnt = int(L.ncnt[t]);
@@ -134,9 +143,17 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
       if (fick && d2 < pc.rcc2) {
         const float w = flux_weight(pc, d2);
         const int tt = ti * T + info_type(infoj);
+        if (kPacked) {
+          const float4 c = L.c4[j];
+          const float cj[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
-        for (int sp = 0; sp < NS; ++sp)
-          if (sp < S) q[sp] -= sh.kap[sp * T * T + tt] * w * (ci[sp] - s.C[sp * n + j]);
+          for (int sp = 0; sp < NS; ++sp)
+            if (sp < S) q[sp] -= sh.kap[sp * T * T + tt] * w * (ci[sp] - cj[sp]);
+        } else {
+#pragma unroll
+          for (int sp = 0; sp < NS; ++sp)
+            if (sp < S) q[sp] -= sh.kap[sp * T * T + tt] * w * (ci[sp] - s.C[sp * n + j]);
+        }
       }
       const int bj = info_body(infoj);
       if (d2 < pc.rc2 && !(bi >= 0 && bi == bj)) {
@@ -210,7 +227,7 @@ constexpr int kBuildHomes = kBuildThreads / kListLanes;  // particles per pass
 constexpr int kStageMax = 2048;                          // staged entries per chunk
 
 __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__restrict__ boxes,
-                                                              int nbox, State s,
+                                                              int nbox, State s, int nspec,
                                                               const uint32_t *__restrict__ cell_start,
                                                               int64_t n, ListDev L,
                                                               uint32_t *err) {
@@ -264,6 +281,11 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
         L.v4[i] = make_float4(s.vx[i], s.vy[i], s.vz[i],
                               __uint_as_float(s.gid[i] - B.gid_base));
         L.xref[i] = make_float4(xi, yi, zi, 0.f);
+        if (L.c4) {
+          const int S = nspec;
+          L.c4[i] = make_float4(s.C[i], S > 1 ? s.C[n + i] : 0.f, S > 2 ? s.C[2 * n + i] : 0.f,
+                                S > 3 ? s.C[3 * n + i] : 0.f);
+        }
       }
     }
     uint32_t cnt = 0;
@@ -301,12 +323,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
   }
 }
 
-void launch_list_build(const BoxDev *boxes, int nbox, State s, const uint32_t *cell_start,
-                       int64_t ncell, int64_t n, const ListDev &L, uint32_t *err,
-                       hipStream_t st) {
+void launch_list_build(const BoxDev *boxes, int nbox, State s, int nspec,
+                       const uint32_t *cell_start, int64_t ncell, int64_t n, const ListDev &L,
+                       uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_list_build, dim3(unsigned(ncell)), dim3(kBuildThreads), 0, st, boxes, nbox,
-                     s, cell_start, n, L, err);
+                     s, nspec, cell_start, n, L, err);
 }
 
 // ------------------------------------------------------------- pair listing

@@ -35,10 +35,11 @@ constexpr int kListLanes = 8;
 // so that a wavefront's loads of one entry index are contiguous; the
 // positions at the rebuild (xref), and per-step packed copies of the
 // particle data the pair kernel gathers: p4 = (x, y, z, info bits),
-// v4 = (vx, vy, vz, box-local gid bits).
+// v4 = (vx, vy, vz, box-local gid bits) and, for up to four species, c4 =
+// the concentrations (zero past the last species; null for more species).
 struct ListDev {
   uint32_t *nbr, *ncnt;
-  float4 *xref, *p4, *v4;
+  float4 *xref, *p4, *v4, *c4;
   uint32_t cap;       // neighbours per particle (a multiple of kListLanes)
   float rl2;          // (max(rc, rcc) + skin)^2
   float drift2;       // squared displacement that invalidates the list
@@ -47,9 +48,9 @@ struct ListDev {
 // After the binning: lists of every particle, within rl of it, from the 27
 // cells around its own (cells must be at least rl wide), and xref, p4, v4
 // of the new order.
-void launch_list_build(const BoxDev *boxes, int nbox, State s, const uint32_t *cell_start,
-                       int64_t ncell, int64_t n, const ListDev &L, uint32_t *err,
-                       hipStream_t st);
+void launch_list_build(const BoxDev *boxes, int nbox, State s, int nspec,
+                       const uint32_t *cell_start, int64_t ncell, int64_t n, const ListDev &L,
+                       uint32_t *err, hipStream_t st);
 
 // First half of a step without binning: half kick and drift as k_prekick,
 // then the displacement check against xref (kErrSkin) and p4, v4.

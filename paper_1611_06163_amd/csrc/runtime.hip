@@ -719,7 +719,8 @@ static int prepare(tdpd_sys *s) {
     s->ld.xref = dallocT<float4>(s, n);
     s->ld.p4 = dallocT<float4>(s, n);
     s->ld.v4 = dallocT<float4>(s, n);
-    if (!s->ld.nbr || !s->ld.ncnt || !s->ld.xref || !s->ld.p4 || !s->ld.v4)
+    s->ld.c4 = S <= 4 ? dallocT<float4>(s, n) : nullptr;
+    if (!s->ld.nbr || !s->ld.ncnt || !s->ld.xref || !s->ld.p4 || !s->ld.v4 || (S <= 4 && !s->ld.c4))
       return s->fail(TDPD_ERR_OOM, "device allocation failed");
   }
   HIPCHK(hipMemsetAsync(s->kdev, 0, sizeof(uint32_t), s->st));
@@ -979,8 +980,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   }
   if (rebuild) s->cur_A = !s->cur_A;
   if (verlet && rebuild)
-    launch_list_build(s->d_boxes, int(s->boxes.size()), s->cur(), s->cell_start, s->ncell, n,
-                      s->ld, s->errw, st);
+    launch_list_build(s->d_boxes, int(s->boxes.size()), s->cur(), s->S, s->cell_start, s->ncell,
+                      n, s->ld, s->errw, st);
   s->phase_end(1, tb, st);
   if (nrbc > 0 && !split) {
     (void)hipEventRecord(s->ev_fork, st);
@@ -1380,7 +1381,11 @@ std::vector<std::pair<void *, size_t>> ckpt_regions(tdpd_sys *s) {
       {c.gid, sizeof(uint32_t) * 2 * n},    // gid, info
       {s->slot_of_gid, sizeof(uint32_t) * n},
       {s->F, sizeof(float) * 3 * n},
-      {s->Q, sizeof(float) * S * n}};
+      {s->Q, sizeof(float) * S * n},
+      // the cells of the last binning (they hold the current positions),
+      // which tdpd_get_pairs reads
+      {s->keys_s, sizeof(uint32_t) * n},
+      {s->cell_start, sizeof(uint32_t) * (size_t(s->ncell) + 1)}};
   if (nrbc) r.push_back({s->d_centroid, sizeof(double) * 3 * nrbc});
   if (s->verlet_every > 0) {  // the lists, so that a resumed run takes the same pairs in the same order
     r.push_back({s->ld.ncnt, sizeof(uint32_t) * n * kListLanes});
@@ -1388,6 +1393,7 @@ std::vector<std::pair<void *, size_t>> ckpt_regions(tdpd_sys *s) {
     r.push_back({s->ld.xref, sizeof(float4) * n});
     r.push_back({s->ld.p4, sizeof(float4) * n});
     r.push_back({s->ld.v4, sizeof(float4) * n});
+    if (s->ld.c4) r.push_back({s->ld.c4, sizeof(float4) * n});
   }
   return r;
 }

@@ -274,11 +274,14 @@ def test_checkpoint_resume_bitwise(tmp_path):
     a.step(7)
     path = str(tmp_path / "ck.bin")
     a.save(path)
+    pairs7 = _sorted_pairs(a.pairs(1))
     a.step(8)
     ref = a.get_state() + a.get_forces()
     b = gpu_system(cfg)
     b.load(path)
     assert b.step_counter == 7
+    # the cells of the last binning come back too: pairs listed right away
+    assert np.array_equal(_sorted_pairs(b.pairs(1)), pairs7)
     b.step(8)
     got = b.get_state() + b.get_forces()
     for name, x, y in zip(("pos", "vel", "conc", "F", "Q"), got, ref):
