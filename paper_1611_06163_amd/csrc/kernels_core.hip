@@ -484,6 +484,13 @@ __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uin
   const int64_t p0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p0 >= n) return;
   const uint32_t q = tmp[p0], c = tmp[n + p0];
+  // the particle's state is loaded before its rank is known, so that those
+  // loads overlap the rank count's
+  const float x = a.x[q], y = a.y[q], z = a.z[q], vx = a.vx[q], vy = a.vy[q], vz = a.vz[q];
+  const uint32_t g = a.gid[q], info = a.info[q];
+  float cv[kMaxS];
+#pragma unroll
+  for (int sp = 0; sp < kMaxS; ++sp) cv[sp] = sp < nspec ? a.C[sp * n + q] : 0.f;
   const uint32_t s0 = start[c], s1 = start[c + 1];
   // rank among the cell's entries by previous slot; eight independent loads
   // per round so that their latencies overlap (past the cell end: no entry)
@@ -496,16 +503,17 @@ __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uin
     for (int u = 0; u < 8; ++u) r += t[u] < q ? 1u : 0u;
   }
   const uint32_t p = s0 + r;
-  b.x[p] = a.x[q];
-  b.y[p] = a.y[q];
-  b.z[p] = a.z[q];
-  b.vx[p] = a.vx[q];
-  b.vy[p] = a.vy[q];
-  b.vz[p] = a.vz[q];
-  for (int sp = 0; sp < nspec; ++sp) b.C[sp * n + p] = a.C[sp * n + q];
-  const uint32_t g = a.gid[q];
+  b.x[p] = x;
+  b.y[p] = y;
+  b.z[p] = z;
+  b.vx[p] = vx;
+  b.vy[p] = vy;
+  b.vz[p] = vz;
+#pragma unroll
+  for (int sp = 0; sp < kMaxS; ++sp)
+    if (sp < nspec) b.C[sp * n + p] = cv[sp];
   b.gid[p] = g;
-  b.info[p] = a.info[q];
+  b.info[p] = info;
   slot_of_gid[g] = p;
   keys_sorted[p] = c;
 }

@@ -187,3 +187,28 @@ def test_list_setting_refused_after_first_step():
     assert e.value.code == -7
     s.close()
 
+
+
+def test_list_batch_box_equals_solo_bitwise():
+    """Lists over a batch of boxes (cells and lists never cross boxes): a
+    box in the batch follows its solo trajectory bit for bit."""
+    boxes = I.ensemble(n_boxes=4, seed=11, lo=2500, hi=9000, shear_max=0.0)
+    c = I._suspension("batch_cell", (14.0, 14.0, 14.0), 3.0, 1, 1099, n_species=1,
+                      permeability=(1.0,))
+    c.box_id = len(boxes)
+    boxes.append(c)
+    bs = _listed(boxes)
+    bs.step(10)
+    pos, vel, conc = bs.get_state()
+    F, Q = bs.get_forces()
+    off = bs.box_offset
+    for b, cfg in enumerate(boxes):
+        solo = _listed(cfg)
+        solo.step(10)
+        p1, v1, c1 = solo.get_state()
+        F1, Q1 = solo.get_forces()
+        sl = slice(off[b], off[b + 1])
+        for name, a, r in [("pos", pos[sl], p1), ("vel", vel[sl], v1), ("conc", conc[sl], c1),
+                           ("F", F[sl], F1), ("Q", Q[sl], Q1)]:
+            assert np.array_equal(a, r), (b, name)
+        solo.close()
