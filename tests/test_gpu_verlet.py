@@ -212,3 +212,15 @@ def test_list_batch_box_equals_solo_bitwise():
                            ("F", F[sl], F1), ("Q", Q[sl], Q1)]:
             assert np.array_equal(a, r), (b, name)
         solo.close()
+
+
+def test_list_empty_and_single_particle():
+    s = _listed(I.make_fluid(box=(7.0, 7.0, 7.0), n=0))
+    s.step(5)
+    s.sync()
+    assert s.get_state()[0].shape == (0, 3)
+    s = _listed(I.make_fluid(box=(7.0, 7.0, 7.0), n=1))
+    s.step(9)
+    F, Q = s.get_forces()
+    assert np.all(F == 0) and np.all(Q == 0)
+    assert len(s.pairs(1)) == 0
