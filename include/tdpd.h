@@ -266,7 +266,8 @@ int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *s
    that syncs) return TDPD_ERR_LIST; the forces of that step are then
    not to be trusted.  The capacity is rounded up to a multiple of 8 and
    split evenly over the 8 sub-lists a particle's neighbours are dealt
-   into (the error is raised when one of them is full); capacity 0 picks
+   into (4 sub-lists from 131,072 particles on; the error is raised when
+   one of them is full); capacity 0 picks
    three times the mean count at the nominal density rho plus 128 (at most
    4096).  Cells are made at least
    max(r_c, r_cc) + skin wide (TDPD_ERR_BOX_TOO_SMALL under 3 per side).

@@ -4,15 +4,17 @@
 // and between rebuilds the pair kernel tests only those (about a quarter of
 // a 27-cell scan at the paper's densities).  The paper's GPU code keeps such
 // lists, rebuilt every few steps, in a transposed layout (performance
-// section); here a particle's list is dealt into kListLanes sub-lists in
+// section); here a particle's list is dealt into 4 or 8 sub-lists in
 // such a layout, so that a wavefront's loads of one entry index are
 // contiguous.
 //
-// kListLanes lanes per particle, one per sub-list, and full lists (each pair
-// in both lists, each particle sums its own row: no atomics, deterministic;
-// the lanes' partial sums are added by shuffles in a fixed order).  Eight
-// lanes per particle give even the 24,500-particle single-cell system
-// 3,000 wavefronts.  The flux is accumulated while a sub-list is walked;
+// One lane per sub-list, and full lists (each pair in both lists, each
+// particle sums its own row: no atomics, deterministic; the lanes' partial
+// sums are added by shuffles in a fixed order).  Eight lanes per particle
+// give even the 24,500-particle single-cell system 3,000 wavefronts; from
+// 131,072 particles on, four lanes fill the GPU with fewer shuffles and
+// longer walks (the 246,608-particle channel: pair kernel 187 against
+// 199 µs).  The flux is accumulated while a sub-list is walked;
 // force pairs (about one entry in seven) are appended to a per-lane queue in
 // LDS and evaluated in a second loop, so the Philox noise and the force
 // arithmetic run on queued pairs only instead of on every entry.
@@ -73,8 +75,9 @@ __device__ __forceinline__ void flush_forces(const PairConst &pc, const BoxDev &
   }
 }
 
-// NS: species bound of the build (the system's count S <= NS).
-template <int NS>
+// NS: species bound of the build (the system's count S <= NS); LANES:
+// sub-lists per particle.
+template <int NS, int LANES>
 __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
                                                             const BoxDev *__restrict__ boxes,
                                                             State s, int64_t n,
@@ -95,8 +98,8 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
   }
   __syncthreads();
   const int64_t t = int64_t(blockIdx.x) * kListThreads + tid;
-  const int64_t i = t / kListLanes;  // the kListLanes lanes of i are adjacent in one wavefront
-  const int lane = int(t % kListLanes);
+  const int64_t i = t / LANES;  // the LANES lanes of i are adjacent in one wavefront
+  const int lane = int(t % LANES);
   if (i >= n) return;
   const float4 pi = L.p4[i];
   const uint32_t infoi = __float_as_uint(pi.w);
@@ -125,7 +128,7 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
     const bool fick = (pc.terms & TDPD_TERM_FLUX_FICK) != 0;
     const int cnt = int(L.ncnt[t]);
     const uint32_t *row = L.nbr + t;
-    const int64_t stride = n * kListLanes;
+    const int64_t stride = n * LANES;
     int m = 0;
     unsigned zero = 0;
     for (int e = 0; e < cnt; ++e) {
@@ -169,7 +172,7 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
   }
   // the lanes of i hold the same i, so they all reach the shuffles
 #pragma unroll
-  for (int off = kListLanes / 2; off > 0; off >>= 1) {
+  for (int off = LANES / 2; off > 0; off >>= 1) {
     fx += __shfl_xor(fx, off);
     fy += __shfl_xor(fy, off);
     fz += __shfl_xor(fz, off);
@@ -194,38 +197,51 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
     if (sp < S) Q[int64_t(S) * i + sp] = q[sp];
 }
 
+template <int LANES>
+static void launch_pair_list_lanes(const PairConst &pc, const BoxDev *boxes, State s, int64_t n,
+                                   const uint32_t *kdev, const ListDev &L, float *F, float *Q,
+                                   unsigned long long *nzero, uint32_t *err, hipStream_t st) {
+  const int64_t lanes = n * LANES;
+  const dim3 g(unsigned((lanes + kListThreads - 1) / kListThreads)), b(kListThreads);
+  const int S = pc.n_species;
+  if (S <= 1)
+    hipLaunchKernelGGL((k_pair_list<1, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
+                       nzero, err);
+  else if (S <= 2)
+    hipLaunchKernelGGL((k_pair_list<2, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
+                       nzero, err);
+  else if (S <= 4)
+    hipLaunchKernelGGL((k_pair_list<4, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
+                       nzero, err);
+  else
+    hipLaunchKernelGGL((k_pair_list<kMaxS, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
+                       nzero, err);
+}
+
 void launch_pair_list(const PairConst &pc, const BoxDev *boxes, State s, int64_t n,
                       const uint32_t *kdev, const ListDev &L, float *F, float *Q,
                       unsigned long long *nzero, uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
-  const int64_t lanes = n * kListLanes;
-  const dim3 g(unsigned((lanes + kListThreads - 1) / kListThreads)), b(kListThreads);
-  const int S = pc.n_species;
-  if (S <= 1)
-    hipLaunchKernelGGL(k_pair_list<1>, g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q, nzero, err);
-  else if (S <= 2)
-    hipLaunchKernelGGL(k_pair_list<2>, g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q, nzero, err);
-  else if (S <= 4)
-    hipLaunchKernelGGL(k_pair_list<4>, g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q, nzero, err);
+  if (L.lanes == 4)
+    launch_pair_list_lanes<4>(pc, boxes, s, n, kdev, L, F, Q, nzero, err, st);
   else
-    hipLaunchKernelGGL(k_pair_list<kMaxS>, g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q, nzero,
-                       err);
+    launch_pair_list_lanes<8>(pc, boxes, s, n, kdev, L, F, Q, nzero, err, st);
 }
 
 // ------------------------------------------------------------- list build
 // One workgroup per cell (cells at least rl wide, so the 27 around a cell
 // hold every neighbour within rl of its particles).  The stencil's
 // positions, shifted into the cell's periodic image, are staged in LDS in
-// chunks of kStageMax; the cell's particles, kListLanes lanes each, test
+// chunks of kStageMax; the cell's particles, LANES lanes each, test
 // them there.  A stencil's entries are dealt round the lanes in one
-// sequence (lane l takes entries l, l + kListLanes, ...), so the sub-lists
+// sequence (lane l takes entries l, l + LANES, ...), so the sub-lists
 // stay within one candidate of each other.  Frozen particles get lists too
 // (their rows are never summed, but tdpd_get_pairs lists pairs between two
 // of them).
 constexpr int kBuildThreads = 256;
-constexpr int kBuildHomes = kBuildThreads / kListLanes;  // particles per pass
-constexpr int kStageMax = 2048;                          // staged entries per chunk
+constexpr int kStageMax = 2048;  // staged entries per chunk
 
+template <int LANES>
 __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__restrict__ boxes,
                                                               int nbox, State s, int nspec,
                                                               const uint32_t *__restrict__ cell_start,
@@ -264,11 +280,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
   }
   __syncthreads();
   const uint32_t total = cpref[27];
-  const uint32_t capl = L.cap / kListLanes;
-  const int64_t stride = n * kListLanes;
-  const uint32_t lane = uint32_t(tid % kListLanes);
-  for (uint32_t hb = h0; hb < h1; hb += kBuildHomes) {
-    const uint32_t i = hb + uint32_t(tid / kListLanes);
+  constexpr int kHomes = kBuildThreads / LANES;  // particles per pass
+  const uint32_t capl = L.cap / LANES;
+  const int64_t stride = n * LANES;
+  const uint32_t lane = uint32_t(tid % LANES);
+  for (uint32_t hb = h0; hb < h1; hb += kHomes) {
+    const uint32_t i = hb + uint32_t(tid / LANES);
     const bool home = i < h1;
     float xi = 0.f, yi = 0.f, zi = 0.f;
     if (home) {
@@ -302,12 +319,12 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
       }
       __syncthreads();
       if (home) {
-        for (uint32_t p = (lane - base) & uint32_t(kListLanes - 1); p < m; p += kListLanes) {
+        for (uint32_t p = (lane - base) & uint32_t(LANES - 1); p < m; p += LANES) {
           const float4 e = stage[p];
           const uint32_t j = __float_as_uint(e.w);
           const float dx = e.x - xi, dy = e.y - yi, dz = e.z - zi;
           if (j != i && dist2(dx, dy, dz) < L.rl2) {
-            if (cnt < capl) L.nbr[int64_t(cnt) * stride + int64_t(i) * kListLanes + lane] = j;
+            if (cnt < capl) L.nbr[int64_t(cnt) * stride + int64_t(i) * LANES + lane] = j;
             ++cnt;
           }
         }
@@ -318,7 +335,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
         atomicOr(err, kErrListFull);
         cnt = capl;
       }
-      L.ncnt[int64_t(i) * kListLanes + lane] = cnt;
+      L.ncnt[int64_t(i) * LANES + lane] = cnt;
     }
   }
 }
@@ -327,8 +344,12 @@ void launch_list_build(const BoxDev *boxes, int nbox, State s, int nspec,
                        const uint32_t *cell_start, int64_t ncell, int64_t n, const ListDev &L,
                        uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_list_build, dim3(unsigned(ncell)), dim3(kBuildThreads), 0, st, boxes, nbox,
-                     s, nspec, cell_start, n, L, err);
+  if (L.lanes == 4)
+    hipLaunchKernelGGL(k_list_build<4>, dim3(unsigned(ncell)), dim3(kBuildThreads), 0, st, boxes,
+                       nbox, s, nspec, cell_start, n, L, err);
+  else
+    hipLaunchKernelGGL(k_list_build<8>, dim3(unsigned(ncell)), dim3(kBuildThreads), 0, st, boxes,
+                       nbox, s, nspec, cell_start, n, L, err);
 }
 
 // ------------------------------------------------------------- pair listing
@@ -341,9 +362,9 @@ __global__ void __launch_bounds__(256) k_list_emit(const BoxDev *__restrict__ bo
   const float4 pi = L.p4[i];
   const uint32_t gi = s.gid[i];
   const BoxDev &B = boxes[info_box(__float_as_uint(pi.w))];
-  const int64_t stride = n * kListLanes;
-  for (int l = 0; l < kListLanes; ++l) {
-    const int64_t t = i * kListLanes + l;
+  const int64_t stride = n * L.lanes;
+  for (int l = 0; l < L.lanes; ++l) {
+    const int64_t t = i * L.lanes + l;
     const int cnt = int(L.ncnt[t]);
     for (int e = 0; e < cnt; ++e) {
       const uint32_t j = L.nbr[int64_t(e) * stride + t];

@@ -25,13 +25,15 @@ __device__ __forceinline__ float pair_disp(float xj, float xi, float L) {
 }
 
 // Lanes that share one particle's list: its neighbours are dealt round-robin
-// at the build into kListLanes sub-lists, each walked by its own lane, and
-// the lanes' partial sums are added by shuffles in a fixed order.
-constexpr int kListLanes = 8;
+// at the build into `lanes` sub-lists (8, or 4 for systems large enough to
+// fill the GPU with four), each walked by its own lane, and the lanes'
+// partial sums are added by shuffles in a fixed order.
+constexpr int kMaxListLanes = 8;
+constexpr int64_t kFourLaneParticles = 131072;  // from this many particles on, 4 lanes
 
 // Buffers of the list path, all in the sorted particle order of the last
 // rebuild: entry m of sub-list l of particle i at
-// nbr[m * (n * kListLanes) + i * kListLanes + l] (m < ncnt[i * kListLanes + l]),
+// nbr[m * (n * lanes) + i * lanes + l] (m < ncnt[i * lanes + l]),
 // so that a wavefront's loads of one entry index are contiguous; the
 // positions at the rebuild (xref), and per-step packed copies of the
 // particle data the pair kernel gathers: p4 = (x, y, z, info bits),
@@ -40,7 +42,8 @@ constexpr int kListLanes = 8;
 struct ListDev {
   uint32_t *nbr, *ncnt;
   float4 *xref, *p4, *v4, *c4;
-  uint32_t cap;       // neighbours per particle (a multiple of kListLanes)
+  uint32_t cap;       // neighbours per particle (a multiple of kMaxListLanes)
+  int lanes;          // sub-lists per particle (4 or 8)
   float rl2;          // (max(rc, rcc) + skin)^2
   float drift2;       // squared displacement that invalidates the list
 };

@@ -715,7 +715,8 @@ static int prepare(tdpd_sys *s) {
   s->list_valid = false;
   if (s->verlet_every > 0) {
     s->ld.nbr = dallocT<uint32_t>(s, size_t(s->ld.cap) * size_t(n));
-    s->ld.ncnt = dallocT<uint32_t>(s, size_t(n) * kListLanes);
+    s->ld.lanes = n >= kFourLaneParticles ? 4 : 8;
+    s->ld.ncnt = dallocT<uint32_t>(s, size_t(n) * s->ld.lanes);
     s->ld.xref = dallocT<float4>(s, n);
     s->ld.p4 = dallocT<float4>(s, n);
     s->ld.v4 = dallocT<float4>(s, n);
@@ -1388,7 +1389,7 @@ std::vector<std::pair<void *, size_t>> ckpt_regions(tdpd_sys *s) {
       {s->cell_start, sizeof(uint32_t) * (size_t(s->ncell) + 1)}};
   if (nrbc) r.push_back({s->d_centroid, sizeof(double) * 3 * nrbc});
   if (s->verlet_every > 0) {  // the lists, so that a resumed run takes the same pairs in the same order
-    r.push_back({s->ld.ncnt, sizeof(uint32_t) * n * kListLanes});
+    r.push_back({s->ld.ncnt, sizeof(uint32_t) * n * s->ld.lanes});
     r.push_back({s->ld.nbr, sizeof(uint32_t) * n * s->ld.cap});
     r.push_back({s->ld.xref, sizeof(float4) * n});
     r.push_back({s->ld.p4, sizeof(float4) * n});
@@ -1638,7 +1639,7 @@ extern "C" int tdpd_set_verlet(tdpd_sys *s, float skin, int32_t every, int32_t c
       const double mean = 4.0 / 3.0 * M_PI * double(rl) * rl * rl * std::max(0.f, s->prm.rho);
       cap = std::min<int64_t>(kMaxListCap, (int64_t(3.0 * mean) + 128 + 31) / 32 * 32);
     }
-    s->ld.cap = uint32_t((cap + kListLanes - 1) / kListLanes * kListLanes);
+    s->ld.cap = uint32_t((cap + kMaxListLanes - 1) / kMaxListLanes * kMaxListLanes);
     s->ld.rl2 = rl * rl;
     const float h = 0.5f * skin * (1.f - 1e-3f);  // half the skin, less a rounding margin
     s->ld.drift2 = h * h;

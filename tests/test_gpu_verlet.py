@@ -224,3 +224,34 @@ def test_list_empty_and_single_particle():
     F, Q = s.get_forces()
     assert np.all(F == 0) and np.all(Q == 0)
     assert len(s.pairs(1)) == 0
+
+
+def test_list_full_size_sampled_c3():
+    """The 246,608-particle channel (four sub-lists per particle from
+    131,072 particles on): sampled forces against the oracle after the setup
+    evaluation and after list steps past a rebuild."""
+    cfg = I.c3()
+    rng = np.random.default_rng(1)
+    which = np.zeros(cfg.n, np.uint8)
+    which[rng.choice(cfg.n, 3000, replace=False)] = 1
+    which[cfg.rbc_first_gid[0]:cfg.rbc_first_gid[0] + 500] = 1
+    o = Oracle(cfg)
+    frozen = (cfg.flags & I.FLAG_FROZEN) != 0
+    h = 0.5 * cfg.dt
+    s = _listed(cfg, skin=0.6)  # membrane vertices can move 0.26 in three steps
+    s.compute_forces(0)
+    for n in (0, 6):
+        if n:
+            s.step(n)
+            s.sync()
+        x, v, c = s.get_state()
+        F, Q = s.get_forces()
+        vh = v.astype(np.float64) - (h * F if n else 0.0)
+        ch = c.astype(np.float64) - (h * Q if n else 0.0)
+        vh[frozen] = 0.0
+        ch[frozen] = c[frozen]
+        ref = o.forces(x, vh, ch, k=n, which=which)
+        excl = near_cutoff_mask(o, cfg, x, vh, ref, n)
+        rep = compare_forces(F, Q, ref, exclude=excl, which=which, label=f"c3-full/list/{n}")
+        assert rep["badF"] == 0 and rep["badQ"] == 0
+    s.close()
