@@ -285,7 +285,7 @@ int tdpd_get_verlet(const tdpd_sys *s, float *skin, int32_t *every, int32_t *cap
 /* ---------------------------------------------------------------------
    Membrane surrogate.  Not part of the paper's method: a learned stand-in
    for the bending force (Eq. 19) plus the local-area force (Eq. 17, k_l
-   term) of a membrane vertex, with the plain forces as judge and fallback.
+   term) of a membrane vertex, with the plain forces as check and fallback.
 
    Network: 20 inputs -> 128 -> 128 -> 128 (SiLU after each) -> 3, on the
    matrix cores in bfloat16 with FP32 accumulation (weights, inputs and
