@@ -232,8 +232,9 @@ void launch_pair_list(const PairConst &pc, const BoxDev *boxes, State s, int64_t
 // One workgroup per cell (cells at least rl wide, so the 27 around a cell
 // hold every neighbour within rl of its particles).  The stencil's
 // positions, shifted into the cell's periodic image, are staged in LDS in
-// chunks of kStageMax; the cell's particles, LANES lanes each, test
-// them there.  A stencil's entries are dealt round the lanes in one
+// chunks of up to kStageMax, keeping only entries within rl of the cell's
+// box (about three quarters of the 27 cells' volume; compacted in stencil
+// order); the cell's particles, LANES lanes each, test them there.  A stencil's entries are dealt round the lanes in one
 // sequence (lane l takes entries l, l + LANES, ...), so the sub-lists
 // stay within one candidate of each other.  Frozen particles get lists too
 // (their rows are never summed, but tdpd_get_pairs lists pairs between two
@@ -250,6 +251,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
   __shared__ float4 stage[kStageMax];
   __shared__ uint32_t cstart[27], cpref[28];
   __shared__ float cshift[27][3];
+  __shared__ uint32_t wsum[kBuildThreads / 64];
   const int tid = int(threadIdx.x);
   const uint32_t c = blockIdx.x;
   const BoxDev &B = boxes[box_of_cell(boxes, nbox, c)];
@@ -280,6 +282,19 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
   }
   __syncthreads();
   const uint32_t total = cpref[27];
+  // the cell's box, widened by a rounding margin
+  float blo[3], bhi[3];
+  {
+    const uint32_t key = c - B.cell_base;
+    const int cc[3] = {int(key % uint32_t(B.nc[0])), int((key / uint32_t(B.nc[0])) % uint32_t(B.nc[1])),
+                       int(key / uint32_t(B.nc[0] * B.nc[1]))};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float h = B.L[a] / float(B.nc[a]), eps = 1e-4f * h;
+      blo[a] = float(cc[a]) * h - eps;
+      bhi[a] = float(cc[a] + 1) * h + eps;
+    }
+  }
   constexpr int kHomes = kBuildThreads / LANES;  // particles per pass
   const uint32_t capl = L.cap / LANES;
   const int64_t stride = n * LANES;
@@ -306,20 +321,43 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
       }
     }
     uint32_t cnt = 0;
-    for (uint32_t base = 0; base < total; base += kStageMax) {
-      const uint32_t m = total - base < uint32_t(kStageMax) ? total - base : uint32_t(kStageMax);
+    uint32_t dealt = 0;  // staged entries of the earlier chunks
+    for (uint32_t g0 = 0; g0 < total;) {  // uniform over the workgroup
+      uint32_t m = 0;
       __syncthreads();  // the previous chunk has been read
-      for (uint32_t p = uint32_t(tid); p < m; p += kBuildThreads) {
-        const uint32_t g = base + p;
-        int u = 0;
-        while (cpref[u + 1] <= g) ++u;
-        const uint32_t j = cstart[u] + (g - cpref[u]);
-        stage[p] = make_float4(s.x[j] + cshift[u][0], s.y[j] + cshift[u][1],
-                               s.z[j] + cshift[u][2], __uint_as_float(j));
+      while (g0 < total && m + kBuildThreads <= uint32_t(kStageMax)) {
+        const uint32_t g = g0 + uint32_t(tid);
+        bool keep = false;
+        float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (g < total) {
+          int u = 0;
+          while (cpref[u + 1] <= g) ++u;
+          const uint32_t j = cstart[u] + (g - cpref[u]);
+          e = make_float4(s.x[j] + cshift[u][0], s.y[j] + cshift[u][1], s.z[j] + cshift[u][2],
+                          __uint_as_float(j));
+          const float ex = fmaxf(fmaxf(blo[0] - e.x, e.x - bhi[0]), 0.f);
+          const float ey = fmaxf(fmaxf(blo[1] - e.y, e.y - bhi[1]), 0.f);
+          const float ez = fmaxf(fmaxf(blo[2] - e.z, e.z - bhi[2]), 0.f);
+          keep = dist2(ex, ey, ez) < L.rl2;
+        }
+        // compaction in stencil order: lanes before in the wavefront, then
+        // the earlier wavefronts' totals
+        const uint64_t bal = __ballot(keep);
+        const int w = tid >> 6, l = tid & 63;
+        if (l == 0) wsum[w] = uint32_t(__popcll(bal));
+        __syncthreads();
+        uint32_t off = m, tot = 0;
+        for (int q = 0; q < kBuildThreads / 64; ++q) {
+          if (q < w) off += wsum[q];
+          tot += wsum[q];
+        }
+        if (keep) stage[off + uint32_t(__popcll(bal & ((1ull << l) - 1ull)))] = e;
+        __syncthreads();  // wsum is rewritten by the next round
+        m += tot;
+        g0 += kBuildThreads;
       }
-      __syncthreads();
       if (home) {
-        for (uint32_t p = (lane - base) & uint32_t(LANES - 1); p < m; p += LANES) {
+        for (uint32_t p = (lane - dealt) & uint32_t(LANES - 1); p < m; p += LANES) {
           const float4 e = stage[p];
           const uint32_t j = __float_as_uint(e.w);
           const float dx = e.x - xi, dy = e.y - yi, dz = e.z - zi;
@@ -329,6 +367,7 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
           }
         }
       }
+      dealt += m;
     }
     if (home) {
       if (cnt > capl) {
