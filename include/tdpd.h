@@ -274,8 +274,8 @@ int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *s
    Call after tdpd_create or tdpd_set_state and before the first step or
    force evaluation of that state (TDPD_ERR_STATE otherwise); skin 0 or
    every 0 switches back to per-step cells.  Not with Lees-Edwards boxes or
-   the random flux (TDPD_ERR_UNSUPPORTED).  Device memory: 4 * capacity + 80
-   bytes per particle (96 up to four species).  Results differ from the cell path's only in
+   the random flux (TDPD_ERR_UNSUPPORTED).  Device memory: at most 4 * capacity +
+   96 bytes per particle.  Results differ from the cell path's only in
    summation order; tdpd_get_pairs then lists pairs from the lists, and
    checkpoints hold the lists, so a resumed run is bit-for-bit the
    uninterrupted one. */
