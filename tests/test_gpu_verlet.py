@@ -255,3 +255,30 @@ def test_list_full_size_sampled_c3():
         rep = compare_forces(F, Q, ref, exclude=excl, which=which, label=f"c3-full/list/{n}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
     s.close()
+
+
+@pytest.mark.parametrize("n_species", [3, 10])
+def test_list_many_species_match_oracle(n_species):
+    """Three species (concentrations packed four to a load) and ten (read
+    from the planes) on lists: forces and every flux against the oracle,
+    at the setup evaluation and after list steps past a rebuild."""
+    cfg = I.make_fluid(box=(8.0, 8.0, 8.0), rho=3.0, n_species=n_species, seed=23)
+    for sp in range(n_species):
+        cfg.kappa[sp] *= 1.0 + 0.25 * sp
+    s = _listed(cfg)
+    o = Oracle(cfg)
+    h = 0.5 * cfg.dt
+    s.compute_forces(0)
+    for n in (0, 6):
+        if n:
+            s.step(n)
+            s.sync()
+        x, v, c = s.get_state()
+        F, Q = s.get_forces()
+        assert Q.shape == (cfg.n, n_species)
+        vh = v.astype(np.float64) - (h * F if n else 0.0)
+        ch = c.astype(np.float64) - (h * Q if n else 0.0)
+        ref = o.forces(x, vh, ch, k=n)
+        excl = near_cutoff_mask(o, cfg, x, vh, ref, n)
+        rep = compare_forces(F, Q, ref, exclude=excl, label=f"{n_species} species/list/{n}")
+        assert rep["badF"] == 0 and rep["badQ"] == 0
