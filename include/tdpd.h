@@ -251,9 +251,9 @@ int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *s
                   int32_t *filter);
 
 /* ---------------------------------------------------------------------
-   Verlet neighbour lists (the paper's performance section: its GPU code
-   keeps per-particle neighbour lists, rebuilt every few steps, instead of
-   scanning cells every step).  With every > 0 and skin > 0, each particle
+   Verlet neighbour lists (Section 3.1: the paper's GPU code keeps
+   per-particle neighbour lists in a locally transposed layout; Section
+   5.2: its benchmarks refresh them every 5 steps).  With every > 0 and skin > 0, each particle
    keeps the list of every other particle closer than max(r_c, r_cc) + skin;
    the lists are rebuilt, together with the cell binning, on every
    every-th force evaluation (the first evaluation after set_state or

@@ -3,10 +3,10 @@
 // within max(rc, rcc) + skin, built from the cell binning every few steps,
 // and between rebuilds the pair kernel tests only those (about a quarter of
 // a 27-cell scan at the paper's densities).  The paper's GPU code keeps such
-// lists, rebuilt every few steps, in a transposed layout (performance
-// section); here a particle's list is dealt into 4 or 8 sub-lists in
-// such a layout, so that a wavefront's loads of one entry index are
-// contiguous.
+// lists in a locally transposed layout (Section 3.1) and refreshes them
+// every 5 steps in its benchmarks (Section 5.2); here a particle's list is
+// dealt into 4 or 8 sub-lists in such a layout, so that a wavefront's loads
+// of one entry index are contiguous.
 //
 // One lane per sub-list, and full lists (each pair in both lists, each
 // particle sums its own row: no atomics, deterministic; the lanes' partial

@@ -1,6 +1,6 @@
 // launch_list.h -- host-side launchers of the Verlet neighbour-list path
 // (the per-particle neighbour lists with a skin, rebuilt every few steps,
-// that the paper's GPU implementation uses in place of per-step cell scans).
+// that the paper's GPU implementation keeps: Sections 3.1 and 5.2).
 #pragma once
 
 #include "launch.h"
