@@ -147,10 +147,14 @@ void radix_sort(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys
 // for the run, and each lane adds its offset in the run.
 // The closing work of an evaluation for particle i: membrane forces added
 // into F, then (integrate) the second half kick of a mobile particle.
-// Returns the total force.
+// Returns the total force.  With vout (the kick folded into the next step's
+// first kick, in the same kernel) the kicked velocity is handed over in
+// registers instead of through memory.  Kicks are explicit fused
+// multiply-adds, so the folded and the separate kicks give the same bits.
 __device__ __forceinline__ float3 close_step(const PairConst &pc, State s, float *F,
                                              const float *Q, int64_t n, const VertexMap &vm,
-                                             bool integrate, int64_t i, uint32_t info) {
+                                             bool integrate, int64_t i, uint32_t info,
+                                             float3 *vout = nullptr) {
   float fx = F[3 * i], fy = F[3 * i + 1], fz = F[3 * i + 2];
   const int body = info_body(info);
   if (vm.Fm && body >= 0) {
@@ -164,10 +168,17 @@ __device__ __forceinline__ float3 close_step(const PairConst &pc, State s, float
   }
   if (integrate && !info_frozen(info)) {
     const float h = pc.half_dt;
-    s.vx[i] += h * fx;
-    s.vy[i] += h * fy;
-    s.vz[i] += h * fz;
-    for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+    const float3 v1 = make_float3(__fmaf_rn(h, fx, s.vx[i]), __fmaf_rn(h, fy, s.vy[i]),
+                                  __fmaf_rn(h, fz, s.vz[i]));
+    if (vout) {
+      *vout = v1;
+    } else {
+      s.vx[i] = v1.x;
+      s.vy[i] = v1.y;
+      s.vz[i] = v1.z;
+    }
+    for (int sp = 0; sp < pc.n_species; ++sp)
+      s.C[sp * n + i] = __fmaf_rn(h, Q[pc.n_species * i + sp], s.C[sp * n + i]);
   }
   return make_float3(fx, fy, fz);
 }
@@ -175,17 +186,20 @@ __device__ __forceinline__ float3 close_step(const PairConst &pc, State s, float
 // Half kick and drift of mobile particle i under force f: velocity and
 // concentration kick, drift, wall reflection, sheared-boundary crossing (at
 // the offsets of counter *kdev + finish) and wrap; stores the new x and v
-// and returns them.
+// and returns them; with vin the kick starts from *vin (the closing kick of
+// the previous step handed over by close_step).
 __device__ __forceinline__ void kick_drift(const PairConst &pc, const BoxDev &B, State s, float3 f,
                                            const float *__restrict__ Q, int64_t n, int64_t i,
                                            const uint32_t *__restrict__ kdev, int finish,
-                                           float &x, float &y, float &z, float &vx, float &vy,
-                                           float &vz) {
+                                           const float3 *vin, float &x, float &y, float &z,
+                                           float &vx, float &vy, float &vz) {
   const float h = pc.half_dt;
-  vx = s.vx[i] + h * f.x;
-  vy = s.vy[i] + h * f.y;
-  vz = s.vz[i] + h * f.z;
-  for (int sp = 0; sp < pc.n_species; ++sp) s.C[sp * n + i] += h * Q[pc.n_species * i + sp];
+  const float3 v0 = vin ? *vin : make_float3(s.vx[i], s.vy[i], s.vz[i]);
+  vx = __fmaf_rn(h, f.x, v0.x);
+  vy = __fmaf_rn(h, f.y, v0.y);
+  vz = __fmaf_rn(h, f.z, v0.z);
+  for (int sp = 0; sp < pc.n_species; ++sp)
+    s.C[sp * n + i] = __fmaf_rn(h, Q[pc.n_species * i + sp], s.C[sp * n + i]);
   x += pc.dt * vx;
   y += pc.dt * vy;
   z += pc.dt * vz;
@@ -247,15 +261,16 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
     const uint32_t info = s.info[i];
     const BoxDev &B = boxes[info_box(info)];
     float x = s.x[i], y = s.y[i], z = s.z[i];
-    float3 f;
+    float3 f, v1;
+    const bool carry = finish && integrate;  // this kernel kicks again
     if (finish) {
-      f = close_step(pc, s, F, Q, n, vprev, true, i, info);
+      f = close_step(pc, s, F, Q, n, vprev, true, i, info, carry ? &v1 : nullptr);
     } else {
       f = make_float3(F[3 * i], F[3 * i + 1], F[3 * i + 2]);
     }
     if (integrate && !info_frozen(info)) {
       float vx, vy, vz;
-      kick_drift(pc, B, s, f, Q, n, i, kdev, finish, x, y, z, vx, vy, vz);
+      kick_drift(pc, B, s, f, Q, n, i, kdev, finish, carry ? &v1 : nullptr, x, y, z, vx, vy, vz);
     }
     const int cx = cell_coord(x, B.inv_h[0], B.nc[0]);
     const int cy = cell_coord(y, B.inv_h[1], B.nc[1]);
@@ -311,7 +326,7 @@ __global__ void __launch_bounds__(256) k_prekick_list(PairConst pc,
   float vx, vy, vz;
   if (integrate && !info_frozen(info)) {
     const float3 f = make_float3(F[3 * i], F[3 * i + 1], F[3 * i + 2]);
-    kick_drift(pc, B, s, f, Q, n, i, kdev, 0, x, y, z, vx, vy, vz);
+    kick_drift(pc, B, s, f, Q, n, i, kdev, 0, nullptr, x, y, z, vx, vy, vz);
   } else {
     vx = s.vx[i];
     vy = s.vy[i];
