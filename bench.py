@@ -1,12 +1,16 @@
 """Throughput benchmark of the tDPD + RBC time step on one MI355X.
 
-Default workload: a single 500-vertex red cell in a 20^3 periodic box of
-density-3 solvent (24,000 solvent + 500 membrane particles, two species),
-the single-RBC configuration.  Prints one JSON line: particle-steps/s of the
-whole step (pair forces and fluxes, membrane terms, binning, velocity
-Verlet) with inputs resident in HBM, the pair kernel's ALU roofline figure
-from HIP events on the library's stream, and the CPU oracle timed on a
-bounded sample of the same workload.
+Default workload: the large suspension, 1000 red cells of 500 vertices in a
+96x96x72 periodic box of density-3 solvent (1,990,656 solvent + 500,000
+membrane particles, two species), the largest single-GPU configuration.
+Prints one JSON line: particle-steps/s of the whole step (pair forces and
+fluxes, membrane terms, binning, velocity Verlet) with inputs resident in
+HBM -- the median of several timed windows of exactly --steps steps -- the
+pair kernel's ALU roofline figure from HIP events on the library's stream,
+and the CPU oracle timed on a bounded sample of the same workload.  Further
+objects: the single-cell box, the batched ensemble, ten species, Verlet
+lists, the random flux and the membrane surrogate, each against the plain
+path on the same GPU.
 """
 import argparse
 import json
@@ -17,16 +21,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU issue slots per unit of pair-kernel work (non-packed FP32; quarter-rate
-# transcendentals and 32-bit multiplies count 4).  A candidate test is 3 sub,
-# 1 mul, 2 fma, 1 compare; a flux pair and species is rsqrt (4), r, weight
-# fma, max, square, C difference, two multiplies and the accumulate; a force
-# pair is rsqrt, e, weights incl. exp2/log2, e.v, three terms, the
-# accumulate, Philox-4x32-10 (10 rounds of two 32x32->64 products, xors
-# and key adds = 140) and Box-Muller (about 21).
-OPS_CANDIDATE = 7
-OPS_FLUX_PER_SPECIES = 12
-OPS_FORCE = 200
+# Algorithmic VALU lane-operations per unit of pair-kernel work (non-packed
+# FP32; quarter-rate transcendentals and 32-bit integer multiplies count 4):
+# a candidate test (displacement, squared distance, cutoff compare), a force
+# pair (weights, three force terms, Philox-4x32-10 and Box-Muller) and a flux
+# pair per species (weight, Fickian term, accumulate).  Candidate tests are
+# those of the 27-cell stencil of every mobile home particle.
+OPS_CANDIDATE = 10
+OPS_FLUX_PER_SPECIES = 16
+OPS_FORCE = 250
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol"
@@ -66,6 +69,9 @@ def pair_traffic(name, tile):
 
 def workload(name):
     from paper_1611_06163_amd import inputs as I
+    if name == "c5":
+        return I.c5(), ("1000 RBCs (500 vertices each) in 96x96x72 periodic tDPD solvent, rho=3, "
+                        "2 species")
     if name == "c2":
         return I.c2(), "single RBC (500 vertices) in 20^3 periodic tDPD solvent, rho=3, 2 species"
     if name == "c1":
@@ -107,7 +113,8 @@ def pair_work(sysg, cfg):
 
 
 def cpu_baseline(cfg, target_s=15.0):
-    import numpy as np
+    """The FP64 oracle stepping the same workload from its initial state (the
+    set-up force evaluation untimed) until target_s seconds have passed."""
     from oracle import Oracle
     o = Oracle(cfg)
     st = o.init_state()
@@ -121,8 +128,8 @@ def cpu_baseline(cfg, target_s=15.0):
         if el > target_s or k >= 5000:
             break
     return dict(value=cfg.n * k / el, unit="particle-steps/s", cores=cores, kind="oracle",
-                sample=f"{k} velocity-Verlet steps of the same workload from its initial "
-                       f"state, FP64 oracle, {cores} OpenMP threads, {el:.1f} s")
+                sample=f"{k} velocity-Verlet steps of the same workload ({cfg.n} particles) from "
+                       f"its initial state, FP64 oracle, {cores} OpenMP threads, {el:.1f} s")
 
 
 def _log(msg):
@@ -190,7 +197,8 @@ def species_leg(torch, tdpd, steps, warmup, n_species=10):
     sysg.autotune(reps=3)
     sysg.step(warmup)
     sysg.sync()
-    el = _timed_steps(torch, sysg, steps)
+    import numpy as np
+    el = float(np.median([_timed_steps(torch, sysg, steps) for _ in range(5)]))
     sysg.set_timing(tdpd.PHASE["pair"])
     sysg.step(steps)
     pair_ms, pair_n = sysg.get_timing(tdpd.PHASE["pair"])
@@ -227,7 +235,7 @@ def verlet_leg(torch, tdpd, steps, warmup, wl, skin, every):
                 kick_bin_list_us_per_step=bin_ms * 1e3 / max(bin_n, 1))
 
 
-def surrogate_leg(torch, tdpd, steps, warmup, workload):
+def surrogate_leg(torch, tdpd, steps, warmup, cfg, desc):
     """Train the membrane surrogate on samples of plain channel runs, then run
     the evaluation workload plain and with the network (fallback tolerance
     1e-2 of the cell's RMS plain force, checked every 10 steps)."""
@@ -239,7 +247,6 @@ def surrogate_leg(torch, tdpd, steps, warmup, workload):
     net, s_F, rep = SU.train(X, T, seed=0, batch=4096, steps=3000, lr=1e-3)
     t2 = time.perf_counter()
     _log(f"surrogate: {X.shape[0]} samples in {t1 - t0:.1f} s, trained in {t2 - t1:.1f} s: {rep}")
-    cfg = I.c5() if workload == "c5" else I.c3()
     runs = []
     for tol in (None, 1e-2, 0.1, 0.5):
         sysg = tdpd.System(cfg)
@@ -264,9 +271,7 @@ def surrogate_leg(torch, tdpd, steps, warmup, workload):
         sysg.close()
         _log(f"surrogate run {r}")
     plain, at = runs[0], runs[1]
-    return dict(workload=("1000 RBCs in 96x96x72" if workload == "c5" else
-                          "100 RBCs in 64x32x32 channel") + ", rho=3, 2 species",
-                particles=cfg.n, value=at["value"], unit="particle-steps/s", tol=1e-2,
+    return dict(workload=desc, particles=cfg.n, value=at["value"], unit="particle-steps/s", tol=1e-2,
                 plain_value=plain["value"], membrane_us=at["membrane_us"],
                 plain_membrane_us=plain["membrane_us"], on_network=at["on_network"],
                 by_tol=runs[1:],
@@ -276,54 +281,83 @@ def surrogate_leg(torch, tdpd, steps, warmup, workload):
                               data="channel 16x32x32, 25 cells, samples every 5 steps"))
 
 
+def plain_leg(torch, tdpd, cfg, desc, steps, warmup, windows=1):
+    """Median whole-step time of `windows` windows of `steps` steps on the
+    default path, after autotuning and warm-up."""
+    import numpy as np
+    sysg = tdpd.System(cfg)
+    sysg.compute_forces(0)
+    sysg.autotune(reps=3)
+    sysg.step(warmup)
+    sysg.sync()
+    els = [_timed_steps(torch, sysg, steps) for _ in range(windows)]
+    el = float(np.median(els))
+    tile = list(sysg.tile)
+    sysg.close()
+    return dict(workload=desc, particles=cfg.n, value=cfg.n * steps / el,
+                unit="particle-steps/s", ms_per_step=el * 1e3 / steps, tile=tile)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--windows", type=int, default=7,
+                    help="timed windows of --steps steps each; the median is reported")
+    ap.add_argument("--workload", default="c5", choices=["c5", "c3", "c2", "c1"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", type=int, default=None, help="pair kernel: 0 simple, 1 tiled")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shape of the pair kernel")
+    ap.add_argument("--no-census", action="store_true",
+                    help="skip the pair census (units of the roofline figure)")
+    ap.add_argument("--no-legs", action="store_true", help="skip every leg below")
+    ap.add_argument("--no-single", action="store_true", help="skip the single-cell leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-species", action="store_true", help="skip the ten-species leg")
-    ap.add_argument("--surrogate-workload", default="c3", choices=["c3", "c5"])
+    ap.add_argument("--no-randflux", action="store_true", help="skip the random-flux leg")
     ap.add_argument("--no-verlet", action="store_true", help="skip the neighbour-list leg")
-    ap.add_argument("--verlet", default="0.45,4", metavar="SKIN,EVERY",
+    ap.add_argument("--verlet", default="0.6,5", metavar="SKIN,EVERY",
                     help="skin and rebuild interval of the neighbour-list leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB device-to-device with torch (a plain "
                          "copy of known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU: the library has no "
+                                   "multi-GPU path, so --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.no_legs:
+        args.no_single = args.no_batched = args.no_surrogate = args.no_species = True
+        args.no_randflux = args.no_verlet = True
+    import numpy as np
     import torch
     from paper_1611_06163_amd import tdpd
     if args.kernel is not None:
         os.environ["TDPD_PAIR_KERNEL"] = str(args.kernel)
     torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
     cfg, desc = workload(args.workload)
+    _log(f"{args.workload}: {cfg.n} particles, {len(cfg.rbc_first_gid)} cells, generated in "
+         f"{time.perf_counter() - t_gen:.1f} s")
     sysg = tdpd.System(cfg)
     sysg.compute_forces(0)
     if not args.no_autotune:
         sysg.autotune(reps=5)  # before the warm-up: untimed
-    n_cand, n_flux, n_force = pair_work(sysg, cfg)
+    n_cand = n_flux = n_force = None
+    if not args.no_census:
+        n_cand, n_flux, n_force = pair_work(sysg, cfg)
     sysg.step(args.warmup)
     sysg.sync()
-    # the timed steps run on the library's default path (captured multi-step
-    # graphs); per-phase HIP events need the uncaptured path, so the pair
-    # kernel's launches are timed by events over a second window of as many
-    # steps right after
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sysg.step(args.steps)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sysg.sync()
+    # the timed windows run on the library's default path (captured
+    # multi-step graphs), each exactly --steps steps between two device
+    # synchronisations; per-phase HIP events need the uncaptured path, so
+    # the pair kernel's launches are timed by events over one more window of
+    # as many steps right after
+    els = [_timed_steps(torch, sysg, args.steps) for _ in range(args.windows)]
+    el = float(np.median(els))
     sysg.set_timing(tdpd.PHASE["pair"])
     torch.cuda.synchronize()
     t2 = time.perf_counter()
@@ -333,11 +367,26 @@ def main():
     sysg.sync()
     pair_ms, pair_n = sysg.get_timing(tdpd.PHASE["pair"])
     sysg.set_timing(0)
-    el = t1 - t0
     value = cfg.n * args.steps / el
-    ops = OPS_CANDIDATE * n_cand + OPS_FLUX_PER_SPECIES * cfg.n_species * n_flux + OPS_FORCE * n_force
     pair_avg_s = pair_ms / max(pair_n, 1) / 1e3
-    achieved = ops / pair_avg_s / 1e12
+    roof = {"bound": "alu", "kernel": "pair (forces + fluxes)", "peak": VALU_PEAK_TOPS,
+            "unit": "TOP/s", "traffic": pair_traffic(args.workload, sysg.tile),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+            "avg_launch_us": pair_avg_s * 1e6, "launches": pair_n,
+            "timing": "HIP events around each pair launch on the library's stream, over one "
+                      "more window of the same number of steps (uncaptured path, "
+                      f"{(t3 - t2) * 1e3 / args.steps:.4f} ms per step)",
+            "ops_per_unit": {"candidate_test": OPS_CANDIDATE, "force_pair": OPS_FORCE,
+                             "flux_pair_per_species": OPS_FLUX_PER_SPECIES}}
+    if n_cand is not None:
+        ops = (OPS_CANDIDATE * n_cand + OPS_FLUX_PER_SPECIES * cfg.n_species * n_flux
+               + OPS_FORCE * n_force)
+        achieved = ops / pair_avg_s / 1e12
+        roof.update(achieved=achieved, frac=achieved / VALU_PEAK_TOPS, ops_per_launch=ops,
+                    units_per_launch={"candidate_tests": n_cand, "flux_pairs": n_flux,
+                                      "force_pairs": n_force})
+    else:
+        roof.update(achieved=None, frac=None)
     d = sysg.diagnostics()
     out = {
         "metric": METRIC,
@@ -356,17 +405,9 @@ def main():
                    "n_species": cfg.n_species, "rbcs": len(cfg.rbc_first_gid),
                    "dt": cfg.dt, "pair_kernel": os.environ.get("TDPD_PAIR_KERNEL", "1"),
                    "tile": list(sysg.tile)},
-        "roofline": {"bound": "alu", "kernel": "pair (forces + fluxes)",
-                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": pair_traffic(args.workload, sysg.tile),
-                     "traffic_unit": "bytes per launch",
-                     "avg_launch_us": pair_avg_s * 1e6, "launches": pair_n,
-                     "timing": "HIP events around each pair launch on the library's stream, "
-                               "over a second window of the same number of steps (uncaptured "
-                               f"path, {(t3 - t2) * 1e3 / args.steps:.4f} ms per step)",
-                     "ops_per_launch": ops,
-                     "units_per_launch": {"candidate_tests": n_cand, "flux_pairs": n_flux,
-                                          "force_pairs": n_force}},
+        "windows": {"count": args.windows, "steps_each": args.steps,
+                    "ms_per_step": [e * 1e3 / args.steps for e in els], "reported": "median"},
+        "roofline": roof,
         "diagnostics": {"kT": d["kT"], "P": [float(x) for x in d["P"]]},
     }
     sysg.close()
@@ -378,24 +419,36 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
+    single = None
+    if not args.no_single or not args.no_species or not args.no_randflux:
+        c2, c2desc = workload("c2")
+        single = plain_leg(torch, tdpd, c2, c2desc, steps=200, warmup=20, windows=5)
+        out["single_rbc"] = single
     if not args.no_batched:
         out["batched"] = batched_leg(torch, tdpd, steps=20, warmup=5)
     if not args.no_verlet:
         skin, every = args.verlet.split(",")
         try:
-            vl = verlet_leg(torch, tdpd, steps=args.steps, warmup=args.warmup,
-                            wl=args.workload, skin=float(skin), every=int(every))
-            vl["vs_cells"] = vl["value"] / value
+            vl = verlet_leg(torch, tdpd, steps=200, warmup=20, wl="c2", skin=float(skin),
+                            every=int(every))
+            vl["vs_cells"] = vl["value"] / single["value"] if single else None
         except tdpd.TdpdError as e:  # e.g. the skin was too small for the interval
             vl = {"skin": float(skin), "every": int(every), "error": str(e)}
         out["verlet"] = vl
-    if not args.no_species and args.workload == "c2":
-        sp = species_leg(torch, tdpd, steps=args.steps, warmup=args.warmup)
-        sp["vs_two_species"] = sp["value"] / value
+    if not args.no_species:
+        sp = species_leg(torch, tdpd, steps=200, warmup=20)
+        sp["vs_two_species"] = sp["value"] / single["value"]
         out["species"] = sp
+    if not args.no_randflux:
+        from paper_1611_06163_amd import inputs as I
+        cr = I.c2()
+        cr.m_s = 0.05
+        rf = plain_leg(torch, tdpd, cr, "single RBC box with the random flux of Eqs. (9)-(10) "
+                                        "(m_s = 0.05)", steps=200, warmup=20, windows=5)
+        rf["vs_without"] = rf["value"] / single["value"]
+        out["random_flux"] = rf
     if not args.no_surrogate:
-        out["surrogate"] = surrogate_leg(torch, tdpd, steps=200, warmup=20,
-                                         workload=args.surrogate_workload)
+        out["surrogate"] = surrogate_leg(torch, tdpd, steps=100, warmup=10, cfg=cfg, desc=desc)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)

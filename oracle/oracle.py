@@ -71,7 +71,7 @@ def _load():
         L.orc_pairs.argtypes = [P, C.c_int64, P, C.c_int, C.c_int, C.c_uint32, C.c_int64, P, P,
                                 P]
         L.orc_forces.restype = C.c_int
-        L.orc_forces.argtypes = [P, C.c_int64, P, P, P, P, C.c_uint32, P, P, P, P, P, P, P, P]
+        L.orc_forces.argtypes = [P, C.c_int64, P, P, P, P, C.c_uint32, P, P, P, P, P, P, P, P, P]
         L.orc_membrane.restype = C.c_int
         L.orc_membrane.argtypes = [P, C.c_int64, P, P, C.c_uint32, P, P, P]
         L.orc_step.restype = C.c_int
@@ -247,13 +247,16 @@ class Oracle:
         nz = np.zeros(1, dtype=np.int64)
         w = None if which is None else np.ascontiguousarray(which, dtype=np.uint8)
         Fa = np.zeros(n)
+        Fm = np.zeros(n)
         Qa = np.zeros((n, cfg.n_species))
         err = self.L.orc_forces(self.h, n, _ptr(pos), _ptr(vel), _ptr(conc), _ptr(flags), k,
                                 _ptr(w), _ptr(F), _ptr(Q), _ptr(av), _ptr(en), _ptr(nz), _ptr(Fa),
-                                _ptr(Qa))
+                                _ptr(Qa), _ptr(Fm))
         # Fabs/Qabs: sum over contributions of their magnitudes (the scale of
-        # the rounding error of an FP32 sum of the same terms)
-        res = dict(F=F, Q=Q, av=av[:self.n_rbc], err=err, nzero=int(nz[0]), Fabs=Fa, Qabs=Qa)
+        # the rounding error of an FP32 sum of the same terms); Fmabs: the
+        # membrane terms' share of Fabs
+        res = dict(F=F, Q=Q, av=av[:self.n_rbc], err=err, nzero=int(nz[0]), Fabs=Fa, Qabs=Qa,
+                   Fmabs=Fm)
         if energy:
             res["energy"] = en
         return res

@@ -787,23 +787,25 @@ static int membrane(const orc_sys *s, int64_t n, const double *pos, const double
           sub3(P[(v + 2) % 3], P[(v + 1) % 3], opp);
           cross3(nh, opp, g);
           for (int q = 0; q < 3; ++q) f[3 * I[v] + q] -= (cg + cl) * 0.5 * g[q];
-          /* A and A0 (and A_j and A_0j) enter as separately rounded terms */
-          fab[I[v]] += (mp->kg * (At + M->A0) / M->A0 + mp->kl * (At_ + M->A0t[t]) / M->A0t[t]) *
-                       0.5 * vnorm(g);
+          /* Error scale of this term: the global coefficient itself (A^t is
+             a sum of exact triangle areas, so c_g carries only its own
+             rounding), the local triangle area A_j and its rest value A_0j
+             (separately rounded), times the gradient's size 1/2 |c - b|,
+             which does not depend on where the cell sits. */
+          fab[I[v]] += (fabs(cg) + mp->kl * (At_ + M->A0t[t]) / M->A0t[t]) * 0.5 * vnorm(g);
         }
       }
       if (terms & T_VOL) {
-        /* dV_t/da = 1/6 b x c, cyclic */
+        /* dV_t/da = 1/6 b x c, cyclic (the same vector for every origin:
+           1/6 (b - a) x (c - a) at a); error scale |c_v| |dV_t/da| */
         double g[3];
         cross3(b, c, g);
         for (int q = 0; q < 3; ++q) f[3 * ia + q] -= cv * g[q] / 6.0;
-        fab[ia] += mp->kv * (Vt + M->V0) / M->V0 * vnorm(g) / 6.0;
         cross3(c, a, g);
         for (int q = 0; q < 3; ++q) f[3 * ib + q] -= cv * g[q] / 6.0;
-        fab[ib] += mp->kv * (Vt + M->V0) / M->V0 * vnorm(g) / 6.0;
         cross3(a, b, g);
         for (int q = 0; q < 3; ++q) f[3 * ic + q] -= cv * g[q] / 6.0;
-        fab[ic] += mp->kv * (Vt + M->V0) / M->V0 * vnorm(g) / 6.0;
+        for (int v = 0; v < 3; ++v) fab[M->tri[3 * t + v]] += fabs(cv) * nl / 6.0;
       }
     }
     /* bending, Eq. (19) */
@@ -849,7 +851,8 @@ static double powp(double w, double e) { return w > 0 ? pow(w, e) : 0.0; }
 int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *vel,
                const double *conc, const uint32_t *flags, uint32_t k,
                const uint8_t *which, double *F, double *Q, double *av,
-               double *energy, int64_t *nzero_out, double *Fabs, double *Qabs) {
+               double *energy, int64_t *nzero_out, double *Fabs, double *Qabs,
+               double *Fmabs) {
   const orc_params *p = &s->p;
   const int n = (int)n64, S = p->n_species, T = p->n_types;
   const int terms = p->terms;
@@ -946,13 +949,15 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
   int err = 0;
   if (s->nrbc > 0) {
     double *Fm = (double *)calloc(3 * (size_t)(n > 0 ? n : 1), sizeof(double));
-    double *Fma = Fabs ? (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double)) : NULL;
+    double *Fma = (Fabs || Fmabs) ? (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double))
+                                  : NULL;
     err = membrane(s, n, pos, vel, k, Fm, energy, av, Fma);
     if (err >= 0)
       for (int i = 0; i < n; ++i) {
         if ((which && !which[i]) || (flags[i] & FROZEN_BIT)) continue;
         for (int a = 0; a < 3; ++a) F[3 * i + a] += Fm[3 * i + a];
         if (Fabs) Fabs[i] += Fma[i];
+        if (Fmabs) Fmabs[i] = Fma[i];
       }
     free(Fm);
     free(Fma);
@@ -1023,7 +1028,8 @@ int orc_step(const orc_sys *s, int64_t n64, double *pos, double *vel, double *co
     }
     for (int a = 0; a < 3; ++a) pos[3 * i + a] = wrap_pos(pos[3 * i + a], p->box[a]);
   }
-  const int err = orc_forces(s, n, pos, vel, conc, flags, k, NULL, F, Q, av, NULL, NULL, NULL, NULL);
+  const int err =
+      orc_forces(s, n, pos, vel, conc, flags, k, NULL, F, Q, av, NULL, NULL, NULL, NULL, NULL);
   for (int i = 0; i < n; ++i) {
     if (flags[i] & FROZEN_BIT) continue;
     for (int a = 0; a < 3; ++a) vel[3 * i + a] += h * F[3 * i + a];

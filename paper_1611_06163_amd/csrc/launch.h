@@ -25,7 +25,8 @@ struct MeshDev {
   const int32_t *ring_off;   // [nv+1] 1-ring of each vertex
   const int32_t *ring;       // counter-clockwise from outside, from the smallest index
   float ell;                 // mean rest edge length (surrogate feature scale)
-  float A0, V0, theta0;
+  double A0, V0;             // rest area and volume (FP64, as the totals they are compared with)
+  float theta0;
   float p, m_pow, kb, kg, kl, kv, gamma_t, gamma_c;
 };
 

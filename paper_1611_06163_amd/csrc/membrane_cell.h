@@ -1,7 +1,8 @@
 // membrane_cell.h -- the RBC membrane terms of one cell (Section 2.2) for
 // workgroups of any multiple of 64 threads, in three parts:
-//   1. K-Gather: per-triangle area and volume (FP32) summed in FP64 over the
-//      cell in a fixed order (A^t, V^t into av), plus the centroid update;
+//   1. K-Gather: per-triangle area and volume in FP64 (from the FP32
+//      positions, relative to the cell's FP64 centroid) summed over the cell
+//      in a fixed order (A^t, V^t into av), plus the centroid update;
 //   2. per bond, once: WLC + POW spring (Eqs. 13-14), viscosity (Eq. 15) and
 //      its random partner (Eq. 16), into the cell's scratch row;
 //   3. per vertex: the signed sum of its bond forces, the global/local area
@@ -99,25 +100,59 @@ __device__ __forceinline__ Cell stage_cell(const MemArgs &ma, const BoxDev *__re
   return Cell{&M, &B, nv, g0, le_offsets(B, k, ma.mc.dt), sl, px, py, pz};
 }
 
+// Nearest image of a relative to the FP64 point c, in FP64 (the shift of a
+// sheared box as in le_rel).
+__device__ __forceinline__ double3 rel64(const BoxDev &B, float3 a, double cx, double cy,
+                                         double cz, float delta) {
+  const double Lx = B.L[0], Ly = B.L[1], Lz = B.L[2];
+  double dx = double(a.x) - cx, dy = double(a.y) - cy, dz = double(a.z) - cz;
+  if (B.shear != 0.f) {
+    if (dy > 0.5 * Ly) {
+      dy -= Ly;
+      dx -= double(delta);
+    } else if (dy < -0.5 * Ly) {
+      dy += Ly;
+      dx += double(delta);
+    }
+  } else {
+    dy -= Ly * rint(dy / Ly);
+  }
+  return make_double3(dx - Lx * rint(dx / Lx), dy, dz - Lz * rint(dz / Lz));
+}
+
+__device__ __forceinline__ double3 sub64(double3 a, double3 b) {
+  return make_double3(a.x - b.x, a.y - b.y, a.z - b.z);
+}
+__device__ __forceinline__ double3 crs64(double3 a, double3 b) {
+  return make_double3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double dt64(double3 a, double3 b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+
 // 1. K-Gather: A^t, V^t into av[r], centroid[r] moved to the mean position.
+// Every triangle's area and volume term is evaluated in FP64 from the FP32
+// positions, so the totals, and with them the global area and volume
+// coefficients of Eqs. (17)-(18), carry no FP32 rounding.
 __device__ __forceinline__ void kgather(const MemArgs &ma, const Cell &C, int r, char *lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const MeshDev &M = *C.M;
   double *red = reinterpret_cast<double *>(lds + (size_t(C.nv) * 16 + 7) / 8 * 8);
   double *tot = red + (nt / 64) * 5;
-  const float3 cf = make_float3(float(ma.centroid[3 * r]), float(ma.centroid[3 * r + 1]),
-                                float(ma.centroid[3 * r + 2]));
+  const double cx = ma.centroid[3 * r], cy = ma.centroid[3 * r + 1], cz = ma.centroid[3 * r + 2];
+  const BoxDev &B = *C.B;
+  const float del = C.le.delta;
   double acc[5] = {0, 0, 0, 0, 0};
   for (int t = tid; t < M.ntri; t += nt) {
-    const float3 a = C.rel(C.P(M.tri[3 * t]), cf);
-    const float3 b = C.rel(C.P(M.tri[3 * t + 1]), cf);
-    const float3 c = C.rel(C.P(M.tri[3 * t + 2]), cf);
-    const float3 nn = crs(sub(b, a), sub(c, a));
-    acc[0] += double(0.5f * sqrtf(dt3(nn, nn)));
-    acc[1] += double(dt3(a, crs(b, c)) * (1.f / 6.f));
+    const double3 a = rel64(B, C.P(M.tri[3 * t]), cx, cy, cz, del);
+    const double3 b = rel64(B, C.P(M.tri[3 * t + 1]), cx, cy, cz, del);
+    const double3 c = rel64(B, C.P(M.tri[3 * t + 2]), cx, cy, cz, del);
+    const double3 nn = crs64(sub64(b, a), sub64(c, a));
+    acc[0] += 0.5 * sqrt(dt64(nn, nn));
+    acc[1] += dt64(a, crs64(b, c)) * (1.0 / 6.0);
   }
   for (int v = tid; v < C.nv; v += nt) {
-    const float3 a = C.rel(C.P(v), cf);
+    const double3 a = rel64(B, C.P(v), cx, cy, cz, del);
     acc[2] += a.x;
     acc[3] += a.y;
     acc[4] += a.z;
@@ -142,9 +177,9 @@ __device__ __forceinline__ void kgather(const MemArgs &ma, const Cell &C, int r,
   if (tid == 0 && !ma.mc.local_only) {
     ma.av[2 * r] = tot[0];
     ma.av[2 * r + 1] = tot[1];
-    ma.centroid[3 * r] = double(cf.x) + tot[2] / C.nv;
-    ma.centroid[3 * r + 1] = double(cf.y) + tot[3] / C.nv;
-    ma.centroid[3 * r + 2] = double(cf.z) + tot[4] / C.nv;
+    ma.centroid[3 * r] = cx + tot[2] / C.nv;
+    ma.centroid[3 * r + 1] = cy + tot[3] / C.nv;
+    ma.centroid[3 * r + 2] = cz + tot[4] / C.nv;
   }
 }
 

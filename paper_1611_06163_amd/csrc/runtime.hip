@@ -798,8 +798,8 @@ static int prepare(tdpd_sys *s) {
       s->mem_lds = std::max(s->mem_lds, membrane_lds_bytes(M.nv));
       s->bond_stride = std::max<int64_t>(s->bond_stride, D.nbond);
       s->max_nv = std::max(s->max_nv, M.nv);
-      D.A0 = float(M.A0);
-      D.V0 = float(M.V0);
+      D.A0 = M.A0;
+      D.V0 = M.V0;
       D.theta0 = float(M.theta0);
       D.p = M.mp.p;
       D.m_pow = M.mp.m_pow;

@@ -199,29 +199,42 @@ __device__ __forceinline__ float le_lift_x(float x, float xo, float delta, float
   return __fadd_rn(X1, m * Lx);
 }
 
+// Nearest-image difference a - o of two coordinates in [0, L): the
+// coordinate that moves by a box length is moved first, which is exact
+// (Sterbenz: it lies in [L/2, L)), so only the final difference rounds.
+__device__ __forceinline__ float near_diff(float a, float o, float L) {
+  const float d = a - o;
+  if (d > 0.5f * L) return (a - L) - o;
+  if (d < -0.5f * L) return a - (o - L);
+  return d;
+}
+
 // nearest-image difference a - o in a (possibly sheared) box; *ny gets -1
 // when a was taken in the image below o (+1 above), which shifts a's x
 // velocity by -u (+u)
 __device__ __forceinline__ float3 le_rel(const BoxDev &B, float3 a, float3 o, float delta,
                                          int *ny) {
-  float dx = a.x - o.x, dy = a.y - o.y;
   int s = 0;
+  float dx, dy;
   if (B.shear != 0.f) {
+    dx = a.x - o.x;
+    dy = a.y - o.y;
     if (dy > 0.5f * B.L[1]) {
-      dy -= B.L[1];
+      dy = (a.y - B.L[1]) - o.y;
       dx -= delta;
       s = -1;
     } else if (dy < -0.5f * B.L[1]) {
-      dy += B.L[1];
+      dy = a.y - (o.y - B.L[1]);
       dx += delta;
       s = 1;
     }
+    dx = min_image(dx, B.L[0], B.invL[0]);
   } else {
-    dy = min_image(dy, B.L[1], B.invL[1]);
+    dx = near_diff(a.x, o.x, B.L[0]);
+    dy = near_diff(a.y, o.y, B.L[1]);
   }
   if (ny) *ny = s;
-  return make_float3(min_image(dx, B.L[0], B.invL[0]), dy,
-                     min_image(a.z - o.z, B.L[2], B.invL[2]));
+  return make_float3(dx, dy, near_diff(a.z, o.z, B.L[2]));
 }
 
 }  // namespace tdpd

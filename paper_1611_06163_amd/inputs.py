@@ -189,15 +189,23 @@ def place_cells(template, n_cells, box, rng, lo=None, hi=None, min_sep=0.9,
                 max_tries=200000):
     """Random sequential placement of rigidly rotated copies of the template
     inside [lo, hi) (per axis), rejecting any copy whose vertices come closer
-    than min_sep to an already placed vertex (periodic in every axis whose
-    range spans the whole box).  Returns a list of [nv,3] float64 arrays."""
+    than min_sep to an already placed vertex (distances periodic in every
+    axis).  Returns a list of [nv,3] float64 arrays.
+
+    A try is checked only against the placed copies whose centre lies within
+    two template radii plus min_sep (in any periodic image), each through its
+    own k-d tree, so the cost of a try does not grow with the number placed."""
     from scipy.spatial import cKDTree
     box = np.asarray(box, dtype=np.float64)
     lo = np.zeros(3) if lo is None else np.asarray(lo, dtype=np.float64)
     hi = box.copy() if hi is None else np.asarray(hi, dtype=np.float64)
     periodic = (lo <= 0) & (hi >= box)
-    placed, all_pts = [], np.zeros((0, 3))
-    tree = None
+    radius = float(np.linalg.norm(template - template.mean(axis=0), axis=1).max())
+    reach = 2.0 * radius + min_sep
+    # periodic images of a neighbour's centre that can come within reach
+    shifts = np.stack(np.meshgrid(*[np.arange(-2, 3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    shifts = shifts * box
+    placed, centres, trees = [], np.zeros((0, 3)), []
     tries = 0
     while len(placed) < n_cells:
         tries += 1
@@ -220,18 +228,29 @@ def place_cells(template, n_cells, box, rng, lo=None, hi=None, min_sep=0.9,
         if not ok:
             continue
         pts = pts + c
-        if tree is not None:
-            w = np.mod(pts, box)
-            # a coarse subset rejects most overlapping tries cheaply
-            d, _ = tree.query(w[::16], k=1, distance_upper_bound=min_sep)
-            if np.isfinite(d).any():
-                continue
-            d, _ = tree.query(w, k=1, distance_upper_bound=min_sep)
-            if np.isfinite(d).any():
-                continue
+        cen = pts.mean(axis=0)
+        clash = False
+        if len(centres):
+            d = cen - centres
+            d -= box * np.round(d / box)
+            for j in np.nonzero(np.linalg.norm(d, axis=1) < reach + 1e-9)[0]:
+                # every image of the try that can reach copy j (a coarse
+                # subset of its vertices first rejects most clashes cheaply)
+                base = cen - (centres[j] + d[j])  # the try moved next to copy j
+                near = shifts[np.linalg.norm(d[j] + shifts, axis=1) < reach + 1e-9]
+                for sub in (pts[::16], pts):
+                    q = (sub - base)[None, :, :] + near[:, None, :]
+                    dist, _ = trees[j].query(q.reshape(-1, 3), k=1, distance_upper_bound=min_sep)
+                    if np.isfinite(dist).any():
+                        clash = True
+                        break
+                if clash:
+                    break
+        if clash:
+            continue
         placed.append(pts)
-        all_pts = np.concatenate([all_pts, np.mod(pts, box)])
-        tree = cKDTree(all_pts, boxsize=box + 1e-9)
+        centres = np.concatenate([centres, cen[None]])
+        trees.append(cKDTree(pts))
     return placed
 
 

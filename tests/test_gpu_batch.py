@@ -5,7 +5,7 @@ the oracle of that box."""
 import numpy as np
 import pytest
 
-from gpu_helpers import compare_forces, gpu_system, near_cutoff_mask
+from gpu_helpers import compare_forces, gpu_system, near_cutoff
 from oracle import Oracle
 from paper_1611_06163_amd import inputs as I
 
@@ -52,7 +52,7 @@ def test_batch_forces_match_oracle_per_box():
         sl = slice(off[b], off[b + 1])
         o = Oracle(cfg)
         ref = o.forces(pos[sl], vel[sl], conc[sl], k=5)
-        excl = near_cutoff_mask(o, cfg, pos[sl], vel[sl], ref, 5)
-        rep = compare_forces(F[sl], Q[sl], ref, exclude=excl, label=f"batch box {b}")
+        excl, sens = near_cutoff(o, cfg, pos[sl], vel[sl], ref, 5)
+        rep = compare_forces(F[sl], Q[sl], ref, exclude=excl, sens=sens, label=f"batch box {b}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         assert rep["excluded"] <= 5 + cfg.n // 20

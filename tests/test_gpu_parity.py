@@ -11,7 +11,7 @@ are counted, reported and bounded.
 import numpy as np
 import pytest
 
-from gpu_helpers import compare_forces, gpu_system, near_cutoff_mask
+from gpu_helpers import compare_forces, gpu_system, near_cutoff
 from oracle import Oracle
 from paper_1611_06163_amd import inputs as I
 from paper_1611_06163_amd import tdpd
@@ -81,8 +81,8 @@ def test_teacher_forced_forces(kernel, name):
     o = Oracle(cfg)
     ref = o.forces(pos, vel, conc, k=k)
     assert ref["err"] == 0
-    excl = near_cutoff_mask(o, cfg, pos, vel, ref, k)
-    rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/k{kernel}")
+    excl, sens = near_cutoff(o, cfg, pos, vel, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"{name}/k{kernel}")
     assert rep["badF"] == 0 and rep["badQ"] == 0
     # a few percent of particles have a force pair close enough to r_c
     assert rep["excluded"] <= 5 + cfg.n // 20
@@ -129,8 +129,8 @@ def test_ten_steps_teacher_forced(name):
         vh[frozen] = 0.0
         ch[frozen] = c[frozen]
         ref = o.forces(x, vh, ch, k=n)
-        excl = near_cutoff_mask(o, cfg, x, vh, ref, n)
-        rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/step{n}")
+        excl, sens = near_cutoff(o, cfg, x, vh, ref, n)
+        rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"{name}/step{n}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         x0, v0, c0, F0, Q0 = x, v, c, F, Q
 
@@ -149,11 +149,22 @@ def test_free_running_trajectory_error_reported():
     dx = x - st["pos"]
     dx -= L * np.round(dx / L)
     err = np.linalg.norm(dx, axis=1)
-    print("free-running 10 steps: max |dx| %.3e, p99 %.3e, max |dv| %.3e, max |dC| %.3e" % (
-        err.max(), np.quantile(err, 0.99), np.abs(v - st["vel"]).max(),
-        np.abs(c - st["conc"]).max()), flush=True)
+    ev = np.linalg.norm(v - st["vel"], axis=1)
+    ec = np.abs(c - st["conc"]).max(axis=1)
+    print("free-running 10 steps: |dx| max %.3e p99 %.3e, |dv| max %.3e p99 %.3e, "
+          "|dC| max %.3e p99 %.3e" % (err.max(), np.quantile(err, 0.99), ev.max(),
+                                     np.quantile(ev, 0.99), ec.max(), np.quantile(ec, 0.99)),
+          flush=True)
+    # FP32 trajectories separate from the FP64 ones only through rounding,
+    # amplified where a pair sits at the force cutoff (a pair counted on one
+    # side only moves its particles' velocities by up to dt/2 times the
+    # cutoff noise force): bounds on the bulk (99th percentile) and the worst
     assert np.quantile(err, 0.99) < 1e-4
     assert err.max() < 1e-2
+    assert np.quantile(ev, 0.99) < 1e-3
+    assert ev.max() < 0.5
+    assert np.quantile(ec, 0.99) < 1e-4
+    assert ec.max() < 1e-2
 
 
 def test_conservation_on_gpu():
@@ -260,8 +271,8 @@ def test_full_size_sampled_c3():
         F, Q = sysg.get_forces()
         pos, vel, conc = sysg.get_state()
         ref = o.forces(pos, vel, conc, k=3, which=which)
-        excl = near_cutoff_mask(o, cfg, pos, vel, ref, 3)
-        rep = compare_forces(F, Q, ref, exclude=excl, which=which, label=f"c3-full/k{kernel}")
+        excl, sens = near_cutoff(o, cfg, pos, vel, ref, 3)
+        rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, which=which, label=f"c3-full/k{kernel}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         sysg.close()
 
@@ -315,8 +326,8 @@ def test_tile_shapes_match_oracle(tile, name):
     pos, vel, conc = sysg.get_state()
     o = Oracle(cfg)
     ref = o.forces(pos, vel, conc, k=k)
-    excl = near_cutoff_mask(o, cfg, pos, vel, ref, k)
-    rep = compare_forces(F, Q, ref, exclude=excl, label=f"{name}/tile{tile}")
+    excl, sens = near_cutoff(o, cfg, pos, vel, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"{name}/tile{tile}")
     assert rep["badF"] == 0 and rep["badQ"] == 0
     assert rep["excluded"] <= 5 + cfg.n // 20
 
@@ -344,8 +355,8 @@ def test_ten_species_match_oracle(kernel, tile):
     pos, vel, conc = sysg.get_state()
     o = Oracle(cfg)
     ref = o.forces(pos, vel, conc, k=k)
-    excl = near_cutoff_mask(o, cfg, pos, vel, ref, k)
-    rep = compare_forces(F, Q, ref, exclude=excl, label=f"10 species/k{kernel}/{tile}")
+    excl, sens = near_cutoff(o, cfg, pos, vel, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"10 species/k{kernel}/{tile}")
     assert rep["badF"] == 0 and rep["badQ"] == 0
     assert rep["excluded"] <= 5 + cfg.n // 20
 

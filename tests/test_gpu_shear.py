@@ -7,7 +7,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_helpers import compare_forces, gpu_system, near_cutoff_mask
+from gpu_helpers import compare_forces, gpu_system, near_cutoff
 from oracle import Oracle
 from paper_1611_06163_amd import inputs as I
 
@@ -52,8 +52,8 @@ def test_teacher_forced_forces(kernel):
     pos, vel, conc = g.get_state()
     o = Oracle(cfg)
     ref = o.forces(pos, vel, conc, k=k)
-    excl = near_cutoff_mask(o, cfg, pos, vel, ref, k)
-    rep = compare_forces(F, Q, ref, exclude=excl, label=f"shear/k{kernel}")
+    excl, sens = near_cutoff(o, cfg, pos, vel, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"shear/k{kernel}")
     assert rep["badF"] == 0 and rep["badQ"] == 0
     assert rep["excluded"] <= 5 + cfg.n // 20
 
@@ -89,8 +89,8 @@ def test_steps_across_the_sheared_boundary():
         assert np.abs(dx).max() < 2e-5, (n, np.abs(dx).max())
         vh = v.astype(np.float64) - h * F
         ref = o.forces(x, vh, c.astype(np.float64) - h * Q, k=n)
-        excl = near_cutoff_mask(o, cfg, x, vh, ref, n)
-        rep = compare_forces(F, Q, ref, exclude=excl, label=f"shear step {n}")
+        excl, sens = near_cutoff(o, cfg, x, vh, ref, n)
+        rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"shear step {n}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         x0, v0, F0 = x, v, F
     assert crossed > 0
@@ -124,8 +124,8 @@ def test_cell_across_the_sheared_boundary():
     p, v, cc = g.get_state()
     o = Oracle(cfg)
     ref = o.forces(p, v, cc, k=k)
-    excl = near_cutoff_mask(o, cfg, p, v, ref, k)
-    rep = compare_forces(F, Q, ref, exclude=excl, label="cell across the sheared boundary")
+    excl, sens = near_cutoff(o, cfg, p, v, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label="cell across the sheared boundary")
     assert rep["badF"] == 0 and rep["badQ"] == 0
     d = g.diagnostics()
     assert np.allclose(d["av"], ref["av"], rtol=2e-6, atol=0)
@@ -154,6 +154,6 @@ def test_sheared_batch_equals_solo_and_oracle():
         sl = slice(off[b], off[b + 1])
         o = Oracle(cfg)
         ref = o.forces(pos[sl], vel[sl], conc[sl], k=9)
-        excl = near_cutoff_mask(o, cfg, pos[sl], vel[sl], ref, 9)
-        rep = compare_forces(F[sl], Q[sl], ref, exclude=excl, label=f"sheared box {b}")
+        excl, sens = near_cutoff(o, cfg, pos[sl], vel[sl], ref, 9)
+        rep = compare_forces(F[sl], Q[sl], ref, exclude=excl, sens=sens, label=f"sheared box {b}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
