@@ -200,6 +200,22 @@ int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *ij, int64_t
    per species, then per cell (A^t, V^t).  cap = doubles available. */
 int tdpd_diagnostics(tdpd_sys *s, double *out, int64_t cap);
 
+/* The same diagnostics for callers that cannot allocate: code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc.  It makes no
+   allocation of any kind and does not wait: it enqueues on the system's
+   stream, writing the same 4 + S + 2 x cells doubles as tdpd_diagnostics
+   (the same bits) to out_dev, a device buffer owned by the caller, valid once
+   the stream reaches that point.  The workgroup partial sums live in a
+   library-wide device scratch of 1.38 MB per GPU (held until the process
+   ends), which limits the system to at most 8,388,608 particles
+   (TDPD_ERR_CAPACITY beyond).  Needs an evaluated state (tdpd_compute_forces
+   or tdpd_step before; else TDPD_ERR_STATE): it never evaluates forces
+   itself.  Every call on a GPU shares that GPU's scratch, so calls that
+   overlap on one GPU (systems on different streams) race; calls on one
+   stream are ordered.  TDPD_ERR_HIP if the scratch could not be located at
+   tdpd_create. */
+int tdpd_diagnostics_noalloc(tdpd_sys *s, double *out_dev, int64_t cap);
+
 /* Kernel timing with HIP events recorded on the system's stream around each
    phase of a force evaluation.  mask bits: TDPD_PHASE_* (0 disables).
    tdpd_get_timing waits for the stream, returns the summed duration in ms

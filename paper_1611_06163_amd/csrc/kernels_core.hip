@@ -628,11 +628,9 @@ void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int n
 }
 
 // ------------------------------------------------------------- diagnostics
-// Fixed-order FP64 reduction: block b sums its contiguous 1024-particle span
-// through an LDS tree; a second one-block pass sums the block partials.
+// Fixed-order FP64 reduction: block b sums its contiguous kDiagSpan-particle
+// span through an LDS tree; a second one-block pass sums the block partials.
 constexpr int kDiagThreads = 256;
-constexpr int kDiagSpan = 1024;
-constexpr int kDiagFields = 5 + kMaxS;
 
 __global__ void __launch_bounds__(kDiagThreads) k_diag_partial(State s, int64_t n, int nspec,
                                                                double *__restrict__ partial) {
@@ -681,6 +679,27 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double *__res
     if (threadIdx.x == 0) out[f] = red[0];
     __syncthreads();
   }
+}
+
+// The reported values from the reduced sums (momentum, kT over the mobile
+// particles, totals per species), in the same FP64 operations and order as
+// the host finish of tdpd_diagnostics, without contraction, so both give the
+// same bits.
+__global__ void k_diag_finish(const double *__restrict__ sums, int nspec, double *__restrict__ out) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  const double nm = sums[4];
+  out[0] = sums[0];
+  out[1] = sums[1];
+  out[2] = sums[2];
+  out[3] = nm > 1 ? (sums[3] - (sums[0] * sums[0] + sums[1] * sums[1] + sums[2] * sums[2]) / nm) /
+                        (3.0 * (nm - 1))
+                  : 0.0;
+  for (int sp = 0; sp < nspec; ++sp) out[4 + sp] = sums[5 + sp];
+}
+
+void launch_diag_finish(const double *sums, int nspec, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(64), 0, st, sums, nspec, out);
 }
 
 void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hipStream_t st) {

@@ -149,7 +149,14 @@ void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
                       int32_t *out, int64_t cap, unsigned long long *count, hipStream_t st);
 
 // FP64 diagnostics in fixed order: [P0,P1,P2, sum v^2, n_mobile, C_0..C_{S-1}]
+// FP64 diagnostics: partial sums of kDiagSpan particles per workgroup
+// (kDiagFields doubles each) into `partial`, then their fixed-order total
+// into out[5 + nspec] (Σv, Σ|v|^2 and the mobile count, ΣC per species).
+constexpr int kDiagSpan = 1024;
+constexpr int kDiagFields = 5 + kMaxS;
 void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hipStream_t st);
+// out[4 + nspec] = (P[3], kT, ΣC[nspec]) from the totals of launch_diag.
+void launch_diag_finish(const double *sums, int nspec, double *out, hipStream_t st);
 
 // Copy (AoS <-> SoA) in gid order.
 void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, int nspec,

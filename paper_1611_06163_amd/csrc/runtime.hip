@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -101,6 +102,7 @@ struct tdpd_sys {
   unsigned long long *nzero = nullptr, *pair_count = nullptr;
   uint32_t *errw = nullptr;
   double *diag_partial = nullptr, *diag_out = nullptr;
+  int device = -1;  // the HIP device current at creation (the stream's)
 
   std::vector<HostMesh> meshes;
   std::vector<int32_t> rbc_mesh, rbc_box;
@@ -285,6 +287,36 @@ static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
 
 
 
+// ------------------------------------------- allocation-free diagnostics
+// Scratch of tdpd_diagnostics_noalloc: the per-workgroup partial sums of up
+// to kNoAllocDiagBlocks workgroups, then the reduced totals.  One copy per
+// device, alive until the process ends; host code never passes `scratch`
+// itself to a kernel (on the host it only names the symbol), only the device
+// address that hipGetSymbolAddress returned for the device.
+constexpr int64_t kNoAllocMaxParticles = int64_t(1) << 23;
+constexpr int64_t kNoAllocDiagBlocks = kNoAllocMaxParticles / kDiagSpan;
+constexpr int64_t kNoAllocScratchDoubles = kNoAllocDiagBlocks * kDiagFields + 32;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device; records the device in *dev.  TDPD_ERR_HIP if the lookup fails.
+static int scratch_for_current_device(int *dev) {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= kMaxDevices) return TDPD_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[d]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TDPD_ERR_HIP;
+    g_scratch_ptr[d] = static_cast<double *>(ptr);
+  }
+  *dev = d;
+  return TDPD_OK;
+}
+
 static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void *hip_stream,
                          tdpd_alloc_fn alloc, tdpd_free_fn free_fn, void *user, tdpd_sys **out) {
   tdpd_sys *s = new tdpd_sys();
@@ -341,6 +373,12 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
     if (std::sscanf(e, "%d,%d,%d,%d", &t.waves, &t.chunks, &t.split, &t.filter) == 4 &&
         pair_tile_built(t, s->S))
       s->tile = t;
+  }
+  // set-up of the allocation-free diagnostics on this device; a failed
+  // lookup only disables that entry point
+  if (scratch_for_current_device(&s->device) != TDPD_OK) {
+    s->device = -1;
+    (void)hipGetLastError();
   }
   *out = s;
   return TDPD_OK;
@@ -727,8 +765,8 @@ static int prepare(tdpd_sys *s) {
   HIPCHK(hipMemsetAsync(s->kdev, 0, sizeof(uint32_t), s->st));
   HIPCHK(hipMemsetAsync(s->cell_count, 0, sizeof(uint32_t) * s->ncell, s->st));
   s->kdev_val = 0;
-  s->diag_partial = dallocT<double>(s, size_t((n + 1023) / 1024 + 1) * (5 + kMaxS));
-  s->diag_out = dallocT<double>(s, 5 + kMaxS);
+  s->diag_partial = dallocT<double>(s, size_t((n + kDiagSpan - 1) / kDiagSpan + 1) * kDiagFields);
+  s->diag_out = dallocT<double>(s, kDiagFields);
   if (!s->F || !s->Q || !s->keys || !s->vals || !s->keys_tmp || !s->vals_tmp || !s->keys_s ||
       !s->perm || !s->hist || !s->cell_start || !s->slot_of_gid || !s->nzero || !s->errw ||
       !s->diag_partial || !s->diag_out)
@@ -1282,6 +1320,33 @@ extern "C" int tdpd_diagnostics(tdpd_sys *s, double *out, int64_t cap) {
   out[2] = d[2];
   out[3] = nm > 1 ? (d[3] - (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) / nm) / (3.0 * (nm - 1)) : 0.0;
   for (int sp = 0; sp < S; ++sp) out[4 + sp] = d[5 + sp];
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_diagnostics_noalloc(tdpd_sys *s, double *out_dev, int64_t cap) {
+  if (!s || !out_dev) return TDPD_ERR_INVALID_ARG;
+  const int S = s->S;
+  const int nrbc = int(s->rbc_mesh.size());
+  const int64_t need = 4 + S + 2 * int64_t(nrbc);
+  if (cap < need) return s->fail(TDPD_ERR_CAPACITY, "diagnostics_noalloc: buffer too small");
+  if (!s->uploaded || !s->forces_valid)
+    return s->fail(TDPD_ERR_STATE,
+                   "diagnostics_noalloc: no evaluated state (call tdpd_compute_forces or tdpd_step)");
+  if (s->n > kNoAllocMaxParticles)
+    return s->fail(TDPD_ERR_CAPACITY,
+                   "diagnostics_noalloc: more than 8,388,608 particles (the scratch limit)");
+  if (s->device < 0 || !g_scratch_ptr[s->device])
+    return s->fail(TDPD_ERR_HIP, "diagnostics_noalloc: device scratch unavailable");
+  double *partial = g_scratch_ptr[s->device];
+  double *sums = partial + kNoAllocDiagBlocks * kDiagFields;
+  // every partial and total the kernels read is written first in this call,
+  // so nothing is cleared
+  launch_diag(s->cur(), s->n, S, partial, sums, s->st);
+  launch_diag_finish(sums, S, out_dev, s->st);
+  HIPCHK(hipGetLastError());
+  if (nrbc > 0)
+    HIPCHK(hipMemcpyAsync(out_dev + 4 + S, s->d_av, sizeof(double) * 2 * nrbc,
+                          hipMemcpyDeviceToDevice, s->st));
   return TDPD_OK;
 }
 

@@ -99,6 +99,7 @@ def lib():
             "tdpd_get_forces": (C.c_int, [P, P, P]),
             "tdpd_get_pairs": (C.c_int, [P, I32, I64, P, C.POINTER(I64)]),
             "tdpd_diagnostics": (C.c_int, [P, P, I64]),
+            "tdpd_diagnostics_noalloc": (C.c_int, [P, P, I64]),
             "tdpd_set_timing": (C.c_int, [P, I32]),
             "tdpd_get_timing": (C.c_int, [P, I32, C.POINTER(C.c_double), C.POINTER(I64)]),
             "tdpd_autotune": (C.c_int, [P, C.c_char_p, I32, C.POINTER(C.c_double)]),
@@ -316,6 +317,13 @@ class System:
         self._check(lib().tdpd_diagnostics(self.h, _ptr(out), out.size))
         return dict(P=out[:3], kT=out[3], C=out[4:4 + self.S],
                     av=out[4 + self.S:].reshape(nrbc, 2))
+
+    def diagnostics_noalloc(self, out_dev_ptr, cap):
+        """Enqueue the diagnostics into a caller-owned device buffer of `cap`
+        doubles (address as an int) on the library's stream; no allocation,
+        no wait."""
+        self._check(lib().tdpd_diagnostics_noalloc(self.h, C.c_void_p(int(out_dev_ptr)),
+                                                   int(cap)))
 
     def surrogate_sample(self):
         """Inputs X [nv][20], plain bending + local-area targets in the local
