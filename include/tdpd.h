@@ -189,10 +189,19 @@ int tdpd_get_state(tdpd_sys *s, float *pos, float *vel, float *conc);
 /* Last evaluated forces [n][3] and concentration rates [n][n_species]. */
 int tdpd_get_forces(tdpd_sys *s, float *F, float *Q);
 
-/* Unordered pairs {gid_i < gid_j} with 0 < d^2 < fl(rcut^2) at the current
-   positions (which = 0: rcut = rc, 1: rcut = rcc), enumerated by the pair
-   kernel's own cell search.  Writes up to cap pairs to ij [cap][2] in no
-   particular order and the total to *n_out; TDPD_ERR_CAPACITY if n_out > cap. */
+/* The neighbour pairs of the pair terms (Section 3.1: particles binned into
+   cells of edge >= the cutoff, pairs found over the 27 surrounding cells;
+   the distance test is the FP32 rule 0 < d^2 < fl(rcut^2) on the nearest
+   periodic or sheared image) at the current positions.
+   which = 0 (rcut = rc) or 1 (rcut = rcc): unordered pairs {gid_i < gid_j},
+   enumerated by the one-thread-per-particle kernel's cell search (with
+   Verlet lists on: from the lists).
+   which = 2 (rc) or 3 (rcc): ordered pairs (home gid, partner gid) of every
+   mobile home, both orientations, as the default tiled pair kernel's
+   candidate path finds them at the current tile shape (stencil filter,
+   periodic and sheared lifts included); TDPD_ERR_STATE with Verlet lists.
+   Writes up to cap pairs to ij [cap][2] in no particular order and the total
+   to *n_out; TDPD_ERR_CAPACITY if n_out > cap. */
 int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *ij, int64_t *n_out);
 
 /* FP64 diagnostics: out[0..2] total momentum of mobile particles, out[3] kT

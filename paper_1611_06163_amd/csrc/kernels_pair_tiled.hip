@@ -16,6 +16,11 @@
 //     then summed per home particle in ring order.
 // Each wave keeps its own partial sums; they are added in wave order at the
 // end, so the summation order, and the result, does not depend on timing.
+// The EMIT build walks the same candidates (stencil, filter, periodic and
+// sheared lifts, FP32 distance test) but, instead of evaluating terms, lists
+// every (home gid, candidate gid) with 0 < d^2 < the given cutoff, so the
+// production candidate path can be checked pair by pair.
+#include <cstring>
 #include <type_traits>
 
 #include "launch.h"
@@ -147,7 +152,16 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
   wave_sync();
 }
 
-template <int NS, int W, int KC, bool SH>
+// Output of the EMIT build: ordered pairs, a counter, the cutoff test.
+struct PairEmit {
+  int32_t *out;                 // [cap][2] (home gid, candidate gid)
+  int64_t cap;
+  unsigned long long *count;    // pairs found (also beyond cap)
+  uint32_t r2m1;                // bit pattern of fl(rcut^2) less one
+  uint32_t k;                   // step counter of the positions
+};
+
+template <int NS, int W, int KC, bool SH, bool EMIT = false>
 __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
                                                             const BoxDev *__restrict__ boxes,
                                                             State s,
@@ -159,10 +173,10 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
                                                             float *__restrict__ Q,
                                                             unsigned long long *nzero,
                                                             uint32_t *err, MemArgs ma, int nmemb,
-                                                            int vparts) {
+                                                            int vparts, PairEmit em) {
   __shared__ TiledShared<NS, W, SH> sh;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint32_t k = *kdev;  // random-number step counter
+  const uint32_t k = EMIT ? em.k : *kdev;  // random-number step counter
   // the first nmemb workgroups (a multiple of 8) take the per-vertex
   // membrane terms of a share of one cell each (K-Gather and bond forces
   // came from the binning launch), in this workgroup's LDS, beside the pair
@@ -494,6 +508,25 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
           // 0 < d2 < r^2 as one unsigned compare of the bit patterns (d2 is
           // +0 or above; the NaN of an empty lane lies above every cutoff)
           const uint32_t d2m1 = __float_as_uint(d2) - 1u;
+          if constexpr (EMIT) {
+            const bool hit = d2m1 < em.r2m1;
+            const uint64_t hm = ballot(hit);
+            if (hm) {
+              unsigned long long base = 0;
+              if (lane == 0) base = atomicAdd(em.count, (unsigned long long)__popcll(hm));
+              const uint64_t b0 =
+                  (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(base >> 32), 0))) << 32) |
+                  uint32_t(__builtin_amdgcn_readlane(int(uint32_t(base)), 0));
+              if (hit) {
+                const uint64_t q = b0 + lane_rank(hm);
+                if (int64_t(q) < em.cap) {
+                  em.out[2 * q] = int32_t(sh.hgid[i]);
+                  em.out[2 * q + 1] = int32_t(s.gid[cj[kk]]);
+                }
+              }
+            }
+            continue;
+          }
           {  // flux on every lane, with zero weight outside the flux cutoff
             const float wdc = d2m1 < rcc2m1 ? flux_weight(pc, d2) : 0.f;
             const int tt = trow + ct[kk];
@@ -519,7 +552,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
             }
           }
         }
-        if (fick) {
+        if (fick && !EMIT) {
 #pragma unroll
           for (int sp = 0; sp < NS; ++sp) {
             if (NS > 2 && sp >= S) break;
@@ -548,7 +581,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       blocks(std::false_type{});
     }
     __syncthreads();
-    if (tid < nh) {
+    if (tid < nh && !EMIT) {
       const int p = hb + tid;
       float fx = 0.f, fy = 0.f, fz = 0.f;
       const bool frozen = info_frozen(sh.hinfo[tid]);
@@ -581,7 +614,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
     }
     __syncthreads();
   }
-  if (zero && lane == 0) atomicAdd(nzero, (unsigned long long)zero);
+  if (!EMIT && zero && lane == 0) atomicAdd(nzero, (unsigned long long)zero);
 }
 
 template <int NS, int W, int KC>
@@ -596,14 +629,34 @@ static void launch_shape(const PairConst &pc, const BoxDev *boxes, State s,
   const int nmemb = (ma.nrbc * vparts + 7) / 8 * 8;
   const dim3 grid(unsigned(per_xcd * 8 + nmemb)), block(64 * W);
   // the sheared-row variant costs registers: only systems with a sheared box get it
+  const PairEmit none{};
   if (sheared)
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, true>), grid, block, 0, st, pc, boxes, s,
                        cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err, ma,
-                       nmemb, vparts);
+                       nmemb, vparts, none);
   else
     hipLaunchKernelGGL((k_pair_tiled<NS, W, KC, false>), grid, block, 0, st, pc, boxes, s,
                        cell_start, ncell, split, filter, per_xcd, n, kdev, F, Q, nzero, err, ma,
-                       nmemb, vparts);
+                       nmemb, vparts, none);
+}
+
+// The EMIT build of one shape (one species slot: it evaluates no terms).
+template <int W, int KC>
+static void launch_emit_shape(const PairConst &pc, const BoxDev *boxes, State s,
+                              const uint32_t *cell_start, int64_t ncell, int split, int filter,
+                              int64_t n, unsigned long long *nzero, uint32_t *err, bool sheared,
+                              const PairEmit &em, hipStream_t st) {
+  const int64_t per_xcd = (ncell * split + 7) / 8;
+  const dim3 grid(unsigned(per_xcd * 8)), block(64 * W);
+  const MemArgs ma{};
+  if (sheared)
+    hipLaunchKernelGGL((k_pair_tiled<1, W, KC, true, true>), grid, block, 0, st, pc, boxes, s,
+                       cell_start, ncell, split, filter, per_xcd, n, nullptr, nullptr, nullptr,
+                       nzero, err, ma, 0, 0, em);
+  else
+    hipLaunchKernelGGL((k_pair_tiled<1, W, KC, false, true>), grid, block, 0, st, pc, boxes, s,
+                       cell_start, ncell, split, filter, per_xcd, n, nullptr, nullptr, nullptr,
+                       nzero, err, ma, 0, 0, em);
 }
 
 template <int NS>
@@ -657,6 +710,32 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
   if (pc.n_species <= 8)
     return launch_ns<8>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
   return launch_ns<16>(pc, boxes, s, cell_start, ncell, n, kdev, F, Q, nzero, err, tile, sheared, ma, st);
+}
+
+bool launch_pair_tiled_emit(const PairConst &pc, const BoxDev *boxes, State s,
+                            const uint32_t *cell_start, int64_t ncell, int64_t n, uint32_t k,
+                            float rcut2, int32_t *out, int64_t cap, unsigned long long *count,
+                            unsigned long long *nzero, uint32_t *err, const PairTile &t,
+                            bool sheared, hipStream_t st) {
+  if (n <= 0 || ncell <= 0) return true;
+  if (t.split < 1 || t.split > 8 || t.filter < 0 || t.filter > 1) return false;
+  uint32_t r2bits;
+  std::memcpy(&r2bits, &rcut2, sizeof(r2bits));
+  const PairEmit em{out, cap, count, r2bits - 1u, k};
+#define TDPD_EMIT_SHAPE(W, KC)                                                              \
+  if (t.waves == W && t.chunks == KC) {                                                     \
+    launch_emit_shape<W, KC>(pc, boxes, s, cell_start, ncell, t.split, t.filter, n, nzero, err, \
+                             sheared, em, st);                                              \
+    return true;                                                                            \
+  }
+  TDPD_EMIT_SHAPE(4, 2)
+  TDPD_EMIT_SHAPE(4, 1)
+  TDPD_EMIT_SHAPE(4, 3)
+  TDPD_EMIT_SHAPE(2, 2)
+  TDPD_EMIT_SHAPE(2, 3)
+  TDPD_EMIT_SHAPE(2, 4)
+#undef TDPD_EMIT_SHAPE
+  return false;
 }
 
 bool pair_tile_built(const PairTile &t, int n_species) {

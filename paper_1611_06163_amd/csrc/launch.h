@@ -184,6 +184,16 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
                        int64_t n, const uint32_t *kdev, float *F, float *Q,
                        unsigned long long *nzero, uint32_t *err, const PairTile &tile,
                        bool sheared, const MemArgs &ma, hipStream_t st);
+// The tiled kernel's candidate path at tile t, listing ordered pairs (home
+// gid, candidate gid) with 0 < d^2 < rcut2 of every mobile home into out
+// [cap][2] (in no particular order) and their number into *count (cleared by
+// the caller); positions at step counter k (the sheared image offset).
+// False for a tile shape that is not built.
+bool launch_pair_tiled_emit(const PairConst &pc, const BoxDev *boxes, State s,
+                            const uint32_t *cell_start, int64_t ncell, int64_t n, uint32_t k,
+                            float rcut2, int32_t *out, int64_t cap, unsigned long long *count,
+                            unsigned long long *nzero, uint32_t *err, const PairTile &t,
+                            bool sheared, hipStream_t st);
 // Whether a workgroup of the shape has the LDS for one cell of max_nv vertices.
 bool pair_tiled_takes_membrane(const PairTile &t, int n_species, bool sheared, int max_nv);
 

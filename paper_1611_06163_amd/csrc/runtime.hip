@@ -1272,20 +1272,28 @@ extern "C" int tdpd_get_forces(tdpd_sys *s, float *F, float *Q) {
 }
 
 extern "C" int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *ij, int64_t *n_out) {
-  if (!s || !n_out || cap < 0 || (cap > 0 && !ij) || (which != 0 && which != 1)) return TDPD_ERR_INVALID_ARG;
+  if (!s || !n_out || cap < 0 || (cap > 0 && !ij) || which < 0 || which > 3) return TDPD_ERR_INVALID_ARG;
   int rc = ensure_forces(s);
   if (rc) return rc;
+  if (which >= 2 && s->verlet_every > 0)
+    return s->fail(TDPD_ERR_STATE, "get_pairs: ordered pairs of the tiled kernel need cell mode");
   *n_out = 0;
   if (s->n == 0) return TDPD_OK;
   int32_t *dout = dallocT<int32_t>(s, 2 * size_t(cap > 0 ? cap : 1));
   if (!dout) return s->fail(TDPD_ERR_OOM, "device allocation failed");
   HIPCHK(hipMemsetAsync(s->pair_count, 0, sizeof(unsigned long long), s->st));
-  if (s->verlet_every > 0)  // the cells are those of the last rebuild: take the lists
-    launch_list_emit(s->d_boxes, s->cur(), s->n, s->ld, which ? s->pc.rcc2 : s->pc.rc2, dout, cap,
-                     s->pair_count, s->st);
-  else
-    launch_pair_emit(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, s->n,
-                     which ? s->pc.rcc2 : s->pc.rc2, s->kdev_val, dout, cap, s->pair_count, s->st);
+  const float rcut2 = (which & 1) ? s->pc.rcc2 : s->pc.rc2;
+  if (which >= 2) {  // the tiled kernel's own candidate path at the current tile
+    if (!launch_pair_tiled_emit(s->pc, s->d_boxes, s->cur(), s->cell_start, s->ncell, s->n,
+                                s->kdev_val, rcut2, dout, cap, s->pair_count, s->nzero, s->errw,
+                                s->tile, s->any_shear, s->st))
+      return s->fail(TDPD_ERR_INVALID_ARG, "get_pairs: tile shape not built");
+  } else if (s->verlet_every > 0) {  // the cells are those of the last rebuild: take the lists
+    launch_list_emit(s->d_boxes, s->cur(), s->n, s->ld, rcut2, dout, cap, s->pair_count, s->st);
+  } else {
+    launch_pair_emit(s->pc, s->d_boxes, s->cur(), s->keys_s, s->cell_start, s->n, rcut2,
+                     s->kdev_val, dout, cap, s->pair_count, s->st);
+  }
   unsigned long long cnt = 0;
   hipError_t e = hipMemcpyAsync(&cnt, s->pair_count, sizeof(cnt), hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);

@@ -57,6 +57,52 @@ def test_pair_sets_bit_exact(name, which):
     assert np.array_equal(got, _sorted_pairs(ref))
 
 
+# (waves, chunks, workgroups per cell) of every built tile shape
+_SHAPES = [(4, 2, 1), (4, 1, 1), (4, 3, 1), (2, 2, 1), (2, 3, 1), (2, 4, 1), (4, 2, 2), (4, 1, 2),
+           (2, 2, 2), (2, 3, 2), (2, 4, 2), (2, 2, 4), (2, 3, 4), (4, 1, 4), (4, 2, 4)]
+
+
+def _ordered_sorted(p):
+    p = np.asarray(p).reshape(-1, 2)
+    return p[np.lexsort((p[:, 1], p[:, 0]))]
+
+
+@pytest.mark.parametrize("filt", [0, 1])
+@pytest.mark.parametrize("name", ["c1", "tiny", "cluster", "dense", "walls", "sheared"])
+def test_tiled_candidate_path_pair_sets_bit_exact(name, filt):
+    """The default tiled kernel's own candidate path (stencil, filter on and
+    off, periodic and sheared lifts, the FP32 distance test) lists, for every
+    mobile home, exactly the partners of the brute-force (or pinned
+    cell-bucket) pair set, at every built tile shape (Section 3.1)."""
+    k = 0
+    if name == "dense":  # stencils beyond the filter's list: the whole stencil is tested
+        cfg = I.make_fluid(box=(6.0, 6.0, 6.0), n=1000, seed=17)
+    elif name == "walls":  # frozen wall slabs: frozen homes are skipped
+        cfg = I.c3(scale=0.25)
+    elif name == "sheared":
+        cfg = I.make_fluid(box=(8.0, 7.0, 6.5), rho=4.0, seed=3, shear_rate=0.4)
+        k = 37
+    else:
+        cfg = _cases()[name]
+    sysg = gpu_system(cfg, kernel=1)
+    sysg.compute_forces(k)
+    pos, _, _ = sysg.get_state()
+    o = Oracle(cfg)
+    mobile = (cfg.flags & I.FLAG_FROZEN) == 0
+    refs = {}
+    for which in (0, 1):
+        ref, _ = o.pairs(pos, which, brute=cfg.n <= 2000, k=k)
+        both = np.concatenate([ref, ref[:, ::-1]])
+        refs[which] = _ordered_sorted(both[mobile[both[:, 0]]])
+    for (wv, ch, sp) in _SHAPES:
+        sysg.tile = (wv, ch, sp, filt)
+        for which in (0, 1):
+            got = _ordered_sorted(sysg.pairs(2 + which))
+            print(name, (wv, ch, sp, filt), which, len(got), len(refs[which]), flush=True)
+            assert np.array_equal(got, refs[which])
+    sysg.close()
+
+
 @pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("name", ["c1", "cluster", "c1_randflux", "c2", "c3_small", "c3_cells"])
 def test_teacher_forced_forces(kernel, name):
