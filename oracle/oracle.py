@@ -40,6 +40,8 @@ class _Params(C.Structure):
         ("body_force", C.c_double * 3), ("wall_axis", C.c_int32), ("wall_w", C.c_double),
         ("seed_lo", C.c_uint32), ("seed_hi", C.c_uint32), ("box_id", C.c_uint32),
         ("terms", C.c_int32), ("shear_rate", C.c_float),
+        ("source", C.c_double * (MAXS * MAXT)), ("decay", C.c_double * (MAXS * MAXT)),
+        ("wall_radius", C.c_double),
     ]
 
 
@@ -134,6 +136,14 @@ def _params_from(cfg, terms=TERMS_ALL):
     p.box_id = cfg.box_id
     p.terms = terms
     p.shear_rate = float(getattr(cfg, "shear_rate", 0.0))
+    for name in ("source", "decay"):
+        a = getattr(cfg, name, None)
+        if a is not None:
+            a = np.asarray(a, dtype=np.float64).reshape(S, T)
+            for s in range(S):
+                for t in range(T):
+                    getattr(p, name)[s * T + t] = a[s, t]
+    p.wall_radius = float(getattr(cfg, "wall_radius", 0.0))
     return p
 
 

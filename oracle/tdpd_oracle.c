@@ -13,7 +13,8 @@
  *   - force on particle i: Eq. (2), sum over j of Eqs. (3)-(5) with the
  *     fluctuation-dissipation pairing of Eq. (6);
  *   - concentration rate: Eq. (7) with the Fickian and random fluxes of
- *     Eqs. (8)-(9) and the pairing of Eq. (10);
+ *     Eqs. (8)-(9), the pairing of Eq. (10) and the source term Q^S (read as
+ *     a zero-order source less a first-order decay per species and type);
  *   - membrane: WLC and POW bond potentials, Eqs. (13)-(14), bond viscosity
  *     and its random partner, Eqs. (15)-(16), area and volume constraints,
  *     Eqs. (17)-(18), bending, Eq. (19);
@@ -85,6 +86,10 @@ typedef struct {
   uint32_t seed_lo, seed_hi, box_id;
   int32_t terms;
   float shear_rate; /* Lees-Edwards shear rate (0: plain periodic box) */
+  /* source term of Eq. (7): Q^S_i = source[s*T + t_i] - decay[s*T + t_i] C_i */
+  double source[ORC_MAXS * ORC_MAXT];
+  double decay[ORC_MAXS * ORC_MAXT];
+  double wall_radius; /* wall_axis 3: cylinder about the x-parallel axis */
 } orc_params;
 
 typedef struct {
@@ -936,6 +941,16 @@ int orc_forces(const orc_sys *s, int64_t n64, const double *pos, const double *v
           }
         }
       }
+      /* Q^S of Eq. (7), the external contribution the paper leaves open
+         (reading: a zero-order source and a first-order decay of the
+         particle's own concentration, per species and particle type) */
+      for (int sp = 0; sp < S; ++sp) {
+        const double a = p->source[sp * T + ti], kd = p->decay[sp * T + ti];
+        if (a == 0 && kd == 0) continue;
+        const double ci = conc[(size_t)S * i + sp];
+        Qi[sp] += a - kd * ci;
+        if (Qabs) Qabs[(size_t)S * i + sp] += fabs(a) + fabs(kd * ci);
+      }
       if (terms & T_BODY) {
         for (int a = 0; a < 3; ++a) Fi[a] += p->body_force[a];
         if (Fabs) Fabs[i] += sqrt(p->body_force[0] * p->body_force[0] +
@@ -1002,7 +1017,21 @@ int orc_step(const orc_sys *s, int64_t n64, double *pos, double *vel, double *co
     for (int a = 0; a < 3; ++a) vel[3 * i + a] += h * F[3 * i + a];
     for (int sp = 0; sp < S; ++sp) conc[(size_t)S * i + sp] += h * Q[(size_t)S * i + sp];
     for (int a = 0; a < 3; ++a) pos[3 * i + a] += p->dt * vel[3 * i + a];
-    if (p->wall_axis >= 0) {
+    if (p->wall_axis == 3) {
+      /* cylindrical wall (reading of the tube of the paper's transport
+         validation): a mobile particle that ends the drift farther than R
+         from the axis (y, z) = (L_y/2, L_z/2) is mirrored through the
+         cylinder along its radius, r -> 2R - r, and its velocity reversed */
+      const double cy = 0.5 * p->box[1], cz = 0.5 * p->box[2], R = p->wall_radius;
+      double *x = pos + 3 * i;
+      const double dy = x[1] - cy, dz = x[2] - cz, r = sqrt(dy * dy + dz * dz);
+      if (r > R) {
+        const double f = (2 * R - r) / r;
+        x[1] = cy + dy * f;
+        x[2] = cz + dz * f;
+        for (int q = 0; q < 3; ++q) vel[3 * i + q] = -vel[3 * i + q];
+      }
+    } else if (p->wall_axis >= 0) {
       const int a = p->wall_axis;
       const double L = p->box[a], w = p->wall_w;
       double *x = pos + 3 * i + a;

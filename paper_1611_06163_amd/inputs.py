@@ -63,8 +63,11 @@ class Config:
     sigma: np.ndarray = None   # [T,T]
     kappa: np.ndarray = None   # [S,T,T]
     body_force: tuple = (0.0, 0.0, 0.0)
-    wall_axis: int = -1
+    wall_axis: int = -1        # 0-2: planar walls across that axis; 3: cylinder along x
     wall_w: float = 0.0
+    wall_radius: float = 0.0   # cylinder radius (wall_axis 3)
+    source: np.ndarray = None  # [S,T] zero-order source rate of Q^S (None: 0)
+    decay: np.ndarray = None   # [S,T] first-order decay rate of Q^S (None: 0)
     shear_rate: float = 0.0
     seed: int = 1
     box_id: int = 0
@@ -384,6 +387,43 @@ def c5(seed=5, n_cells=1000):
     96x96x72 at density 3 plus 1000 cells."""
     return _suspension("large_suspension", (96.0, 96.0, 72.0), 3.0, n_cells, seed,
                        steps=100)
+
+
+def cylinder(radius=20.0, length=80.0, rho=4.0, seed=9, wall=2.0, c0=0.0, c_wall=1.0,
+             kappa=5.0, moving=True, steps=10000):
+    """Diffusion in a long tube with a Dirichlet wall (the paper's transport
+    validation, Section 4: radius 20, length 80, density 4, alpha 18.75,
+    gamma 4.5, r_c = r_cc = 1.58, s = 0.41, flux exponent 2, kappa 5).
+    Uniform positions at density rho fill a box of length `length` and width
+    2 (radius + wall); particles farther than `radius` from the x-parallel
+    axis through the box centre are frozen wall particles that hold the wall
+    concentration c_wall (and exchange flux with the fluid: kappa to the wall
+    as to the fluid), the fluid starts at c0.  moving=False gives the fluid
+    zero velocities (run with the force terms off, the particles then stay
+    in place: the pure-diffusion case)."""
+    rng = np.random.default_rng(seed)
+    w = 2.0 * (radius + wall)
+    box = (float(length), w, w)
+    n = int(round(rho * float(np.prod(box))))
+    pos = uniform_positions(n, box, rng)
+    dy = pos[:, 1].astype(np.float64) - 0.5 * w
+    dz = pos[:, 2].astype(np.float64) - 0.5 * w
+    outside = dy * dy + dz * dz > radius * radius
+    flags = np.full(n, T_SOLVENT, dtype=np.uint32)
+    flags[outside] = T_WALL | FLAG_FROZEN
+    mobile = ~outside
+    vel = maxwell_velocities(n, 1.0, rng, mobile)
+    if not moving:
+        vel[:] = 0.0
+    conc = np.full((n, 1), c0, dtype=np.float32)
+    conc[outside, 0] = c_wall
+    alpha, gamma, sigma, kap = pair_tables(3, 1, a=18.75, g=4.5, s=3.0, kappa=kappa)
+    cfg = Config(name="cylinder", box=box, rc=1.58, rcc=1.58, rho=rho, s_exp=0.41,
+                 sc_exp=2.0, n_species=1, alpha=alpha, gamma=gamma, sigma=sigma,
+                 kappa=kap, wall_axis=3, wall_radius=float(radius), seed=seed,
+                 steps=steps)
+    cfg.pos, cfg.vel, cfg.conc, cfg.flags = pos, vel, conc, flags
+    return cfg
 
 
 def ensemble_sizes(n_boxes=256, lo=2000, hi=60000, seed=4):
