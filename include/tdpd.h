@@ -90,8 +90,10 @@ typedef struct {
   float sigma[TDPD_MAX_TYPES * TDPD_MAX_TYPES];
   float kappa[TDPD_MAX_SPECIES * TDPD_MAX_TYPES * TDPD_MAX_TYPES]; /* [(s*T+ti)*T+tj] */
   float body_force[3];
-  int32_t wall_axis; /* -1: none; else mobile particles crossing wall_w or
-                        L - wall_w on that axis are reflected */
+  int32_t wall_axis; /* -1: none; 0-2: mobile particles crossing wall_w or
+                        L - wall_w on that axis are reflected; 3: a tube about
+                        the x-parallel axis through (L_y/2, L_z/2), see
+                        wall_radius */
   float wall_w;
   uint64_t seed;     /* Philox key */
   uint32_t box_id;   /* part of the Philox counter, < 2^24 */
@@ -102,6 +104,22 @@ typedef struct {
                         in x at step counter k and moves with
                         u = fl32(gamma L_y) in x (FP64 products of the FP32
                         values); not with walls (TDPD_ERR_UNSUPPORTED) */
+  /* Source term Q^S of Eq. (7), the external contribution the paper leaves
+     open, read as a zero-order source less a first-order decay of the
+     particle's own concentration per species s and particle type t:
+     Q^S_i = source[s*n_types + t_i] - decay[s*n_types + t_i] * C_i^s, added
+     to the fluxes of mobile particles where they are evaluated (at the
+     half-step concentrations).  Zero switches it off; values must be finite. */
+  float source[TDPD_MAX_SPECIES * TDPD_MAX_TYPES];
+  float decay[TDPD_MAX_SPECIES * TDPD_MAX_TYPES];
+  /* Tube radius R for wall_axis = 3 (the Dirichlet cylinder of the paper's
+     transport validation, Section 4): a mobile particle that ends a drift
+     farther than R from the axis is mirrored along its radius to 2R - r and
+     its velocity reversed.  The wall itself is made of frozen particles of
+     the input (outside R), which hold their concentration: with kappa to
+     the fluid above zero they are a Dirichlet reservoir.  Needs
+     0 < R < min(L_y, L_z) / 2. */
+  float wall_radius;
 } tdpd_params;
 
 typedef struct {

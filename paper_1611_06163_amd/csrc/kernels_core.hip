@@ -203,7 +203,22 @@ __device__ __forceinline__ void kick_drift(const PairConst &pc, const BoxDev &B,
   x += pc.dt * vx;
   y += pc.dt * vy;
   z += pc.dt * vz;
-  if (pc.wall_axis >= 0) {
+  if (pc.wall_axis == 3) {
+    // the tube: a particle farther than R from the axis is mirrored along
+    // its radius to 2R - r, its velocity reversed
+    const float cy = 0.5f * B.L[1], cz = 0.5f * B.L[2], R = pc.wall_radius;
+    const float dy = y - cy, dz = z - cz;
+    const float r2 = __fmaf_rn(dz, dz, dy * dy);
+    if (r2 > R * R) {
+      const float r = __builtin_amdgcn_sqrtf(r2);
+      const float f = (2.f * R - r) / r;
+      y = __fmaf_rn(dy, f, cy);
+      z = __fmaf_rn(dz, f, cz);
+      vx = -vx;
+      vy = -vy;
+      vz = -vz;
+    }
+  } else if (pc.wall_axis >= 0) {
     float *c = pc.wall_axis == 0 ? &x : (pc.wall_axis == 1 ? &y : &z);
     const float L = B.L[pc.wall_axis], w = pc.wall_w;
     bool hit = false;

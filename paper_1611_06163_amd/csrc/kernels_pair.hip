@@ -185,6 +185,8 @@ __global__ void __launch_bounds__(256) k_pair_simple(PairConst pc,
                 info_type(infoj), bi >= 0 && bi == bj, gi, s.gid[j] - B.gid_base, k, acc);
     });
     if (zero) atomicAdd(nzero, (unsigned long long)zero);
+    if (pc.has_source)
+      for (int sp = 0; sp < S; ++sp) acc.q[sp] += source_term(pc, sp, ti, ci[sp]);
     if (pc.terms & TDPD_TERM_BODY_FORCE) {
       acc.fx += pc.body_force[0];
       acc.fy += pc.body_force[1];

@@ -182,6 +182,10 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
   }
   if (lane != 0) return;
   if (mobile) {
+    if (pc.has_source)
+#pragma unroll
+      for (int sp = 0; sp < NS; ++sp)
+        if (sp < S) q[sp] += source_term(pc, sp, info_type(infoi), s.C[sp * n + i]);
     if (pc.terms & TDPD_TERM_BODY_FORCE) {
       fx += pc.body_force[0];
       fy += pc.body_force[1];

@@ -545,10 +545,11 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
               sh.ring[w][e] = make_float4(dx, dy, dz, __uint_as_float(hbits | cj[kk]));
               if constexpr (LE) sh.rl[w][e] = uint8_t((lift[kk] >> 3) & 3u);
             }
-            tail = uniform(tail + uint32_t(__popcll(fm)));
-            if (tail - head >= 64) {
+            // (cursors re-read as scalars, so their arithmetic stays scalar)
+            tail = uniform(tail) + uint32_t(__popcll(fm));
+            if (tail - uniform(head) >= 64u) {
               flush_ring<NS, W, LE>(pc, B, s, sh, w, head, 64, k, le.u);
-              head = uniform(head + 64u);
+              head = uniform(head) + 64u;
             }
           }
         }
@@ -606,9 +607,11 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       for (int sp = 0; sp < NS; ++sp) {
         if (sp >= S) break;
         float q = 0.f;
-        if (!frozen)
+        if (!frozen) {
 #pragma unroll
           for (int v = 0; v < W; ++v) q += sh.qa[v][sp][tid];
+          if (pc.has_source) q += source_term(pc, sp, info_type(sh.hinfo[tid]), sh.hc[sp][tid]);
+        }
         Q[S * p + sp] = q;
       }
     }

@@ -244,8 +244,10 @@ static int check_common(const tdpd_params *p) {
   if (!(p->rc > 0.f) || !(p->rcc > 0.f) || !(p->dt > 0.f) || !(p->kT >= 0.f) ||
       !(p->s_exp >= 0.f) || !(p->sc_exp >= 0.f) || !(p->m_s >= 0.f) || !(p->rho >= 0.f))
     return TDPD_ERR_INVALID_ARG;
-  if (p->wall_axis < -1 || p->wall_axis > 2) return TDPD_ERR_INVALID_ARG;
+  if (p->wall_axis < -1 || p->wall_axis > 3) return TDPD_ERR_INVALID_ARG;
   const int T = p->n_types;
+  for (int e = 0; e < p->n_species * T; ++e)
+    if (!std::isfinite(p->source[e]) || !std::isfinite(p->decay[e])) return TDPD_ERR_INVALID_ARG;
   for (int i = 0; i < T; ++i)
     for (int j = 0; j < T; ++j) {
       const float g = p->gamma[i * T + j], sg = p->sigma[i * T + j];
@@ -276,7 +278,11 @@ static int make_box(const tdpd_params *p, const tdpd_box &in, HostBox &b) {
     b.nc[a] = int(std::floor(double(in.box[a]) / (double(rmax) * (1.0 + 1e-4))));
     if (b.nc[a] < 3) return TDPD_ERR_BOX_TOO_SMALL;
   }
-  if (p->wall_axis >= 0 && !(p->wall_w > 0.f && 2.f * p->wall_w < in.box[p->wall_axis]))
+  if (p->wall_axis >= 0 && p->wall_axis <= 2 &&
+      !(p->wall_w > 0.f && 2.f * p->wall_w < in.box[p->wall_axis]))
+    return TDPD_ERR_INVALID_ARG;
+  if (p->wall_axis == 3 &&
+      !(p->wall_radius > 0.f && 2.f * p->wall_radius < std::min(in.box[1], in.box[2])))
     return TDPD_ERR_INVALID_ARG;
   b.ncell = int64_t(b.nc[0]) * b.nc[1] * b.nc[2];
   b.seed = in.seed;
@@ -359,6 +365,14 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
   std::memcpy(pc.kappa, p->kappa, sizeof(pc.kappa));
   pc.wall_axis = p->wall_axis;
   pc.wall_w = p->wall_w;
+  pc.wall_radius = p->wall_radius;
+  pc.has_source = 0;
+  for (int e = 0; e < kMaxS * kMaxT; ++e) {
+    const bool used = e < p->n_species * p->n_types;
+    pc.source[e] = used ? p->source[e] : 0.f;
+    pc.decay[e] = used ? p->decay[e] : 0.f;
+    if (pc.source[e] != 0.f || pc.decay[e] != 0.f) pc.has_source = 1;
+  }
   pc.terms = p->terms;
   pc.n_boxes = int(s->boxes.size());
   s->mc.kT = p->kT;
@@ -1421,6 +1435,7 @@ uint64_t fingerprint(const tdpd_sys *s) {
   f.bytes(p.alpha, sizeof(p.alpha)); f.bytes(p.gamma, sizeof(p.gamma));
   f.bytes(p.sigma, sizeof(p.sigma)); f.bytes(p.kappa, sizeof(p.kappa));
   f.bytes(p.body_force, sizeof(p.body_force)); f.val(p.wall_axis); f.val(p.wall_w);
+  f.bytes(p.source, sizeof(p.source)); f.bytes(p.decay, sizeof(p.decay)); f.val(p.wall_radius);
   f.val(p.terms);
   f.val(s->n); f.val(s->S); f.val(uint64_t(s->boxes.size()));
   f.val(s->verlet_every); f.val(s->verlet_skin); f.val(s->ld.cap);

@@ -59,6 +59,10 @@ struct PairConst {
   float wall_w;
   int terms;
   int n_boxes;
+  // source term Q^S of Eq. (7): source - decay * C per [species * n_types + type]
+  int has_source;
+  float source[kMaxS * kMaxT], decay[kMaxS * kMaxT];
+  float wall_radius;  // wall_axis 3: tube radius about (L_y/2, L_z/2)
 };
 
 // State planes of one particle ordering.
@@ -138,6 +142,13 @@ __device__ __forceinline__ float disp(float xj, float s, float xi) {
 }
 __device__ __forceinline__ float dist2(float dx, float dy, float dz) {
   return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
+}
+
+// Q^S of Eq. (7) for a mobile particle of type t holding concentration c of
+// species sp: the zero-order source less the first-order decay.
+__device__ __forceinline__ float source_term(const PairConst &pc, int sp, int t, float c) {
+  const int e = sp * pc.n_types + t;
+  return __fmaf_rn(-pc.decay[e], c, pc.source[e]);
 }
 
 // w^e for w in [0,1]; zero at w <= 0

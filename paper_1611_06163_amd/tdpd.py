@@ -47,6 +47,9 @@ class tdpd_params(C.Structure):
         ("body_force", C.c_float * 3), ("wall_axis", C.c_int32), ("wall_w", C.c_float),
         ("seed", C.c_uint64), ("box_id", C.c_uint32), ("terms", C.c_int32),
         ("shear_rate", C.c_float),
+        ("source", C.c_float * (MAX_SPECIES * MAX_TYPES)),
+        ("decay", C.c_float * (MAX_SPECIES * MAX_TYPES)),
+        ("wall_radius", C.c_float),
     ]
 
 
@@ -164,6 +167,14 @@ def params_from_config(cfg, terms=TERMS_ALL):
     p.wall_axis, p.wall_w = cfg.wall_axis, cfg.wall_w
     p.seed, p.box_id, p.terms = cfg.seed, cfg.box_id, terms
     p.shear_rate = float(getattr(cfg, "shear_rate", 0.0))
+    for name in ("source", "decay"):
+        a = getattr(cfg, name, None)
+        if a is not None:
+            a = np.asarray(a, dtype=np.float64).reshape(S, T)
+            for s in range(S):
+                for t in range(T):
+                    getattr(p, name)[s * T + t] = a[s, t]
+    p.wall_radius = float(getattr(cfg, "wall_radius", 0.0))
     return p
 
 
