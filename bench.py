@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--no-species", action="store_true", help="skip the ten-species leg")
     ap.add_argument("--no-randflux", action="store_true", help="skip the random-flux leg")
+    ap.add_argument("--no-tube", action="store_true",
+                    help="skip the Dirichlet-tube leg (source term and cylindrical wall)")
     ap.add_argument("--no-verlet", action="store_true", help="skip the neighbour-list leg")
     ap.add_argument("--verlet", default="0.6,5", metavar="SKIN,EVERY",
                     help="skin and rebuild interval of the neighbour-list leg")
@@ -331,7 +333,7 @@ def main():
         sys.exit(2)
     if args.no_legs:
         args.no_single = args.no_batched = args.no_surrogate = args.no_species = True
-        args.no_randflux = args.no_verlet = True
+        args.no_randflux = args.no_verlet = args.no_tube = True
     import numpy as np
     import torch
     from paper_1611_06163_amd import tdpd
@@ -447,6 +449,16 @@ def main():
                                         "(m_s = 0.05)", steps=200, warmup=20, windows=5)
         rf["vs_without"] = rf["value"] / single["value"]
         out["random_flux"] = rf
+    if not args.no_tube:
+        from paper_1611_06163_amd import inputs as I
+        ct = I.cylinder(radius=20.0, length=80.0, rho=4.0, seed=23, moving=True)
+        ct.source = np.zeros((1, ct.n_types))
+        ct.decay = np.zeros((1, ct.n_types))
+        ct.decay[0, I.T_SOLVENT] = 0.05  # a first-order reaction in the fluid (Q^S)
+        tl = plain_leg(torch, tdpd, ct, "tube of radius 20, length 80, density 4 with a "
+                                        "Dirichlet wall of held particles and a first-order "
+                                        "reaction (Eqs. 7, 20)", steps=100, warmup=10, windows=3)
+        out["tube"] = tl
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(torch, tdpd, steps=100, warmup=10, cfg=cfg, desc=desc)
     if not args.no_cpu_baseline:

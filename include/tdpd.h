@@ -356,8 +356,14 @@ int64_t tdpd_mlp_num_params(void);
    TDPD_ERR_INVALID_ARG for a non-finite value. */
 int tdpd_mlp_set_params(tdpd_mlp *m, const float *params);
 int tdpd_mlp_get_params(tdpd_mlp *m, float *params);
-/* Y [n][3] = network(X [n][20]); host buffers. */
+/* Y [n][3] = network(X [n][20]); host buffers.  One fused kernel: weights
+   resident in LDS as bfloat16, activations kept on chip, gfx950's
+   16x16x32 bfloat16 matrix cores. */
 int tdpd_mlp_forward(tdpd_mlp *m, const float *X, int64_t n, float *Y);
+/* Parity/debug: the same forward pass, also returning the three hidden
+   layers' FP32 activations before their bfloat16 rounding, H [3][n][128]
+   (host buffer, caller-owned). */
+int tdpd_mlp_forward_hidden(tdpd_mlp *m, const float *X, int64_t n, float *Y, float *H);
 /* Mean over rows and outputs of (y - T/target_scale)^2 and its gradient
    with respect to the parameters (TDPD_MLP_PARAMS floats, may be NULL). */
 int tdpd_mlp_loss_grad(tdpd_mlp *m, const float *X, const float *T, int64_t n,

@@ -29,7 +29,18 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return uint16_t(b >> 16);
 }
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.f + __expf(-z)); }
+// SiLU z sigma(z) with the hardware exponential and reciprocal (a few ulps,
+// far inside the bfloat16 rounding that follows)
+__device__ __forceinline__ float silu_f(float z) {
+  return z * __builtin_amdgcn_rcpf(1.f + __expf(-z));
+}
+
+// order this wavefront's LDS writes before its later LDS reads (other lanes)
+__device__ __forceinline__ void wave_barrier_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __device__ __forceinline__ float silu_grad_f(float z) {
   const float sg = 1.f / (1.f + __expf(-z));
   return sg * (1.f + z * (1.f - sg));
@@ -199,7 +210,8 @@ __global__ void __launch_bounds__(256) k_surr_features(SurrDev sd, const BoxDev 
                                                        const uint32_t *__restrict__ slot_of_gid,
                                                        const double *__restrict__ av,
                                                        int64_t nvert,
-                                                       const uint32_t *__restrict__ kdev, float dt) {
+                                                       const uint32_t *__restrict__ kdev, int kofs,
+                                                       float dt) {
   const int64_t vg = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (vg >= nvert) return;
   const int r = sd.vcell[vg];
@@ -214,7 +226,7 @@ __global__ void __launch_bounds__(256) k_surr_features(SurrDev sd, const BoxDev 
   const float3 pv = pos(v);
   const int r0 = M.ring_off[v], deg = M.ring_off[v + 1] - r0;
   float3 u[kRingMax];
-  const LeOff le = le_offsets(B, *kdev, dt);
+  const LeOff le = le_offsets(B, *kdev + uint32_t(kofs), dt);
   for (int kk = 0; kk < deg && kk < kRingMax; ++kk) u[kk] = le_rel(B, pos(M.ring[r0 + kk]), pv, le.delta, nullptr);
   const int dg = deg < kRingMax ? deg : kRingMax;
   float3 nn = make_float3(0.f, 0.f, 0.f);
@@ -258,10 +270,10 @@ __global__ void __launch_bounds__(256) k_surr_features(SurrDev sd, const BoxDev 
 
 void launch_surr_features(const SurrDev &sd, const BoxDev *boxes, const MeshDev *meshes, State s,
                           const uint32_t *slot_of_gid, const double *av, int64_t nvert,
-                          const uint32_t *kdev, float dt, hipStream_t st) {
+                          const uint32_t *kdev, float dt, int kofs, hipStream_t st) {
   if (nvert <= 0) return;
   hipLaunchKernelGGL(k_surr_features, dim3(unsigned((nvert + 255) / 256)), dim3(256), 0, st, sd,
-                     boxes, meshes, s, slot_of_gid, av, nvert, kdev, dt);
+                     boxes, meshes, s, slot_of_gid, av, nvert, kdev, kofs, dt);
 }
 
 // Fs = s_F R^T y (global frame) for every vertex
@@ -374,8 +386,178 @@ void launch_sum_parts(const double *part, int64_t n, double *out, hipStream_t st
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, part, n, out);
 }
 
-void mlp_forward(const float *params, const float *X, int64_t n, float *Ha, float *Hb, float *Y,
-                 hipStream_t st) {
+// ------------------------------------------------- fused forward pass
+// The whole network in one kernel: a workgroup keeps the four weight
+// matrices in LDS as bfloat16 (loaded once) and walks tiles of 128 rows; each
+// wavefront owns 16 rows, so its activations never leave its own rows of the
+// LDS tile (no barrier between layers).  Layers run on gfx950's
+// v_mfma_f32_16x16x32_bf16 (16 x 32 A block, 32 x 16 B block, FP32
+// accumulation): lane l holds A[l % 16][8 (l / 16) + 0..7] and
+// B[8 (l / 16) + 0..7][l % 16], and receives D[4 (l / 16) + 0..3][l % 16].
+// The rounding points are those of the layer-by-layer path: inputs, weights
+// and hidden activations to bfloat16 where they enter a product, bias and
+// SiLU in FP32.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kFusedRows = 128;                 // rows per tile (8 wavefronts x 16)
+constexpr int kFusedThreads = 512;
+constexpr int kK1 = 32;                         // first layer's K (20 inputs, padded)
+constexpr int kS1 = kK1 + 8;                    // LDS row strides in bfloat16 (16-byte
+constexpr int kSH = kSurrHid + 8;               // aligned, offset against bank conflicts)
+constexpr int kN4 = 16;                         // last layer's N (3 outputs, padded)
+
+struct FusedShared {
+  uint16_t w1[kSurrHid][kS1];
+  uint16_t w2[kSurrHid][kSH];
+  uint16_t w3[kSurrHid][kSH];
+  uint16_t w4[kN4][kSH];
+  float b1[kSurrHid], b2[kSurrHid], b3[kSurrHid], b4[kN4];
+  uint16_t act[kFusedRows][kSH];
+};
+
+__device__ __forceinline__ v8bf lds_v8(const uint16_t *p) {
+  return __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4 *>(p));
+}
+
+// acc[c] += A (16 rows of this wave, K columns of act) x W^T (column tiles c)
+template <int K, int NT, int SA, int SW>
+__device__ __forceinline__ void fused_layer(const uint16_t (*act)[kSH], const uint16_t *w, int r0,
+                                            int lane, v4f (&acc)[NT]) {
+  const int rr = lane & 15, kq = 8 * (lane >> 4);
+#pragma unroll
+  for (int c = 0; c < NT; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const v8bf a = lds_v8(&act[r0 + rr][k0 + kq]);
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      const v8bf b = lds_v8(w + (16 * c + rr) * SW + k0 + kq);
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+    }
+  }
+}
+
+// bias + SiLU of a hidden layer, rounded to bfloat16 into the wave's rows;
+// with hdbg the FP32 activations (before that rounding) also go to
+// hdbg[row][128] (rows past n are not written)
+__device__ __forceinline__ void fused_store_hidden(uint16_t (*act)[kSH], const float *bias,
+                                                   int r0, int lane, const v4f (&acc)[8],
+                                                   float *hdbg, int64_t row0, int64_t n) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int col = 16 * c + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * (lane >> 4) + q;
+      const float h = silu_f(acc[c][q] + bias[col]);
+      act[r0 + r][col] = to_bf16(h);
+      if (hdbg && row0 + r < n) hdbg[(row0 + r) * kSurrHid + col] = h;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kFusedThreads) k_mlp_fused(const float *__restrict__ params,
+                                                             const float *__restrict__ X, int64_t n,
+                                                             float *__restrict__ Y,
+                                                             float *__restrict__ hdbg) {
+  __shared__ __align__(16) FusedShared sh;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const MlpLayout L;
+  // weights and biases, once per workgroup (padding zero)
+  for (int e = tid; e < kSurrHid * kS1; e += kFusedThreads) {
+    const int o = e / kS1, k = e % kS1;
+    sh.w1[o][k] = k < kSurrIn ? to_bf16(params[L.W1 + o * kSurrIn + k]) : uint16_t(0);
+  }
+  // (four consecutive weights per thread: one 16-byte load, one 8-byte store)
+  for (int e = tid; e < kSurrHid * (kSH / 4); e += kFusedThreads) {
+    const int o = e / (kSH / 4), k = 4 * (e % (kSH / 4));
+    uint2 v2 = make_uint2(0u, 0u), v3 = make_uint2(0u, 0u);
+    if (k < kSurrHid) {
+      const float4 a = *reinterpret_cast<const float4 *>(params + L.W2 + o * kSurrHid + k);
+      const float4 b = *reinterpret_cast<const float4 *>(params + L.W3 + o * kSurrHid + k);
+      v2 = make_uint2(uint32_t(to_bf16(a.x)) | (uint32_t(to_bf16(a.y)) << 16),
+                      uint32_t(to_bf16(a.z)) | (uint32_t(to_bf16(a.w)) << 16));
+      v3 = make_uint2(uint32_t(to_bf16(b.x)) | (uint32_t(to_bf16(b.y)) << 16),
+                      uint32_t(to_bf16(b.z)) | (uint32_t(to_bf16(b.w)) << 16));
+    }
+    *reinterpret_cast<uint2 *>(&sh.w2[o][k]) = v2;
+    *reinterpret_cast<uint2 *>(&sh.w3[o][k]) = v3;
+  }
+  for (int e = tid; e < kN4 * kSH; e += kFusedThreads) {
+    const int o = e / kSH, k = e % kSH;
+    sh.w4[o][k] = (o < kSurrOut && k < kSurrHid) ? to_bf16(params[L.W4 + o * kSurrHid + k]) : uint16_t(0);
+  }
+  for (int e = tid; e < kSurrHid; e += kFusedThreads) {
+    sh.b1[e] = params[L.b1 + e];
+    sh.b2[e] = params[L.b2 + e];
+    sh.b3[e] = params[L.b3 + e];
+  }
+  if (tid < kN4) sh.b4[tid] = tid < kSurrOut ? params[L.b4 + tid] : 0.f;
+  __syncthreads();
+  const int r0 = 16 * w;  // this wave's rows of the tile
+  const int64_t ntiles = (n + kFusedRows - 1) / kFusedRows;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * kFusedRows + r0;
+    // inputs of the wave's 16 rows, bfloat16, K padded to 32 (all loads
+    // issued before the first is used)
+    float xv[16 * kK1 / 64];
+#pragma unroll
+    for (int u = 0; u < 16 * kK1 / 64; ++u) {
+      const int e = lane + 64 * u, r = e / kK1, k = e % kK1;
+      const int64_t i = row0 + r;
+      xv[u] = (k < kSurrIn && i < n) ? X[i * kSurrIn + k] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 16 * kK1 / 64; ++u) {
+      const int e = lane + 64 * u;
+      sh.act[r0 + e / kK1][e % kK1] = to_bf16(xv[u]);
+    }
+    wave_barrier_lds();
+    v4f acc[8];
+    fused_layer<kK1, 8, kSH, kS1>(sh.act, &sh.w1[0][0], r0, lane, acc);
+    wave_barrier_lds();
+    fused_store_hidden(sh.act, sh.b1, r0, lane, acc, hdbg ? hdbg + 0 * n * kSurrHid : nullptr,
+                       row0, n);
+    wave_barrier_lds();
+    fused_layer<kSurrHid, 8, kSH, kSH>(sh.act, &sh.w2[0][0], r0, lane, acc);
+    wave_barrier_lds();
+    fused_store_hidden(sh.act, sh.b2, r0, lane, acc, hdbg ? hdbg + 1 * n * kSurrHid : nullptr,
+                       row0, n);
+    wave_barrier_lds();
+    fused_layer<kSurrHid, 8, kSH, kSH>(sh.act, &sh.w3[0][0], r0, lane, acc);
+    wave_barrier_lds();
+    fused_store_hidden(sh.act, sh.b3, r0, lane, acc, hdbg ? hdbg + 2 * n * kSurrHid : nullptr,
+                       row0, n);
+    wave_barrier_lds();
+    v4f o[1];
+    fused_layer<kSurrHid, 1, kSH, kSH>(sh.act, &sh.w4[0][0], r0, lane, o);
+    const int col = lane & 15;
+    if (col < kSurrOut) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t i = row0 + 4 * (lane >> 4) + q;
+        if (i < n) Y[i * kSurrOut + col] = o[0][q] + sh.b4[col];
+      }
+    }
+    wave_barrier_lds();  // the next tile's inputs overwrite these rows
+  }
+}
+
+void mlp_forward(const float *params, const float *X, int64_t n, float *Y, hipStream_t st,
+                 float *hdbg) {
+  if (n <= 0) return;
+  const int64_t ntiles = (n + kFusedRows - 1) / kFusedRows;
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const unsigned grid = unsigned(ntiles < ncu ? ntiles : ncu);
+  hipLaunchKernelGGL(k_mlp_fused, dim3(grid), dim3(kFusedThreads), 0, st, params, X, n, Y, hdbg);
+}
+
+// The same network layer by layer (four matrix-product launches with the
+// hidden activations in HBM), used by training.
+void mlp_forward_layers(const float *params, const float *X, int64_t n, float *Ha, float *Hb,
+                        float *Y, hipStream_t st) {
   const MlpLayout L;
   GemmArgs g{};
   g.A = X; g.sa_i = kSurrIn; g.sa_p = 1;

@@ -236,11 +236,17 @@ void launch_colsum(const float *D, int64_t m, int ld, int ncol, float *out, hipS
 void launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                  float b2, float eps, float bc1, float bc2, hipStream_t st);
 
-// Network forward pass on n rows of X [n][20] into Y [n][3] with two
-// scratch activations Ha, Hb [n][128]; params in the flat layout
-// [W1 (128x20), b1, W2, b2, W3, b3, W4 (3x128), b4].
-void mlp_forward(const float *params, const float *X, int64_t n, float *Ha, float *Hb, float *Y,
-                 hipStream_t st);
+// Network forward pass on n rows of X [n][20] into Y [n][3], one fused
+// kernel (weights in LDS, activations on chip); params in the flat layout
+// [W1 (128x20), b1, W2, b2, W3, b3, W4 (3x128), b4].  With hdbg the FP32
+// hidden activations (before their bfloat16 rounding) also go to hdbg
+// [3][n][128] (parity checks).
+void mlp_forward(const float *params, const float *X, int64_t n, float *Y, hipStream_t st,
+                 float *hdbg = nullptr);
+// The same network as four matrix-product launches with the hidden
+// activations in Ha, Hb [n][128] (the training path's layout).
+void mlp_forward_layers(const float *params, const float *X, int64_t n, float *Ha, float *Hb,
+                        float *Y, hipStream_t st);
 
 struct SurrDev {
   const int32_t *vcell, *rbc_mesh, *rbc_box;
@@ -251,7 +257,7 @@ struct SurrDev {
 };
 void launch_surr_features(const SurrDev &sd, const BoxDev *boxes, const MeshDev *meshes, State s,
                           const uint32_t *slot_of_gid, const double *av, int64_t nvert,
-                          const uint32_t *kdev, float dt, hipStream_t st);
+                          const uint32_t *kdev, float dt, int kofs, hipStream_t st);
 void launch_surr_apply(const SurrDev &sd, int64_t nvert, hipStream_t st);
 void launch_surr_targets(const SurrDev &sd, float *T, int64_t nvert, hipStream_t st);
 void launch_surr_check(const SurrDev &sd, int nrbc, const uint32_t *kdev, int every,

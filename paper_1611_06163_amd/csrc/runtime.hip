@@ -1013,11 +1013,28 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   // serialised).  The surrogate, the simple pair kernel, the radix binning,
   // a timed membrane phase or a mesh too large for either launch's LDS take
   // the membrane kernel on a second stream beside the pair kernel instead.
-  const bool split = nrbc > 0 && tiled && !verlet && s->bin_mode == 0 && s->fuse_membrane && !s->surr_on &&
+  const bool split = nrbc > 0 && tiled && !verlet && s->bin_mode == 0 && s->fuse_membrane &&
                      !(s->timing_mask & (1 << 2)) && scan_takes_membrane(s->max_nv) &&
                      pair_tiled_takes_membrane(s->tile, s->S, s->any_shear, s->max_nv);
   MemArgs ma_split = mem_args(s, s->mc, s->Fm, SurrUse{nullptr, nullptr});
   if (!split) ma_split.nrbc = 0;
+  // With the surrogate on the split path the network runs on the second
+  // stream beside the binning, on the drifted positions in the previous
+  // order (so its cell totals are those of the previous evaluation, which
+  // the binning scan then updates); the check and the pair kernel's
+  // per-vertex terms, which take its forces where the last check allows,
+  // wait for it.
+  const bool surr_split = split && s->surr_on;
+  if (surr_split) {
+    (void)hipEventRecord(s->ev_fork, st);
+    (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
+    launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av,
+                         s->nvert, s->kdev, s->pc.dt, fuse_prev ? 1 : 0, s->st2);
+    mlp_forward(s->surr_params, s->sd.X, s->nvert, s->sd.Y, s->st2);
+    launch_surr_apply(s->sd, s->nvert, s->st2);
+    (void)hipEventRecord(s->ev_join, s->st2);
+    ma_split.su = SurrUse{s->sd.flag, s->sd.Fs};
+  }
   if (!rebuild) {
     // the particle order of the last rebuild stays
   } else if (s->bin_mode == 0) {
@@ -1035,6 +1052,19 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   if (verlet && rebuild)
     launch_list_build(s->d_boxes, int(s->boxes.size()), s->cur(), s->S, s->cell_start, s->ncell,
                       n, s->ld, s->errw, st);
+  if (surr_split) {
+    // every surr_every steps (gated on the device counter): the plain
+    // bending + local-area forces and the per-vertex fallback decision,
+    // before the pair kernel's per-vertex terms read it
+    (void)hipStreamWaitEvent(st, s->ev_join, 0);
+    MembraneConst ml = s->mc;
+    ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
+    ml.local_only = 1;
+    ml.gate = s->surr_every;
+    launch_membrane(mem_args(s, ml, s->sd.Fp, SurrUse{nullptr, nullptr}), s->d_boxes, s->cur(),
+                    s->kdev, s->errw, s->mem_lds, st);
+    launch_surr_check(s->sd, nrbc, s->kdev, s->surr_every, st);
+  }
   s->phase_end(1, tb, st);
   if (nrbc > 0 && !split) {
     (void)hipEventRecord(s->ev_fork, st);
@@ -1046,8 +1076,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
       // steps, gated on the device counter) the plain bending + local-area
       // forces and the per-vertex fallback decision
       launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av,
-                           s->nvert, s->kdev, s->pc.dt, s->st2);
-      mlp_forward(s->surr_params, s->sd.X, s->nvert, s->surr_Ha, s->surr_Hb, s->sd.Y, s->st2);
+                           s->nvert, s->kdev, s->pc.dt, 0, s->st2);
+      mlp_forward(s->surr_params, s->sd.X, s->nvert, s->sd.Y, s->st2);
       launch_surr_apply(s->sd, s->nvert, s->st2);
       MembraneConst ml = s->mc;
       ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
@@ -1803,7 +1833,7 @@ extern "C" int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *o
   // counter already holds the next step's
   launch_set_counter(s->kdev, s->kdev_val, s->st);
   launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av, nv,
-                       s->kdev, s->pc.dt, s->st);
+                       s->kdev, s->pc.dt, 0, s->st);
   MembraneConst ml = s->mc;
   ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
   ml.local_only = 1;

@@ -229,10 +229,33 @@ extern "C" int tdpd_mlp_forward(tdpd_mlp *m, const float *X, int64_t n, float *Y
   int rc = ensure_cap(m, n);
   if (rc) return rc;
   MLPCHK(hipMemcpyAsync(m->X, X, sizeof(float) * n * kSurrIn, hipMemcpyHostToDevice, m->st));
-  mlp_forward(m->params, m->X, n, m->H[0], m->H[1], m->Y, m->st);
+  mlp_forward(m->params, m->X, n, m->Y, m->st);
   if ((rc = check_launch(m))) return rc;
   MLPCHK(hipMemcpyAsync(Y, m->Y, sizeof(float) * n * kSurrOut, hipMemcpyDeviceToHost, m->st));
   MLPCHK(hipStreamSynchronize(m->st));
+  return TDPD_OK;
+}
+
+extern "C" int tdpd_mlp_forward_hidden(tdpd_mlp *m, const float *X, int64_t n, float *Y,
+                                       float *H) {
+  if (!m || n < 0 || (n > 0 && (!X || !Y || !H))) return TDPD_ERR_INVALID_ARG;
+  if (n == 0) return TDPD_OK;
+  int rc = ensure_cap(m, n);
+  if (rc) return rc;
+  float *dH = static_cast<float *>(m->dalloc(sizeof(float) * size_t(n) * 3 * kSurrHid));
+  if (!dH) return m->fail(TDPD_ERR_OOM, "device allocation failed");
+  hipError_t e = hipMemcpyAsync(m->X, X, sizeof(float) * n * kSurrIn, hipMemcpyHostToDevice, m->st);
+  if (e == hipSuccess) {
+    mlp_forward(m->params, m->X, n, m->Y, m->st, dH);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(Y, m->Y, sizeof(float) * n * kSurrOut, hipMemcpyDeviceToHost, m->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(H, dH, sizeof(float) * size_t(n) * 3 * kSurrHid, hipMemcpyDeviceToHost, m->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->st);
+  m->dfree(dH);
+  if (e != hipSuccess) return m->fail(TDPD_ERR_HIP, std::string("mlp_forward_hidden: ") + hipGetErrorString(e));
   return TDPD_OK;
 }
 

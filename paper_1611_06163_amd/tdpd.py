@@ -116,6 +116,7 @@ def lib():
             "tdpd_mlp_set_params": (C.c_int, [P, P]),
             "tdpd_mlp_get_params": (C.c_int, [P, P]),
             "tdpd_mlp_forward": (C.c_int, [P, P, I64, P]),
+            "tdpd_mlp_forward_hidden": (C.c_int, [P, P, I64, P, P]),
             "tdpd_mlp_loss_grad": (C.c_int, [P, P, P, I64, C.c_float, C.POINTER(C.c_double), P]),
             "tdpd_mlp_train": (C.c_int, [P, P, P, I64, C.c_float, I32, I32, C.c_float, P]),
             "tdpd_mlp_last_error": (C.c_char_p, [P]),
@@ -462,6 +463,16 @@ class Mlp:
         Y = np.empty((X.shape[0], 3), np.float32)
         self._check(lib().tdpd_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(Y)))
         return Y
+
+    def forward_hidden(self, X):
+        """Y [n][3] and the hidden layers' FP32 activations H [3][n][128]
+        (before their bfloat16 rounding)."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        n = X.shape[0]
+        Y = np.empty((n, 3), np.float32)
+        H = np.empty((3, n, 128), np.float32)
+        self._check(lib().tdpd_mlp_forward_hidden(self.h, _ptr(X), n, _ptr(Y), _ptr(H)))
+        return Y, H
 
     def loss_grad(self, X, T, target_scale=1.0):
         X = np.ascontiguousarray(X, dtype=np.float32)

@@ -3,6 +3,7 @@
 rounding points, the features and plain targets against the oracle, and the
 step with the network switched in."""
 import copy
+import math
 
 import numpy as np
 import pytest
@@ -27,14 +28,16 @@ def _data(n, seed):
 
 @pytest.mark.parametrize("n", [1, 63, 1000, 5000])
 def test_forward_matches_oracle(n):
-    """Both sides round each hidden activation to bfloat16 where it enters
-    the next product, the GPU after FP32 and the oracle after FP64
-    accumulation.  Where the two sums fall on the two sides of a rounding
-    boundary one activation differs by a bfloat16 ulp (2^-8 relative), which
-    moves that row's output by far less than 1e-2 of the output scale; every
-    other row agrees to FP32 accumulation error.  So: all rows within 1e-2 of
-    the RMS output, 99 % of rows within 1e-4 of their own output (the stated
-    1e-3 with margin), and the median at FP32 level."""
+    """End to end from the same inputs.  Both sides round each hidden
+    activation to bfloat16 where it enters the next product, the GPU after
+    FP32 and the oracle after FP64 accumulation, so where an activation sits
+    within accumulation error of a rounding boundary the two round it to
+    neighbouring bfloat16 values (2^-8 relative) and that row's output moves
+    by up to a few 1e-3 of its size.  The strict parity of every layer is
+    test_forward_layers_teacher_forced (1e-5 of the magnitude sums, from
+    the GPU's own rounded inputs); here: 99 % of rows within the surrogate's
+    1e-3 forward bound, every row within 1e-2 of the output scale, the
+    median at FP32 level."""
     p = I.mlp_init_params(1)
     X, _ = _data(n, 2)
     net = tdpd.Mlp(p)
@@ -45,11 +48,43 @@ def test_forward_matches_oracle(n):
     rms = np.sqrt(np.mean(nrm ** 2))
     rel = err / np.maximum(nrm, 1e-30)
     print("forward rel err: median", np.median(rel), "p99", np.quantile(rel, 0.99), "max",
-          rel.max(), "max / rms", (err / rms).max(), flush=True)
+          rel.max(), "rows above 1e-3", int((rel > 1e-3).sum()), "of", n, flush=True)
+    assert np.mean(rel <= 1e-3) >= 0.99
     assert (err <= 1e-2 * rms).all()
-    assert np.quantile(rel, 0.99) <= 1e-4
     assert np.median(rel) <= 1e-5
     assert np.array_equal(net.get_params(), p)
+
+
+@pytest.mark.parametrize("n", [63, 5000])
+def test_forward_layers_teacher_forced(n):
+    """Each layer of the fused forward pass from the GPU's own bfloat16
+    inputs: the oracle evaluates layer l (FP64 accumulation of the same
+    bfloat16 products, bias, SiLU) on the GPU's rounded activations of
+    layer l - 1, so no rounding decision can differ, and every activation
+    and output must agree to FP32 accumulation error: within 1e-5 of the
+    sum of the magnitudes entering it (the surrogate's 1e-3 forward bound
+    with a wide margin)."""
+    p = I.mlp_init_params(1)
+    X, _ = _data(n, 2)
+    net = tdpd.Mlp(p)
+    Y, H = net.forward_hidden(X)
+    layers = S.unpack(p)
+    ins = [X.astype(np.float64)] + [H[l].astype(np.float64) for l in range(3)]
+    worst = 0.0
+    for l, (W, b) in enumerate(layers):
+        A, Wr = S.bf16(ins[l]), S.bf16(W)
+        z = A @ Wr.T + b
+        mag = np.abs(A) @ np.abs(Wr).T + np.abs(b)
+        got = H[l] if l < 3 else Y
+        if l < 3:
+            want = S.silu(z)
+            scale = np.abs(S.silu_grad(z)) * mag + np.abs(want)
+        else:
+            want, scale = z, mag
+        e = np.abs(got.astype(np.float64) - want) / np.maximum(scale, 1e-30)
+        print(f"layer {l + 1}: max error / magnitude sum {e.max():.2e}", flush=True)
+        worst = max(worst, float(e.max()))
+    assert worst <= 1e-5
 
 
 def test_gradient_matches_oracle():
