@@ -36,11 +36,13 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 
 # HBM bytes per launch of the pair kernel from two rocprofv3 counter runs
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the factors a 256 MiB copy gives;
-# profiles/pair_tiled_single_rbc_20cube_hbm.md).  Valid only for the kernel
+# profiles/hbm_traffic_suspension_1000rbc.md).  Valid only for the kernel
 # sources and tile shape they were taken with: reported when both match.
 PAIR_SOURCES = ("kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h", "launch.h",
                 "membrane_cell.h")
 PAIR_TRAFFIC = {
+    "c5": {"sha256": "1983a1b52eadb0f371110f8dcb1bbdc36d781db6fc37e6ed338b50928afefe2c",
+           "tiles": {"2,3,1,1": [4.4213e+08, 5.6135e+07]}},
     "c2": {"sha256": "59dc66a822af5242516ac95286b8168f93d17401f5cd557e331bda8f01b0a829",
            "tiles": {"4,2,2,0": [3.048e+06, 4.964e+05],
                      "2,3,2,0": [3.182e+06, 4.965e+05],
@@ -257,12 +259,7 @@ def surrogate_leg(torch, tdpd, steps, warmup, cfg, desc):
         sysg.step(warmup)
         sysg.sync()
         el = _timed_steps(torch, sysg, steps)
-        sysg.set_timing(tdpd.PHASE["membrane"])
-        sysg.step(min(steps, 100))
-        mem_ms, mem_n = sysg.get_timing(tdpd.PHASE["membrane"])
-        sysg.set_timing(0)
-        r = dict(tol=tol, value=cfg.n * steps / el, ms_per_step=el * 1e3 / steps,
-                 membrane_us=mem_ms * 1e3 / max(mem_n, 1))
+        r = dict(tol=tol, value=cfg.n * steps / el, ms_per_step=el * 1e3 / steps)
         if tol is not None:
             st = sysg.surrogate_stats()
             r.update(on_network=st["on_network"], eligible=st["eligible"],
@@ -270,11 +267,24 @@ def surrogate_leg(torch, tdpd, steps, warmup, cfg, desc):
         runs.append(r)
         sysg.close()
         _log(f"surrogate run {r}")
+    # the network's forward pass alone on as many rows as the workload has
+    # vertices (host buffers in and out; the kernel's own time is in the
+    # kernel trace)
+    import numpy as np
+    nv = 0 if cfg.mesh_xyz is None else len(cfg.mesh_xyz) * len(cfg.rbc_first_gid)
+    nrow = min(nv, X.shape[0]) or X.shape[0]
+    Xr = np.ascontiguousarray(X[:nrow])
+    net.forward(Xr)
+    t3 = time.perf_counter()
+    for _ in range(5):
+        net.forward(Xr)
+    fwd_ms = (time.perf_counter() - t3) * 1e3 / 5
     plain, at = runs[0], runs[1]
     return dict(workload=desc, particles=cfg.n, value=at["value"], unit="particle-steps/s", tol=1e-2,
-                plain_value=plain["value"], membrane_us=at["membrane_us"],
-                plain_membrane_us=plain["membrane_us"], on_network=at["on_network"],
+                plain_value=plain["value"], on_network=at["on_network"],
                 by_tol=runs[1:],
+                network_forward=dict(rows=nrow, ms_host_buffers=fwd_ms,
+                                     flop_per_row=2 * (20 * 128 + 2 * 128 * 128 + 128 * 3)),
                 error="per-vertex |F_net - F_plain| / RMS_cell |F_plain| of bending + "
                       "local-area force at the last check; vertices above tol use F_plain",
                 training=dict(rep, collect_s=t1 - t0, train_s=t2 - t1,

@@ -167,9 +167,15 @@ int tdpd_create_batch(const tdpd_params *p, int32_t n_boxes, const tdpd_box *box
 int tdpd_set_state_boxes(tdpd_sys *s, const int64_t *box_count, const float *pos, const float *vel,
                          const float *conc, const uint32_t *flags);
 
-/* Set the whole particle state of a one-box system: n particles, pos [n][3] (wrapped into the box
-   by the library), vel [n][3], conc [n][n_species], flags [n].  All host
-   pointers.  Resets the step counter to 0 and drops membranes added before. */
+/* Set the whole particle state of a one-box system (Section 2.1: each
+   particle carries a position and a velocity, Eqs. (1)-(2), and one
+   concentration per species, Eq. (7)): n particles, pos [n][3] (wrapped
+   into the box by the library), vel [n][3], conc [n][n_species], flags [n]
+   (type, frozen bit).  All host pointers, copied before the call returns.
+   Resets the step counter to 0 and drops membranes added before.
+   TDPD_ERR_INVALID_ARG for n < 0, a NULL array with n > 0 or a bad flags
+   word; TDPD_ERR_NONFINITE for a non-finite value; TDPD_ERR_STATE on a
+   batch (which takes tdpd_set_state_boxes). */
 int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const float *vel,
                    const float *conc, const uint32_t *flags);
 
@@ -182,10 +188,18 @@ int tdpd_set_state(tdpd_sys *s, int64_t n, const float *pos, const float *vel,
 int tdpd_add_mesh(tdpd_sys *s, int32_t nv, const double *ref_xyz, int32_t ntri,
                   const int32_t *tri, const tdpd_mesh_params *mp, int32_t *mesh_id);
 
-/* Bind particles [first_gid, first_gid + nv) to one cell of mesh mesh_id
+/* Bind particles [first_gid, first_gid + nv) to one red cell of mesh
+   mesh_id (Section 2.2: the membrane vertices are particles of the fluid
+   that also carry the membrane forces of Eqs. (13)-(19); Section 3.3)
    (vertex v is particle first_gid + v; all in one box, whose half length
-   must exceed 1.25 times the cell's radius plus 1).  Pair forces between vertices of the
-   same cell are left to the bonded terms; fluxes act between all pairs. */
+   must exceed 1.25 times the cell's radius plus 1).  Pair forces between
+   vertices of the same cell are left to the bonded terms; fluxes act
+   between all pairs.  Writes the cell's index to *rbc_id.  Call after
+   set_state and before stepping (TDPD_ERR_STATE otherwise).
+   TDPD_ERR_INVALID_ARG for an unknown mesh, a gid range outside the state
+   or across two boxes, or a particle already bound or frozen;
+   TDPD_ERR_UNSUPPORTED for too many cells or a cell too large for its
+   box. */
 int tdpd_add_rbc(tdpd_sys *s, int32_t mesh_id, int64_t first_gid, int32_t *rbc_id);
 
 /* Evaluate F and Q at the current state with random-number step counter k,
@@ -193,16 +207,23 @@ int tdpd_add_rbc(tdpd_sys *s, int32_t mesh_id, int64_t first_gid, int32_t *rbc_i
    dissipative force and fluxes see.  Asynchronous. */
 int tdpd_compute_forces(tdpd_sys *s, uint32_t k);
 
-/* Advance n_steps velocity-Verlet steps; step n draws random numbers with
-   counter k = n.  The first call after set_state evaluates the forces at
-   k = 0 first.  Asynchronous: errors found by kernels surface at the next
-   tdpd_sync or tdpd_get_*. */
+/* Advance n_steps steps of Eqs. (1), (2) and (7) (positions, velocities,
+   concentrations) with velocity Verlet, the forces of Eqs. (3)-(6) and
+   (13)-(19) and the fluxes of Eqs. (7)-(10) evaluated once per step; step
+   n draws random numbers with counter k = n.  The first call after
+   set_state evaluates the forces at k = 0 first.  Asynchronous: errors
+   found by kernels surface at the next tdpd_sync or tdpd_get_*.
+   TDPD_ERR_INVALID_ARG for n_steps < 0, TDPD_ERR_STATE before set_state,
+   TDPD_ERR_UNSUPPORTED once the 32-bit step counter would wrap. */
 int tdpd_step(tdpd_sys *s, int32_t n_steps);
 
 /* Wait for the stream, then read and clear the device error word. */
 int tdpd_sync(tdpd_sys *s);
 
-/* Copy state to host buffers in gid order; any pointer may be NULL. */
+/* Copy the state of Eqs. (1), (2) and (7) to host buffers in gid order:
+   pos [n][3] (in the box), vel [n][3], conc [n][n_species]; any pointer
+   may be NULL.  Waits for the stream; returns a kernel error found since
+   the last sync. */
 int tdpd_get_state(tdpd_sys *s, float *pos, float *vel, float *conc);
 /* Last evaluated forces [n][3] and concentration rates [n][n_species]. */
 int tdpd_get_forces(tdpd_sys *s, float *F, float *Q);
@@ -222,9 +243,14 @@ int tdpd_get_forces(tdpd_sys *s, float *F, float *Q);
    to *n_out; TDPD_ERR_CAPACITY if n_out > cap. */
 int tdpd_get_pairs(tdpd_sys *s, int32_t which, int64_t cap, int32_t *ij, int64_t *n_out);
 
-/* FP64 diagnostics: out[0..2] total momentum of mobile particles, out[3] kT
-   = sum |v - vbar|^2 / (3 (N_mobile - 1)), out[4..4+S) total concentration
-   per species, then per cell (A^t, V^t).  cap = doubles available. */
+/* FP64 diagnostics of the conserved and controlled quantities: out[0..2]
+   total momentum of mobile particles (conserved by the pair forces,
+   Section 2.1), out[3] kT = sum |v - vbar|^2 / (3 (N_mobile - 1)) (the
+   temperature of Eq. (6)), out[4..4+S) total concentration per species
+   (conserved by the fluxes of Eqs. (8)-(10)), then per cell the total area
+   and volume (A^t, V^t) of Eqs. (17)-(18).  cap = doubles available in the
+   host buffer out (TDPD_ERR_CAPACITY if short).  Evaluates the forces
+   first if the state has none yet; waits for the stream. */
 int tdpd_diagnostics(tdpd_sys *s, double *out, int64_t cap);
 
 /* The same diagnostics for callers that cannot allocate: code under HIP graph
@@ -307,12 +333,12 @@ int tdpd_get_tile(const tdpd_sys *s, int32_t *waves, int32_t *chunks, int32_t *s
    checked every step: a larger displacement, or a particle with more
    than capacity list entries, makes the next tdpd_sync (and every call
    that syncs) return TDPD_ERR_LIST; the forces of that step are then
-   not to be trusted.  The capacity is rounded up to a multiple of 8 and
+   not to be trusted.  A given capacity is rounded up to a multiple of 8 and
    split evenly over the 8 sub-lists a particle's neighbours are dealt
    into (4 sub-lists from 131,072 particles on; the error is raised when
    one of them is full); capacity 0 picks
-   three times the mean count at the nominal density rho plus 128 (at most
-   4096).  Cells are made at least
+   three times the mean count at the nominal density rho plus 128, rounded
+   up to a multiple of 32 (at most 4096).  Cells are made at least
    max(r_c, r_cc) + skin wide (TDPD_ERR_BOX_TOO_SMALL under 3 per side).
    Call after tdpd_create or tdpd_set_state and before the first step or
    force evaluation of that state (TDPD_ERR_STATE otherwise); skin 0 or
