@@ -38,8 +38,8 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 # (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, the factors a 256 MiB copy gives;
 # profiles/hbm_traffic_suspension_1000rbc.md).  Valid only for the kernel
 # sources and tile shape they were taken with: reported when both match.
-PAIR_SOURCES = ("kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h", "launch.h",
-                "membrane_cell.h")
+PAIR_SOURCES = ("pair_tiled.h", "kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h",
+                "launch.h", "membrane_cell.h")
 PAIR_TRAFFIC = {
     "c5": {"sha256": "1983a1b52eadb0f371110f8dcb1bbdc36d781db6fc37e6ed338b50928afefe2c",
            "tiles": {"2,3,1,1": [4.4213e+08, 5.6135e+07]}},

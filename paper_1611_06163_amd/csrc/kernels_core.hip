@@ -544,7 +544,9 @@ __global__ void __launch_bounds__(256) k_rank_gather(State a, State b, const uin
     if (sp < nspec) b.C[sp * n + p] = cv[sp];
   b.gid[p] = g;
   b.info[p] = info;
-  slot_of_gid[g] = p;
+  // the id-to-slot map serves the membrane gathers: vertices only (a
+  // scattered 4-byte store per solvent particle would cost a write granule)
+  if (info_body(info) >= 0) slot_of_gid[g] = p;
   keys_sorted[p] = c;
 }
 
@@ -629,10 +631,10 @@ __global__ void __launch_bounds__(256) k_reorder(State a, State b, const uint32_
   b.vy[p] = a.vy[q];
   b.vz[p] = a.vz[q];
   for (int sp = 0; sp < nspec; ++sp) b.C[sp * n + p] = a.C[sp * n + q];
-  const uint32_t g = a.gid[q];
+  const uint32_t g = a.gid[q], info = a.info[q];
   b.gid[p] = g;
-  b.info[p] = a.info[q];
-  slot_of_gid[g] = uint32_t(p);
+  b.info[p] = info;
+  if (info_body(info) >= 0) slot_of_gid[g] = uint32_t(p);  // vertices only
 }
 
 void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
@@ -726,13 +728,14 @@ void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hi
 }
 
 // ------------------------------------------------------------- gid order
-__global__ void __launch_bounds__(256) k_gather_gid(State s, const uint32_t *__restrict__ slot,
-                                                    int64_t n, int nspec, const float *__restrict__ F,
-                                                    const float *__restrict__ Q, float *pos,
-                                                    float *vel, float *conc, float *Fo, float *Qo) {
-  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const uint32_t p = slot[g];
+// Copy of the state (and F, Q) in gid order: slot p goes to row gid[p].
+__global__ void __launch_bounds__(256) k_to_gid_order(State s, int64_t n, int nspec,
+                                                      const float *__restrict__ F,
+                                                      const float *__restrict__ Q, float *pos,
+                                                      float *vel, float *conc, float *Fo, float *Qo) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t g = s.gid[p];
   if (pos) {
     pos[3 * g] = s.x[p];
     pos[3 * g + 1] = s.y[p];
@@ -754,12 +757,11 @@ __global__ void __launch_bounds__(256) k_gather_gid(State s, const uint32_t *__r
     for (int sp = 0; sp < nspec; ++sp) Qo[nspec * g + sp] = Q[nspec * p + sp];
 }
 
-void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, int nspec,
-                             const float *F, const float *Q, float *pos, float *vel, float *conc,
-                             float *Fo, float *Qo, hipStream_t st) {
+void launch_gid_order(State s, int64_t n, int nspec, const float *F, const float *Q, float *pos,
+                      float *vel, float *conc, float *Fo, float *Qo, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather_gid, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, s,
-                     slot_of_gid, n, nspec, F, Q, pos, vel, conc, Fo, Qo);
+  hipLaunchKernelGGL(k_to_gid_order, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, s, n,
+                     nspec, F, Q, pos, vel, conc, Fo, Qo);
 }
 
 }  // namespace tdpd

@@ -90,7 +90,8 @@ void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
 // cell_start (counts zeroed for the next step; tile_sum holds
 // count_scan_tiles(ncell) words; tmp holds 2n words), scatter, and the rank
 // fix-up fused with
-// the reorder of every state plane into dst (slot_of_gid and the sorted keys
+// the reorder of every state plane into dst (slot_of_gid of the membrane
+// vertices and the sorted keys
 // updated).  Same permutation as the stable radix sort.
 int64_t count_scan_tiles(int64_t ncell);
 // With advance, the scatter also advances the step counter *advance by one.
@@ -111,7 +112,8 @@ bool scan_takes_membrane(int max_nv);
 // cell_start[c] = first sorted index of cell c, cell_start[ncell] = n.
 void launch_cell_bounds(const uint32_t *sorted_keys, int64_t n, int64_t ncell,
                         uint32_t *cell_start, hipStream_t st);
-// dst[p] = src[perm[p]] for every state plane; slot_of_gid[gid] = p.
+// dst[p] = src[perm[p]] for every state plane; slot_of_gid[gid] = p for
+// membrane vertices (the map serves the membrane gathers only).
 void launch_reorder(State src, State dst, const uint32_t *perm, int64_t n, int nspec,
                     uint32_t *slot_of_gid, hipStream_t st);
 // Adds the membrane forces Fm (indexed by global vertex, see launch_membrane)
@@ -142,6 +144,9 @@ extern const PairTile kPairTiles[];  // the shapes the kernel is built for
 extern const int kNumPairTiles;
 // Whether the shape is built for n_species species.
 bool pair_tile_built(const PairTile &t, int n_species);
+// Whether the tiled kernel runs its queued-flux build for these parameters
+// (the random flux on, or more than four species).
+bool pair_tiled_queued(const PairConst &pc);
 // Enumerate pairs (gid_i < gid_j) below rcut^2 with the same cell search.
 void launch_pair_emit(const PairConst &pc, const BoxDev *boxes, State s,
                       const uint32_t *cell_keys,
@@ -158,10 +163,9 @@ void launch_diag(State s, int64_t n, int nspec, double *partial, double *out, hi
 // out[4 + nspec] = (P[3], kT, ΣC[nspec]) from the totals of launch_diag.
 void launch_diag_finish(const double *sums, int nspec, double *out, hipStream_t st);
 
-// Copy (AoS <-> SoA) in gid order.
-void launch_gather_gid_order(State s, const uint32_t *slot_of_gid, int64_t n, int nspec,
-                             const float *F, const float *Q, float *pos, float *vel, float *conc,
-                             float *Fo, float *Qo, hipStream_t st);
+// Copy (SoA -> AoS) in gid order: slot p to row gid[p].
+void launch_gid_order(State s, int64_t n, int nspec, const float *F, const float *Q, float *pos,
+                      float *vel, float *conc, float *Fo, float *Qo, hipStream_t st);
 
 
 // All membrane terms of every cell, one workgroup per cell: per-cell FP64

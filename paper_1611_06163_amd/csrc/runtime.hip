@@ -1003,10 +1003,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
                     s->kdev, st);  // advances the counter
     return TDPD_OK;
   }
-  // the tiled kernel has no random-flux path; that term (m_s > 0) uses the
-  // one-thread-per-particle kernel; it also packs a slot into 26 bits
-  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
-  const bool tiled = !(s->pair_kernel == 0 || random_flux || n >= (int64_t(1) << 26));
+  // (the tiled kernel packs a slot into 26 bits)
+  const bool tiled = !(s->pair_kernel == 0 || n >= (int64_t(1) << 26));
   // The membrane terms normally ride along in two launches the step makes
   // anyway: the K-Gather and bond forces in the binning scan's launch, the
   // per-vertex part in the pair kernel's (no second stream, nothing
@@ -1287,9 +1285,8 @@ static int readback(tdpd_sys *s, float *pos, float *vel, float *conc, float *F, 
   float *buf = dallocT<float>(s, size_t(n) * (9 + 2 * S));
   if (!buf) return s->fail(TDPD_ERR_OOM, "device allocation failed");
   float *dp = buf, *dv = buf + 3 * n, *dc = buf + 6 * n, *dF = dc + S * n, *dQ = dF + 3 * n;
-  launch_gather_gid_order(s->cur(), s->slot_of_gid, n, S, s->F, s->Q, pos ? dp : nullptr,
-                          vel ? dv : nullptr, conc ? dc : nullptr, F ? dF : nullptr,
-                          Q ? dQ : nullptr, s->st);
+  launch_gid_order(s->cur(), n, S, s->F, s->Q, pos ? dp : nullptr, vel ? dv : nullptr,
+                   conc ? dc : nullptr, F ? dF : nullptr, Q ? dQ : nullptr, s->st);
   hipError_t e = hipSuccess;
   if (pos && e == hipSuccess) e = hipMemcpyAsync(pos, dp, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, s->st);
   if (vel && e == hipSuccess) e = hipMemcpyAsync(vel, dv, sizeof(float) * 3 * n, hipMemcpyDeviceToHost, s->st);
@@ -1600,9 +1597,9 @@ std::string tune_signature(const tdpd_sys *s) {
   (void)hipGetDevice(&dev);
   (void)hipGetDeviceProperties(&prop, dev);
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s n=%lld S=%d boxes=%zu cells=%lld rbcs=%zu terms=%d",
+  std::snprintf(buf, sizeof(buf), "%s n=%lld S=%d boxes=%zu cells=%lld rbcs=%zu terms=%d q=%d",
                 prop.gcnArchName, (long long)s->n, s->S, s->boxes.size(), (long long)s->ncell,
-                s->rbc_mesh.size(), s->prm.terms);
+                s->rbc_mesh.size(), s->prm.terms, pair_tiled_queued(s->pc) ? 1 : 0);
   for (char *c = buf; *c; ++c)
     if (*c == ':' || *c == '\n') *c = '_';
   return buf;
@@ -1637,8 +1634,7 @@ extern "C" int tdpd_autotune(tdpd_sys *s, const char *cache_path, int32_t reps,
   const std::string sig = tune_signature(s);
   PairTile best = s->tile;
   double best_t = -1.0;
-  const bool random_flux = s->pc.ms_rho > 0.f && (s->pc.terms & TDPD_TERM_FLUX_RANDOM);
-  if (s->n == 0 || s->pair_kernel == 0 || random_flux || s->n >= (int64_t(1) << 26)) {
+  if (s->n == 0 || s->pair_kernel == 0 || s->n >= (int64_t(1) << 26)) {
     if (best_ms) *best_ms = 0.0;
     return TDPD_OK;  // the tiled kernel is not used for this system
   }

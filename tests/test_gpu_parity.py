@@ -104,8 +104,14 @@ def test_tiled_candidate_path_pair_sets_bit_exact(name, filt):
 
 
 @pytest.mark.parametrize("kernel", [0, 1])
-@pytest.mark.parametrize("name", ["c1", "cluster", "c1_randflux", "c2", "c3_small", "c3_cells"])
+@pytest.mark.parametrize("name", ["c1", "cluster", "c1_randflux", "c2", "c2_randflux",
+                                  "three_randflux", "c3_small", "c3_cells"])
 def test_teacher_forced_forces(kernel, name):
+    """Forces and fluxes of one evaluation against the oracle at the GPU's
+    own state; with the random flux of Eqs. (9)-(10) (m_s > 0) the tiled
+    kernel runs its queued-flux build: one, two (with a cell body, whose
+    vertex pairs exchange flux but no pair force) and three species (the
+    third from the second Philox stream's other word pair)."""
     if name == "c1":
         cfg = I.c1()
     elif name == "cluster":
@@ -113,6 +119,12 @@ def test_teacher_forced_forces(kernel, name):
     elif name == "c1_randflux":
         cfg = I.c1()
         cfg.m_s = 0.05
+    elif name == "c2_randflux":
+        cfg = I.c2()
+        cfg.m_s = 0.05
+    elif name == "three_randflux":
+        cfg = I.make_fluid(box=(8.0, 8.0, 8.0), rho=3.0, n_species=3, seed=29)
+        cfg.m_s = 0.08
     elif name == "c2":
         cfg = I.c2()
     elif name == "c3_cells":  # twenty cells
@@ -350,19 +362,22 @@ def test_checkpoint_resume_bitwise(tmp_path):
 
 @pytest.mark.parametrize("tile", [(4, 1, 1, 1), (4, 3, 1, 0), (2, 2, 1, 1), (2, 4, 1, 0),
                                   (4, 2, 2, 1), (2, 2, 4, 0), (2, 3, 1, 1), (4, 2, 1, 0)])
-@pytest.mark.parametrize("name", ["cluster", "c2", "dense"])
+@pytest.mark.parametrize("name", ["cluster", "c2", "dense", "cluster_randflux", "c2_randflux"])
 def test_tile_shapes_match_oracle(tile, name):
     """Every tile shape of the cell-tiled kernel, with and without the
     stencil filter, gives forces and fluxes within tolerance of the oracle
     (cluster: cells above 64 particles and stencils above 256 candidates;
     c2: one cell body in solvent; dense: stencils of 1000 candidates, beyond
-    the filter's list, which then tests the whole stencil)."""
-    if name == "cluster":
+    the filter's list, which then tests the whole stencil; *_randflux: the
+    queued-flux build with the random flux, m_s = 0.05)."""
+    if name.startswith("cluster"):
         cfg = _cluster_cfg()
     elif name == "dense":
         cfg = I.make_fluid(box=(6.0, 6.0, 6.0), n=1000, seed=17)
     else:
         cfg = I.c2()
+    if name.endswith("randflux"):
+        cfg.m_s = 0.05
     sysg = gpu_system(cfg, kernel=1)
     sysg.tile = tile
     assert sysg.tile == tile
@@ -378,31 +393,33 @@ def test_tile_shapes_match_oracle(tile, name):
     assert rep["excluded"] <= 5 + cfg.n // 20
 
 
-def _ten_species():
-    cfg = I.make_fluid(box=(8.0, 8.0, 8.0), rho=3.0, n_species=10, seed=23)
-    for sp in range(10):
+def _ten_species(ns=10):
+    cfg = I.make_fluid(box=(8.0, 8.0, 8.0), rho=3.0, n_species=ns, seed=23)
+    for sp in range(ns):
         cfg.kappa[sp] *= 1.0 + 0.25 * sp
     return cfg
 
 
+@pytest.mark.parametrize("ns", [10, 6])
 @pytest.mark.parametrize("kernel,tile", [(0, None), (1, (4, 2, 1, 1)), (1, (4, 1, 2, 0)),
                                          (1, (2, 2, 1, 0)), (1, (4, 2, 4, 1))])
-def test_ten_species_match_oracle(kernel, tile):
+def test_ten_species_match_oracle(kernel, tile, ns):
     """Ten species (the 16-species build of the tiled kernel, two register
-    chunks at most): forces and all ten fluxes against the oracle."""
-    cfg = _ten_species()
+    chunks at most) and six (the 8-species build), both with the flux
+    queued: forces and all fluxes against the oracle."""
+    cfg = _ten_species(ns)
     sysg = gpu_system(cfg, kernel=kernel)
     if tile is not None:
         sysg.tile = tile
     k = 6
     sysg.compute_forces(k)
     F, Q = sysg.get_forces()
-    assert Q.shape == (cfg.n, 10)
+    assert Q.shape == (cfg.n, ns)
     pos, vel, conc = sysg.get_state()
     o = Oracle(cfg)
     ref = o.forces(pos, vel, conc, k=k)
     excl, sens = near_cutoff(o, cfg, pos, vel, ref, k)
-    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"10 species/k{kernel}/{tile}")
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"{ns} species/k{kernel}/{tile}")
     assert rep["badF"] == 0 and rep["badQ"] == 0
     assert rep["excluded"] <= 5 + cfg.n // 20
 
