@@ -443,6 +443,10 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       uint32_t row[Shm::kRow];
 #pragma unroll
       for (int c = 0; c < Shm::kRow / 4; ++c) {
+        if (c > 0 && 4 * c >= 2 + S) {  // words past the species in use
+          row[4 * c] = row[4 * c + 1] = row[4 * c + 2] = row[4 * c + 3] = 0u;
+          continue;
+        }
         const uint4 r4 = sh.tab[w][tq][c];
         row[4 * c] = r4.x;
         row[4 * c + 1] = r4.y;
@@ -601,8 +605,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
               row[2 + sp] = (sp < NS && sp < S) ? __float_as_uint(s.C[sp * n + j]) : 0u;
 #pragma unroll
             for (int c = 0; c < Shm::kRow / 4; ++c)
-              sh.tab[w][kk * 64 + lane][c] =
-                  make_uint4(row[4 * c], row[4 * c + 1], row[4 * c + 2], row[4 * c + 3]);
+              if (c == 0 || 4 * c < 2 + S)
+                sh.tab[w][kk * 64 + lane][c] =
+                    make_uint4(row[4 * c], row[4 * c + 1], row[4 * c + 2], row[4 * c + 3]);
           } else {
             const uint32_t inf = s.info[j];
             ct[kk] = info_type(inf);
