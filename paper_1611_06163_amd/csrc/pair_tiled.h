@@ -734,12 +734,20 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
               qp[sp] = fmaf(sh.kap[sp][tt] * wdc, cc[kk][sp] - ci[sp], qp[sp]);
             }
           }
-          // homes outside any cell body test the cutoff alone
-          const bool hitf = bq == -3 ? d2m1 < rc2m1 : (d2m1 < rc2m1) & (cbody[kk] != bq);
-          const uint64_t fm = ballot(hitf);
+          // (a home outside any cell body has bq = -3, which no candidate's
+          // body id matches).  The mask is the AND of two ballots of single
+          // compares, each of which is the compare's own lane mask (a ballot
+          // of the combined predicate would first turn it into a lane value
+          // and back)
+          const bool inr = d2m1 < rc2m1, other = cbody[kk] != bq;
+          const uint64_t fm = ballot(inr) & ballot(other);
           if (fm) {
-            if (hitf) {
-              const uint32_t e = (lane_rank(fm) + tail) & uint32_t(kRing - 1);
+            if (inr && other) {
+              // rank among the set lanes, with the ring's tail as its base
+              const uint32_t e =
+                  __builtin_amdgcn_mbcnt_hi(uint32_t(fm >> 32),
+                                            __builtin_amdgcn_mbcnt_lo(uint32_t(fm), tail)) &
+                  uint32_t(kRing - 1);
               sh.ring[w][e] = make_float4(dx, dy, dz, __uint_as_float(hbits | cj[kk]));
               if constexpr (LE) sh.rl[w][e] = uint8_t((lift[kk] >> 3) & 3u);
             }
