@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtdpd.so")
 SOURCES = ["kernels_core.hip", "kernels_pair.hip", "kernels_pair_tiled.hip",
-           "kernels_pair_tiled_rf.hip", "kernels_pair_tiled_ns.hip", "kernels_pair_tiled_ns16.hip",
+           "kernels_pair_tiled_rf.hip", "kernels_pair_tiled_ns.hip",
+           "kernels_pair_tiled_ns12.hip", "kernels_pair_tiled_ns16.hip",
            "kernels_pair_list.hip", "kernels_membrane.hip", "kernels_surrogate.hip", "surrogate.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -2,8 +2,9 @@
 // one- and two-species builds, the EMIT build that lists the candidate
 // path's pairs, and the dispatch over species counts and tile shapes.  The
 // queued-flux builds (random flux, and five or more species) are
-// instantiated in kernels_pair_tiled_rf.hip, kernels_pair_tiled_ns.hip and
-// kernels_pair_tiled_ns16.hip, so the four compile in parallel.
+// instantiated in kernels_pair_tiled_rf.hip, kernels_pair_tiled_ns.hip,
+// kernels_pair_tiled_ns12.hip and kernels_pair_tiled_ns16.hip, so the five
+// compile in parallel.
 #include "pair_tiled.h"
 
 namespace tdpd {
@@ -15,6 +16,7 @@ extern TDPD_TILED_NS_DECL(2, true);
 extern TDPD_TILED_NS_DECL(4, true);
 extern TDPD_TILED_NS_DECL(4, false);
 extern TDPD_TILED_NS_DECL(8, true);
+extern TDPD_TILED_NS_DECL(12, true);
 extern TDPD_TILED_NS_DECL(16, true);
 
 // The EMIT build of one shape (one species slot: it evaluates no terms).
@@ -80,6 +82,7 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
     TDPD_NS(4, false);
   }
   if (pc.n_species <= 8) TDPD_NS(8, true);
+  if (pc.n_species <= 12) TDPD_NS(12, true);
   TDPD_NS(16, true);
 #undef TDPD_NS
 }
@@ -139,7 +142,8 @@ bool pair_tiled_takes_membrane(const PairTile &t, int n_species, bool sheared, i
                       : n_species == 2 ? lds_ns<2, false>(t, sheared)
                       : n_species <= 4 ? lds_ns<4, false>(t, sheared)
                       : n_species <= 8 ? lds_ns<8, true>(t, sheared)
-                                       : lds_ns<16, true>(t, sheared);
+                      : n_species <= 12 ? lds_ns<12, true>(t, sheared)
+                                        : lds_ns<16, true>(t, sheared);
   return membrane_cell_lds(max_nv, 64 * t.waves) <= have;
 }
 

@@ -116,14 +116,22 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
 
 template <int NS, int W, int KC, bool SH, bool QF>
 struct TiledShared {
+  // The queued builds keep 32 homes per pass (a cell at the densities of
+  // the method holds about a dozen particles; more take further passes):
+  // their per-wave flux accumulators scale with it.
+  static constexpr int kH = QF ? 32 : kHome;
+  // Many species (QF, NS > 4): the block table holds slot and info word
+  // only, and the queue evaluation reads a partner's concentrations from L2
+  // (a full row would hold NS of them per candidate and cap the occupancy).
+  static constexpr bool kNarrow = QF && NS > 4;
   // words of a candidate's row in the block table: slot, info word, the
   // concentrations, padded to whole 16-byte loads
-  static constexpr int kRow = (2 + NS + 3) / 4 * 4;
-  float hx[kHome], hy[kHome], hz[kHome], hvx[kHome], hvy[kHome], hvz[kHome];
-  float hc[NS][kHome];
-  uint32_t hgid[kHome], hinfo[kHome];
-  float fa[W][3][kHome];
-  float qa[W][NS][kHome];
+  static constexpr int kRow = kNarrow ? 2 : (2 + NS + 3) / 4 * 4;
+  float hx[kH], hy[kH], hz[kH], hvx[kH], hvy[kH], hvz[kH];
+  float hc[NS][kH];
+  uint32_t hgid[kH], hinfo[kH];
+  float fa[W][3][kH];
+  float qa[W][NS][kH];
   float kap[NS][kMaxT * kMaxT];
   int seg_start[kMaxSeg];
   int seg_pref[kMaxSeg + 1];
@@ -132,7 +140,8 @@ struct TiledShared {
   int8_t seg_m[kMaxSeg];   // multiple of L_x added to the lifted x
   // (QF) the candidates of each wave's register block (kk * 64 + lane):
   // slot, info word and concentrations, read when a queued pair is evaluated
-  uint4 tab[QF ? W : 1][QF ? KC * 64 : 1][QF ? kRow / 4 : 1];
+  uint4 tab[QF && !kNarrow ? W : 1][QF && !kNarrow ? KC * 64 : 1][QF && !kNarrow ? kRow / 4 : 1];
+  uint2 tabn[kNarrow ? W : 1][kNarrow ? KC * 64 : 1];
   // (QF) pair queue of each wave: candidates within the largest cutoff, as
   // (displacement, home index << kJBits | position in the block table)
   float4 fq[QF ? W : 1][QF ? kRing : 1];
@@ -389,8 +398,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
     sh.kap[sp][tt] = (sp < S && tt < T * T) ? pc.kappa[sp * T * T + tt] : 0.f;
   }
 
-  for (int hb = h0; hb < h1; hb += kHome) {
-    const int nh = min(kHome, h1 - hb);
+  constexpr int kH = Shm::kH;
+  for (int hb = h0; hb < h1; hb += kH) {
+    const int nh = min(kH, h1 - hb);
     if (tid < nh) {
       const int p = hb + tid;
       sh.hx[tid] = s.x[p];
@@ -404,9 +414,11 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       sh.hgid[tid] = s.gid[p];
       sh.hinfo[tid] = s.info[p];
     }
-    sh.fa[w][0][lane] = sh.fa[w][1][lane] = sh.fa[w][2][lane] = 0.f;
+    if (lane < kH) {
+      sh.fa[w][0][lane] = sh.fa[w][1][lane] = sh.fa[w][2][lane] = 0.f;
 #pragma unroll
-    for (int sp = 0; sp < NS; ++sp) sh.qa[w][sp][lane] = 0.f;
+      for (int sp = 0; sp < NS; ++sp) sh.qa[w][sp][lane] = 0.f;
+    }
     __syncthreads();
     // this wave's cursors (wave-uniform): the force ring (head, tail), or
     // with QF the pair queue (head, tail) and the force ring (fhead, ftail)
@@ -441,20 +453,31 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       const int i = valid ? int(wd >> kJBits) : 0;
       const uint32_t tq = valid ? (wd & ((1u << kJBits) - 1)) : 0u;
       uint32_t row[Shm::kRow];
+      if constexpr (Shm::kNarrow) {
+        const uint2 r2 = sh.tabn[w][tq];
+        row[0] = r2.x;
+        row[1] = r2.y;
+      } else {
 #pragma unroll
-      for (int c = 0; c < Shm::kRow / 4; ++c) {
-        if (c > 0 && 4 * c >= 2 + S) {  // words past the species in use
-          row[4 * c] = row[4 * c + 1] = row[4 * c + 2] = row[4 * c + 3] = 0u;
-          continue;
+        for (int c = 0; c < Shm::kRow / 4; ++c) {
+          if (c > 0 && 4 * c >= 2 + S) {  // words past the species in use
+            row[4 * c] = row[4 * c + 1] = row[4 * c + 2] = row[4 * c + 3] = 0u;
+            continue;
+          }
+          const uint4 r4 = sh.tab[w][tq][c];
+          row[4 * c] = r4.x;
+          row[4 * c + 1] = r4.y;
+          row[4 * c + 2] = r4.z;
+          row[4 * c + 3] = r4.w;
         }
-        const uint4 r4 = sh.tab[w][tq][c];
-        row[4 * c] = r4.x;
-        row[4 * c + 1] = r4.y;
-        row[4 * c + 2] = r4.z;
-        row[4 * c + 3] = r4.w;
       }
       // (lanes past m read a stale table row: masked)
       const uint32_t j = valid ? row[0] : 0u, infoj = valid ? row[1] : 0u;
+      // the partner's concentration of species sp (from the table, or L2)
+      auto cjv = [&](int sp) __attribute__((always_inline)) -> float {
+        if constexpr (Shm::kNarrow) return s.C[sp * n + j];
+        else return __uint_as_float(row[2 + sp]);
+      };
       const float d2 = dist2(re.x, re.y, re.z);  // the bits of the test
       const uint32_t d2b = __float_as_uint(d2);
       const uint32_t infoi = sh.hinfo[i];
@@ -482,7 +505,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
         for (int sp = 0; sp < NS; ++sp) {
           q[sp] = 0.f;
           if (fick && inq && (NS == 1 || sp < S))
-            q[sp] = sh.kap[sp][tt] * wdc * (__uint_as_float(row[2 + sp]) - sh.hc[sp][i]);
+            q[sp] = sh.kap[sp][tt] * wdc * (cjv(sp) - sh.hc[sp][i]);
         }
         if (rflux && inq) {
           // eps_ij w_RC zeta_ij / sqrt(dt) per species, zeta from the pair's
@@ -493,7 +516,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
           const uint32_t lo = gi < gj ? gi : gj, hi = gi < gj ? gj : gi;
           const float a = (gi > gj ? -pc.isdt : pc.isdt) * powu(wq, pc.sc_half);
           auto add = [&](int sp, float z) __attribute__((always_inline)) {
-            const float csum = fmaxf(__uint_as_float(row[2 + sp]) + sh.hc[sp][i], 0.f);
+            const float csum = fmaxf(cjv(sp) + sh.hc[sp][i], 0.f);
             const float eps = __builtin_amdgcn_sqrtf(pc.ms_rho * sh.kap[sp][tt] * csum);
             q[sp] = fmaf(eps * a, z, q[sp]);
           };
@@ -513,7 +536,7 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
         // runs of equal home index: a lane starts a run where the index
         // differs from the previous lane's (lane 0 always; lanes past m
         // form a run of zeros)
-        const int ik = valid ? i : kHome;
+        const int ik = valid ? i : kH;
         const int ip = __builtin_amdgcn_update_dpp(-1, ik, 0x138, 0xf, 0xf, false);  // wave_shr:1
         const bool run0 = ik != ip;
         seg_scan<NS>(q, run0);
@@ -596,7 +619,9 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
               lift[kk] |= 2u | (1u << 3) | (uint32_t(sh.seg_m[lo] + 2) << 5);
             }
           }
-          if constexpr (QF) {
+          if constexpr (Shm::kNarrow) {
+            sh.tabn[w][kk * 64 + lane] = make_uint2(j, s.info[j]);
+          } else if constexpr (QF) {
             uint32_t row[Shm::kRow];
             row[0] = j;
             row[1] = s.info[j];
@@ -870,10 +895,10 @@ bool launch_tiled_ns(const PairConst &pc, const BoxDev *boxes, State s, const ui
                      int64_t ncell, int64_t n, const uint32_t *kdev, float *F, float *Q,
                      unsigned long long *nzero, uint32_t *err, const PairTile &t, bool sheared,
                      const MemArgs &ma, hipStream_t st) {
-// (16 species: one or two register chunks only, the rest is registers for
-// the species)
+// (nine or more species: one or two register chunks only, the rest is
+// registers for the species)
 #define TDPD_SHAPE(W, KC)                                                                    \
-  if constexpr (NS < 16 || KC <= 2) {                                                        \
+  if constexpr (NS <= 8 || KC <= 2) {                                                        \
     if (t.waves == W && t.chunks == KC) {                                                    \
       launch_shape<NS, W, KC, QF>(pc, boxes, s, cell_start, ncell, t.split, t.filter, n, kdev, \
                                   F, Q, nzero, err, sheared, ma, st);                        \
