@@ -16,6 +16,7 @@ extern TDPD_TILED_NS_DECL(2, true);
 extern TDPD_TILED_NS_DECL(4, true);
 extern TDPD_TILED_NS_DECL(4, false);
 extern TDPD_TILED_NS_DECL(8, true);
+extern TDPD_TILED_NS_DECL(10, true);
 extern TDPD_TILED_NS_DECL(12, true);
 extern TDPD_TILED_NS_DECL(16, true);
 
@@ -82,6 +83,7 @@ bool launch_pair_tiled(const PairConst &pc, const BoxDev *boxes, State s,
     TDPD_NS(4, false);
   }
   if (pc.n_species <= 8) TDPD_NS(8, true);
+  if (pc.n_species <= 10) TDPD_NS(10, true);
   if (pc.n_species <= 12) TDPD_NS(12, true);
   TDPD_NS(16, true);
 #undef TDPD_NS
@@ -142,6 +144,7 @@ bool pair_tiled_takes_membrane(const PairTile &t, int n_species, bool sheared, i
                       : n_species == 2 ? lds_ns<2, false>(t, sheared)
                       : n_species <= 4 ? lds_ns<4, false>(t, sheared)
                       : n_species <= 8 ? lds_ns<8, true>(t, sheared)
+                      : n_species <= 10 ? lds_ns<10, true>(t, sheared)
                       : n_species <= 12 ? lds_ns<12, true>(t, sheared)
                                         : lds_ns<16, true>(t, sheared);
   return membrane_cell_lds(max_nv, 64 * t.waves) <= have;

@@ -473,9 +473,16 @@ __global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
       }
       // (lanes past m read a stale table row: masked)
       const uint32_t j = valid ? row[0] : 0u, infoj = valid ? row[1] : 0u;
-      // the partner's concentration of species sp (from the table, or L2)
+      // the partner's concentrations (from the table, or from L2: the loads
+      // are issued here, for every lane, so that their latency overlaps the
+      // force-pair compaction below; lanes past m read slot 0)
+      float cjn[Shm::kNarrow ? NS : 1];
+      if constexpr (Shm::kNarrow) {
+#pragma unroll
+        for (int sp = 0; sp < NS; ++sp) cjn[sp] = sp < S ? s.C[sp * n + j] : 0.f;
+      }
       auto cjv = [&](int sp) __attribute__((always_inline)) -> float {
-        if constexpr (Shm::kNarrow) return s.C[sp * n + j];
+        if constexpr (Shm::kNarrow) return cjn[sp];
         else return __uint_as_float(row[2 + sp]);
       };
       const float d2 = dist2(re.x, re.y, re.z);  // the bits of the test

@@ -404,7 +404,7 @@ def _ten_species(ns=10):
 @pytest.mark.parametrize("kernel,tile", [(0, None), (1, (4, 2, 1, 1)), (1, (4, 1, 2, 0)),
                                          (1, (2, 2, 1, 0)), (1, (4, 2, 4, 1))])
 def test_ten_species_match_oracle(kernel, tile, ns):
-    """Ten species (the 16-species build of the tiled kernel, two register
+    """Ten species (the 10-species build of the tiled kernel, two register
     chunks at most) and six (the 8-species build), both with the flux
     queued: forces and all fluxes against the oracle."""
     cfg = _ten_species(ns)
@@ -420,6 +420,28 @@ def test_ten_species_match_oracle(kernel, tile, ns):
     ref = o.forces(pos, vel, conc, k=k)
     excl, sens = near_cutoff(o, cfg, pos, vel, ref, k)
     rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"{ns} species/k{kernel}/{tile}")
+    assert rep["badF"] == 0 and rep["badQ"] == 0
+    assert rep["excluded"] <= 5 + cfg.n // 20
+
+
+@pytest.mark.parametrize("tile", [(4, 2, 1, 1), (2, 2, 2, 0)])
+@pytest.mark.parametrize("ns", [3, 12, 16])
+def test_species_builds_match_oracle(ns, tile):
+    """The other species builds of the tiled kernel: three (the 4-species
+    build, flux in place), twelve and sixteen (queued flux, partner
+    concentrations from L2): forces and all fluxes against the oracle."""
+    cfg = _ten_species(ns)
+    sysg = gpu_system(cfg, kernel=1)
+    sysg.tile = tile
+    k = 4
+    sysg.compute_forces(k)
+    F, Q = sysg.get_forces()
+    assert Q.shape == (cfg.n, ns)
+    pos, vel, conc = sysg.get_state()
+    o = Oracle(cfg)
+    ref = o.forces(pos, vel, conc, k=k)
+    excl, sens = near_cutoff(o, cfg, pos, vel, ref, k)
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, label=f"{ns} species/{tile}")
     assert rep["badF"] == 0 and rep["badQ"] == 0
     assert rep["excluded"] <= 5 + cfg.n // 20
 
