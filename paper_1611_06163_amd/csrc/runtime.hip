@@ -118,7 +118,10 @@ struct tdpd_sys {
   PairTile tile{4, 2, 1, 1};  // shape of the cell-tiled kernel
   int bin_mode = 0;     // 0: counting (one-digit stable) sort, 1: LSD radix sort
   bool use_graph = true;
-  bool fuse_membrane = true;  // cells handled by the first workgroups of the pair kernel
+  // membrane parts inside the scan's and the pair kernel's launches: 1
+  // always, 0 never (a kernel of its own on the second stream), -1 by size
+  int fuse_membrane = -1;
+  int cu_count = 256;  // compute units of the device
   // Verlet neighbour lists (verlet_every > 0): rebuilt with the binning on
   // every verlet_every-th evaluation, pairs taken from them in between
   int verlet_every = 0;
@@ -381,7 +384,14 @@ static int create_common(const tdpd_params *p, std::vector<HostBox> boxes, void 
   if (const char *e = std::getenv("TDPD_PAIR_KERNEL")) s->pair_kernel = std::atoi(e);
   if (const char *e = std::getenv("TDPD_BIN")) s->bin_mode = std::atoi(e);
   if (const char *e = std::getenv("TDPD_GRAPH")) s->use_graph = std::atoi(e) != 0;
-  if (const char *e = std::getenv("TDPD_FUSE_MEMBRANE")) s->fuse_membrane = std::atoi(e) != 0;
+  if (const char *e = std::getenv("TDPD_FUSE_MEMBRANE")) s->fuse_membrane = std::atoi(e) != 0 ? 1 : 0;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      s->cu_count = cus;
+  }
   if (const char *e = std::getenv("TDPD_TILE")) {  // "waves,chunks,split,filter"
     PairTile t{};
     if (std::sscanf(e, "%d,%d,%d,%d", &t.waves, &t.chunks, &t.split, &t.filter) == 4 &&
@@ -1011,7 +1021,14 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   // serialised).  The surrogate, the simple pair kernel, the radix binning,
   // a timed membrane phase or a mesh too large for either launch's LDS take
   // the membrane kernel on a second stream beside the pair kernel instead.
-  const bool split = nrbc > 0 && tiled && !verlet && s->bin_mode == 0 && s->fuse_membrane &&
+  // By size: the membrane workgroups of the scan's launch run after the
+  // scan and before the pair kernel; beyond about four rounds of the chip
+  // (many cells) a kernel of its own beside the pair kernel, where the pair
+  // work hides it, costs less than the fork and join of the second stream.
+  const bool fuse = s->fuse_membrane == 1 ||
+                    (s->fuse_membrane < 0 &&
+                     int64_t(nrbc) * membrane_element_parts(s->bond_stride) <= 4 * int64_t(s->cu_count));
+  const bool split = nrbc > 0 && tiled && !verlet && s->bin_mode == 0 && fuse &&
                      !(s->timing_mask & (1 << 2)) && scan_takes_membrane(s->max_nv) &&
                      pair_tiled_takes_membrane(s->tile, s->S, s->any_shear, s->max_nv);
   MemArgs ma_split = mem_args(s, s->mc, s->Fm, SurrUse{nullptr, nullptr});
