@@ -162,9 +162,15 @@ __device__ __forceinline__ float3 close_step(const PairConst &pc, State s, float
     fx += vm.Fm[3 * v];
     fy += vm.Fm[3 * v + 1];
     fz += vm.Fm[3 * v + 2];
-    F[3 * i] = fx;
-    F[3 * i + 1] = fy;
-    F[3 * i + 2] = fz;
+    // the total force is kept for readback, except where the next step
+    // begins in the same kernel (its pair kernel overwrites F before anyone
+    // reads it; scattered over the vertices, the stores would cost a write
+    // granule each)
+    if (!vout) {
+      F[3 * i] = fx;
+      F[3 * i + 1] = fy;
+      F[3 * i + 2] = fz;
+    }
   }
   if (integrate && !info_frozen(info)) {
     const float h = pc.half_dt;
