@@ -274,9 +274,12 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
                                                  uint32_t *__restrict__ vals, int integrate,
                                                  uint32_t *__restrict__ cell_count,
                                                  uint32_t *__restrict__ kdev, int finish,
-                                                 VertexMap vprev) {
+                                                 VertexMap vprev, uint32_t *__restrict__ kstep) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const bool active = i < n;
+  // the counter of this evaluation, for kernels on the second stream that
+  // run while the scatter advances *kdev
+  if (i == 0 && kstep) *kstep = *kdev + uint32_t(finish);
   uint32_t key = 0xffffffffu;
   if (active) {
     const uint32_t info = s.info[i];
@@ -322,10 +325,10 @@ __global__ void __launch_bounds__(256) k_prekick(PairConst pc, const BoxDev *__r
 void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
                     const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
                     uint32_t *cell_count, uint32_t *kdev, bool finish, VertexMap prev,
-                    hipStream_t st) {
+                    uint32_t *kstep, hipStream_t st) {
   const int64_t nb = n > 0 ? (n + 255) / 256 : 1;
   hipLaunchKernelGGL(k_prekick, dim3(unsigned(nb)), dim3(256), 0, st, pc, boxes, s, F, Q, n, keys,
-                     vals, int(integrate), cell_count, kdev, int(finish), prev);
+                     vals, int(integrate), cell_count, kdev, int(finish), prev, kstep);
 }
 
 // First half of a step on the neighbour-list path (no binning): half kick
@@ -338,8 +341,10 @@ __global__ void __launch_bounds__(256) k_prekick_list(PairConst pc,
                                                       const float *__restrict__ Q, int64_t n,
                                                       int integrate,
                                                       const uint32_t *__restrict__ kdev,
-                                                      ListDev L, uint32_t *err) {
+                                                      ListDev L, uint32_t *err,
+                                                      uint32_t *__restrict__ kstep) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i == 0 && kstep) *kstep = *kdev;
   if (i >= n) return;
   const uint32_t info = s.info[i];
   const BoxDev &B = boxes[info_box(info)];
@@ -368,10 +373,10 @@ __global__ void __launch_bounds__(256) k_prekick_list(PairConst pc,
 
 void launch_prekick_list(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
                          const float *Q, int64_t n, bool integrate, const uint32_t *kdev,
-                         const ListDev &L, uint32_t *err, hipStream_t st) {
+                         const ListDev &L, uint32_t *err, uint32_t *kstep, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_prekick_list, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pc, boxes,
-                     s, F, Q, n, int(integrate), kdev, L, err);
+                     s, F, Q, n, int(integrate), kdev, L, err, kstep);
 }
 
 // ------------------------------------------------------------- counting binning

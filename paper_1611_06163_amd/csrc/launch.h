@@ -85,7 +85,7 @@ struct VertexMap {
 void launch_prekick(const PairConst &pc, const BoxDev *boxes, State s, float *F,
                     const float *Q, int64_t n, uint32_t *keys, uint32_t *vals, bool integrate,
                     uint32_t *cell_count, uint32_t *kdev, bool finish, VertexMap prev,
-                    hipStream_t st);
+                    uint32_t *kstep, hipStream_t st);
 // Counting binning after launch_prekick: scan of the cell counts into
 // cell_start (counts zeroed for the next step; tile_sum holds
 // count_scan_tiles(ncell) words; tmp holds 2n words), scatter, and the rank

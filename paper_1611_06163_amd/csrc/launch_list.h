@@ -59,7 +59,7 @@ void launch_list_build(const BoxDev *boxes, int nbox, State s, int nspec,
 // then the displacement check against xref (kErrSkin) and p4, v4.
 void launch_prekick_list(const PairConst &pc, const BoxDev *boxes, State s, const float *F,
                          const float *Q, int64_t n, bool integrate, const uint32_t *kdev,
-                         const ListDev &L, uint32_t *err, hipStream_t st);
+                         const ListDev &L, uint32_t *err, uint32_t *kstep, hipStream_t st);
 
 // Pair forces and fluxes over the lists (same outputs as the cell kernels).
 void launch_pair_list(const PairConst &pc, const BoxDev *boxes, State s, int64_t n,

@@ -98,7 +98,10 @@ struct tdpd_sys {
   float *F = nullptr, *Q = nullptr;
   uint32_t *keys = nullptr, *vals = nullptr, *keys_tmp = nullptr, *vals_tmp = nullptr;
   uint32_t *keys_s = nullptr, *perm = nullptr, *hist = nullptr, *cell_start = nullptr;
-  uint32_t *slot_of_gid = nullptr;
+  // gid -> slot of the membrane vertices, one map per state buffer (the
+  // binning writes the other one, so kernels on the second stream can read
+  // the current one while it runs)
+  uint32_t *slot_of_gid = nullptr, *slot_of_gid_b = nullptr;
   unsigned long long *nzero = nullptr, *pair_count = nullptr;
   uint32_t *errw = nullptr;
   double *diag_partial = nullptr, *diag_out = nullptr;
@@ -130,6 +133,7 @@ struct tdpd_sys {
   int list_age = 0;  // evaluations made with the current lists
   ListDev ld{};
   uint32_t *kdev = nullptr;       // device step counter read by the kernels
+  uint32_t *kstep = nullptr;      // the counter of the current evaluation (second stream)
   uint32_t kdev_val = 0;          // host mirror of *kdev
   uint32_t *cell_count = nullptr, *bin_tmp = nullptr, *tile_sum = nullptr;
   float *Fm = nullptr;            // membrane forces by global vertex [nvert][3]
@@ -155,6 +159,8 @@ struct tdpd_sys {
 
   State &cur() { return cur_A ? A : B; }
   State &nxt() { return cur_A ? B : A; }
+  uint32_t *slot_cur() const { return cur_A ? slot_of_gid : slot_of_gid_b; }
+  uint32_t *slot_nxt() const { return cur_A ? slot_of_gid_b : slot_of_gid; }
 
   int fail(int code, const std::string &m) {
     err = m;
@@ -765,10 +771,12 @@ static int prepare(tdpd_sys *s) {
   s->hist = dallocT<uint32_t>(s, radix_hist_words(n));
   s->cell_start = dallocT<uint32_t>(s, size_t(s->ncell) + 1);
   s->slot_of_gid = dallocT<uint32_t>(s, n);
+  s->slot_of_gid_b = dallocT<uint32_t>(s, n);
   s->nzero = dallocT<unsigned long long>(s, 2);
   s->pair_count = s->nzero + 1;
   s->errw = dallocT<uint32_t>(s, 1);
-  s->kdev = dallocT<uint32_t>(s, 1);
+  s->kdev = dallocT<uint32_t>(s, 2);
+  s->kstep = s->kdev ? s->kdev + 1 : nullptr;
   s->cell_count = dallocT<uint32_t>(s, size_t(s->ncell));
   s->bin_tmp = dallocT<uint32_t>(s, 2 * size_t(n));
   s->tile_sum = dallocT<uint32_t>(s, size_t(count_scan_tiles(s->ncell)));
@@ -792,7 +800,8 @@ static int prepare(tdpd_sys *s) {
   s->diag_partial = dallocT<double>(s, size_t((n + kDiagSpan - 1) / kDiagSpan + 1) * kDiagFields);
   s->diag_out = dallocT<double>(s, kDiagFields);
   if (!s->F || !s->Q || !s->keys || !s->vals || !s->keys_tmp || !s->vals_tmp || !s->keys_s ||
-      !s->perm || !s->hist || !s->cell_start || !s->slot_of_gid || !s->nzero || !s->errw ||
+      !s->perm || !s->hist || !s->cell_start || !s->slot_of_gid || !s->slot_of_gid_b ||
+      !s->nzero || !s->errw ||
       !s->diag_partial || !s->diag_out)
     return s->fail(TDPD_ERR_OOM, "device allocation failed");
   // SoA planes in gid order
@@ -812,6 +821,7 @@ static int prepare(tdpd_sys *s) {
     HIPCHK(hipMemcpyAsync(s->A.x, planes.data(), sizeof(float) * planes.size(), hipMemcpyHostToDevice, s->st));
     HIPCHK(hipMemcpyAsync(s->A.gid, ints.data(), sizeof(uint32_t) * ints.size(), hipMemcpyHostToDevice, s->st));
     HIPCHK(hipMemcpyAsync(s->slot_of_gid, ints.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, s->st));
+    HIPCHK(hipMemcpyAsync(s->slot_of_gid_b, ints.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, s->st));
     HIPCHK(hipMemsetAsync(s->F, 0, sizeof(float) * 3 * n, s->st));
     HIPCHK(hipMemsetAsync(s->Q, 0, sizeof(float) * S * n, s->st));
   }
@@ -960,7 +970,7 @@ static MemArgs mem_args(const tdpd_sys *s, const MembraneConst &mc, float *Fm_ou
   m.rbc_box = s->d_rbc_box;
   m.rbc_first = s->d_rbc_first;
   m.rbc_voff = s->d_rbc_voff;
-  m.slot_of_gid = s->slot_of_gid;
+  m.slot_of_gid = s->slot_cur();
   m.av = s->d_av;
   m.centroid = s->d_centroid;
   m.Fm = Fm_out;
@@ -998,10 +1008,11 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   const bool tb = s->phase_begin(1, st);
   if (rebuild) {
     launch_prekick(s->pc, s->d_boxes, s->cur(), s->F, s->Q, n, s->keys, s->vals, integrate,
-                   s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, fuse_prev, vmap, st);
+                   s->bin_mode == 0 ? s->cell_count : nullptr, s->kdev, fuse_prev, vmap, s->kstep,
+                   st);
   } else {
     launch_prekick_list(s->pc, s->d_boxes, s->cur(), s->F, s->Q, n, integrate, s->kdev, s->ld,
-                        s->errw, st);
+                        s->errw, s->kstep, st);
   }
   if (verlet) {
     s->list_age = rebuild ? 1 : s->list_age + 1;
@@ -1033,6 +1044,39 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
                      pair_tiled_takes_membrane(s->tile, s->S, s->any_shear, s->max_nv);
   MemArgs ma_split = mem_args(s, s->mc, s->Fm, SurrUse{nullptr, nullptr});
   if (!split) ma_split.nrbc = 0;
+  // The membrane kernel on the second stream (when the membrane terms do not
+  // ride in the binning and pair launches) starts right after the first
+  // kick: it reads the drifted positions in the previous order through the
+  // current id-to-slot map (the binning writes the other one) and the
+  // evaluation's counter from the snapshot, so it runs beside the binning
+  // and the pair kernel.
+  if (nrbc > 0 && !split) {
+    (void)hipEventRecord(s->ev_fork, st);
+    (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
+    const bool tm = s->phase_begin(2, s->st2);
+    SurrUse su{nullptr, nullptr};
+    if (s->surr_on) {
+      // network forces from the lagged cell totals, then (every surr_every
+      // steps, gated on the device counter) the plain bending + local-area
+      // forces and the per-vertex fallback decision
+      launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_cur(), s->d_av,
+                           s->nvert, s->kstep, s->pc.dt, 0, s->st2);
+      mlp_forward(s->surr_params, s->sd.X, s->nvert, s->sd.Y, s->st2);
+      launch_surr_apply(s->sd, s->nvert, s->st2);
+      MembraneConst ml = s->mc;
+      ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
+      ml.local_only = 1;
+      ml.gate = s->surr_every;
+      launch_membrane(mem_args(s, ml, s->sd.Fp, SurrUse{nullptr, nullptr}), s->d_boxes, s->cur(),
+                      s->kstep, s->errw, s->mem_lds, s->st2);
+      launch_surr_check(s->sd, nrbc, s->kstep, s->surr_every, s->st2);
+      su = SurrUse{s->sd.flag, s->sd.Fs};
+    }
+    launch_membrane(mem_args(s, s->mc, s->Fm, su), s->d_boxes, s->cur(), s->kstep, s->errw,
+                    s->mem_lds, s->st2);
+    s->phase_end(2, tm, s->st2);
+    (void)hipEventRecord(s->ev_join, s->st2);
+  }
   // With the surrogate on the split path the network runs on the second
   // stream beside the binning, on the drifted positions in the previous
   // order (so its cell totals are those of the previous evaluation, which
@@ -1043,8 +1087,8 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
   if (surr_split) {
     (void)hipEventRecord(s->ev_fork, st);
     (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
-    launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av,
-                         s->nvert, s->kdev, s->pc.dt, fuse_prev ? 1 : 0, s->st2);
+    launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_cur(), s->d_av,
+                         s->nvert, s->kstep, s->pc.dt, 0, s->st2);
     mlp_forward(s->surr_params, s->sd.X, s->nvert, s->sd.Y, s->st2);
     launch_surr_apply(s->sd, s->nvert, s->st2);
     (void)hipEventRecord(s->ev_join, s->st2);
@@ -1054,16 +1098,18 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
     // the particle order of the last rebuild stays
   } else if (s->bin_mode == 0) {
     launch_bin_counting(s->cur(), s->nxt(), s->keys, s->vals, s->cell_count, s->ncell,
-                        s->cell_start, s->bin_tmp, s->tile_sum, n, s->S, s->slot_of_gid, s->keys_s,
+                        s->cell_start, s->bin_tmp, s->tile_sum, n, s->S, s->slot_nxt(), s->keys_s,
                         fuse_prev ? s->kdev : nullptr, ma_split, s->d_boxes, s->kdev,
                         fuse_prev ? 1 : 0, s->errw, st);
   } else {
     radix_sort(s->keys, s->vals, s->keys_tmp, s->vals_tmp, s->keys_s, s->perm, s->hist, n,
                s->key_bits, st);
     launch_cell_bounds(s->keys_s, n, s->ncell, s->cell_start, st);
-    launch_reorder(s->cur(), s->nxt(), s->perm, n, s->S, s->slot_of_gid, st);
+    launch_reorder(s->cur(), s->nxt(), s->perm, n, s->S, s->slot_nxt(), st);
   }
   if (rebuild) s->cur_A = !s->cur_A;
+  // the pair kernel's per-vertex membrane terms read the new order
+  ma_split.slot_of_gid = s->slot_cur();
   if (verlet && rebuild)
     launch_list_build(s->d_boxes, int(s->boxes.size()), s->cur(), s->S, s->cell_start, s->ncell,
                       n, s->ld, s->errw, st);
@@ -1081,33 +1127,6 @@ static int enqueue_evaluation(tdpd_sys *s, bool integrate, hipStream_t st, bool 
     launch_surr_check(s->sd, nrbc, s->kdev, s->surr_every, st);
   }
   s->phase_end(1, tb, st);
-  if (nrbc > 0 && !split) {
-    (void)hipEventRecord(s->ev_fork, st);
-    (void)hipStreamWaitEvent(s->st2, s->ev_fork, 0);
-    const bool tm = s->phase_begin(2, s->st2);
-    SurrUse su{nullptr, nullptr};
-    if (s->surr_on) {
-      // network forces from the lagged cell totals, then (every surr_every
-      // steps, gated on the device counter) the plain bending + local-area
-      // forces and the per-vertex fallback decision
-      launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av,
-                           s->nvert, s->kdev, s->pc.dt, 0, s->st2);
-      mlp_forward(s->surr_params, s->sd.X, s->nvert, s->sd.Y, s->st2);
-      launch_surr_apply(s->sd, s->nvert, s->st2);
-      MembraneConst ml = s->mc;
-      ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
-      ml.local_only = 1;
-      ml.gate = s->surr_every;
-      launch_membrane(mem_args(s, ml, s->sd.Fp, SurrUse{nullptr, nullptr}), s->d_boxes, s->cur(),
-                      s->kdev, s->errw, s->mem_lds, s->st2);
-      launch_surr_check(s->sd, nrbc, s->kdev, s->surr_every, s->st2);
-      su = SurrUse{s->sd.flag, s->sd.Fs};
-    }
-    launch_membrane(mem_args(s, s->mc, s->Fm, su), s->d_boxes, s->cur(), s->kdev, s->errw,
-                    s->mem_lds, s->st2);
-    s->phase_end(2, tm, s->st2);
-    (void)hipEventRecord(s->ev_join, s->st2);
-  }
   const bool tp = s->phase_begin(0, st);
   if (verlet) {
     launch_pair_list(s->pc, s->d_boxes, s->cur(), n, s->kdev, s->ld, s->F, s->Q, s->nzero,
@@ -1512,7 +1531,7 @@ std::vector<std::pair<void *, size_t>> ckpt_regions(tdpd_sys *s) {
   std::vector<std::pair<void *, size_t>> r = {
       {c.x, sizeof(float) * (6 + S) * n},   // x, y, z, vx, vy, vz, C planes (one block)
       {c.gid, sizeof(uint32_t) * 2 * n},    // gid, info
-      {s->slot_of_gid, sizeof(uint32_t) * n},
+      {s->slot_cur(), sizeof(uint32_t) * n},
       {s->F, sizeof(float) * 3 * n},
       {s->Q, sizeof(float) * S * n},
       // the cells of the last binning (they hold the current positions),
@@ -1845,7 +1864,7 @@ extern "C" int tdpd_surrogate_sample(tdpd_sys *s, float *X, float *T, uint8_t *o
   // the state is that of the last evaluation (counter kdev_val); the device
   // counter already holds the next step's
   launch_set_counter(s->kdev, s->kdev_val, s->st);
-  launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_of_gid, s->d_av, nv,
+  launch_surr_features(s->sd, s->d_boxes, s->d_meshes, s->cur(), s->slot_cur(), s->d_av, nv,
                        s->kdev, s->pc.dt, 0, s->st);
   MembraneConst ml = s->mc;
   ml.terms = s->mc.terms & (TDPD_TERM_AREA | TDPD_TERM_BENDING);
