@@ -170,6 +170,21 @@ def test_skin_exceeded_is_reported():
     s.close()
 
 
+def test_bench_skin_survives_ten_thousand_channel_steps():
+    """The skin and interval the benchmark uses (0.6, every 5 steps) keep
+    every particle within half the skin between rebuilds over 10,000 steps
+    of the 100-cell channel (membrane vertices, pushed by stiff bonds, move
+    faster than the solvent): no step reports TDPD_ERR_LIST and the state
+    stays finite."""
+    s = _listed(I.c3(), skin=0.6, every=5)
+    for _ in range(20):
+        s.step(500)
+        s.sync()  # raises on a reported skin or capacity violation
+    x, v, c = s.get_state()
+    assert np.isfinite(x).all() and np.isfinite(v).all() and np.isfinite(c).all()
+    s.close()
+
+
 def test_list_capacity_overflow_is_reported():
     s = _listed(I.c1(), capacity=16)  # about 110 neighbours each at rho = 4
     with pytest.raises(tdpd.TdpdError) as e:
