@@ -308,9 +308,15 @@ int tdpd_load(tdpd_sys *s, const char *path);
    system's stream), keeps the fastest and re-evaluates the forces with it.
    With cache_path (may be NULL) it first looks for a line written for the
    same device and workload signature (particle, species, box, cell and RBC
-   counts, term mask) and uses it without timing; otherwise it appends the
-   result.  *best_ms (may be NULL) gets the chosen shape's time, 0 when the
-   tiled kernel is not used (m_s > 0, or the simple kernel selected).
+   counts, term mask, in-place or queued flux) and uses it without timing;
+   otherwise it appends the result.  *best_ms (may be NULL) gets the chosen
+   shape's time, 0 when the tiled kernel is not used (the simple kernel
+   selected, or 2^26 particles or more).  One to four species without the
+   random flux evaluate the flux in place on every candidate lane; the
+   random flux (m_s > 0) and five or more species take the queued-flux
+   build, in which the flux pairs are compacted into an LDS queue first;
+   both are built in every shape, and both give results within rounding of
+   each other.
    tdpd_set_tile returns TDPD_ERR_UNSUPPORTED for a shape that is not built.
    These calls are not part of the paper's method: they choose among
    equivalent evaluation orders of Eqs. (2)-(10). */
