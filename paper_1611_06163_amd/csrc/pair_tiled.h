@@ -158,7 +158,8 @@ struct TiledShared {
 // Evaluate ring entries [head, head+m) of wave w (m <= 64) and add them to
 // that wave's home accumulators; every home index forms one run in the
 // window (entries are appended in home order and the ring is flushed at the
-// end of each register block), so run leaders never collide.
+// end of each register block), so the per-run sums (segmented DPP scans,
+// registers only) land on distinct homes.
 template <int NS, int W, bool LE, typename Shm>
 __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B, const State &s,
                                            Shm &sh, int w, uint32_t head, int m,
@@ -166,6 +167,7 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
   const int lane = threadIdx.x & 63;
   const uint32_t e = (head + lane) & (kRing - 1);
   int hi_i = -1;
+  float f3[3] = {0.f, 0.f, 0.f};
   wave_sync();
   if (lane < m) {
     const float4 re = sh.ring[w][e];
@@ -183,26 +185,20 @@ __device__ __forceinline__ void flush_ring(const PairConst &pc, const BoxDev &B,
                                 sh.hvz[hi_i], vxj, s.vy[j], s.vz[j], info_type(sh.hinfo[hi_i]),
                                 info_type(s.info[j]), sh.hgid[hi_i] - B.gid_base,
                                 s.gid[j] - B.gid_base, k);
-    sh.ring[w][e] = make_float4(f.x, f.y, f.z, re.w);
+    f3[0] = f.x;
+    f3[1] = f.y;
+    f3[2] = f.z;
   }
-  wave_sync();
-  if (lane < m) {
-    const bool leader =
-        lane == 0 ||
-        int(__float_as_uint(sh.ring[w][(head + lane - 1) & (kRing - 1)].w) >> kJBits) != hi_i;
-    if (leader) {
-      float ax = 0.f, ay = 0.f, az = 0.f;
-      for (int q = lane; q < m; ++q) {
-        const float4 rq = sh.ring[w][(head + q) & (kRing - 1)];
-        if (int(__float_as_uint(rq.w) >> kJBits) != hi_i) break;
-        ax += rq.x;
-        ay += rq.y;
-        az += rq.z;
-      }
-      sh.fa[w][0][hi_i] += ax;
-      sh.fa[w][1][hi_i] += ay;
-      sh.fa[w][2][hi_i] += az;
-    }
+  // a lane starts a run where its home index differs from the previous
+  // lane's (lane 0 always; the lanes past m form a run of their own)
+  const int ip = __builtin_amdgcn_update_dpp(-1, hi_i, 0x138, 0xf, 0xf, false);  // wave_shr:1
+  const bool run0 = hi_i != ip;
+  seg_scan<3>(f3, run0);
+  const uint64_t rm = ballot(run0);
+  if (lane < m && (lane == m - 1 || ((rm >> (lane + 1)) & 1ull))) {  // the run's last lane
+    sh.fa[w][0][hi_i] += f3[0];
+    sh.fa[w][1][hi_i] += f3[1];
+    sh.fa[w][2][hi_i] += f3[2];
   }
   wave_sync();
 }
@@ -217,7 +213,7 @@ struct PairEmit {
 };
 
 template <int NS, int W, int KC, bool SH, bool QF, bool EMIT = false>
-__global__ void __launch_bounds__(64 * W) k_pair_tiled(PairConst pc,
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(NS <= 2 && !QF && !SH && KC <= 3 ? 6 : 1))) k_pair_tiled(PairConst pc,
                                                             const BoxDev *__restrict__ boxes,
                                                             State s,
                                                             const uint32_t *__restrict__ cell_start,
