@@ -41,13 +41,8 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 PAIR_SOURCES = ("pair_tiled.h", "kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h",
                 "launch.h", "membrane_cell.h")
 PAIR_TRAFFIC = {
-    "c5": {"sha256": "d6d9566159978aec270ddb8fb31913ef275bb8cd02e3a061e5de94478a273b83",
-           "tiles": {"2,3,1,1": [3.0646e+08, 5.0024e+07]}},
-    "c2": {"sha256": "59dc66a822af5242516ac95286b8168f93d17401f5cd557e331bda8f01b0a829",
-           "tiles": {"4,2,2,0": [3.048e+06, 4.964e+05],
-                     "2,3,2,0": [3.182e+06, 4.965e+05],
-                     "4,2,2,1": [3.052e+06, 4.964e+05],
-                     "2,3,2,1": [3.184e+06, 4.965e+05]}},
+    "c5": {"sha256": "490abcc330e14f6131eec0f699a9586a3fe70fd628eb6784527ce2ceed6c9868",
+           "tiles": {"2,3,1,1": [3.0650e+08, 4.9977e+07]}},
 }
 
 

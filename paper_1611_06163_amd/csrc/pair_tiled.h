@@ -14,7 +14,7 @@
 //     register block;
 //   - force pairs are compacted with a wave ballot into the wave's LDS ring
 //     and evaluated 64 at a time, one pair per lane (Philox noise, weights),
-//     then summed per home particle in ring order.
+//     then summed per home particle with segmented DPP scans.
 // The queued-flux build (QF) compacts every candidate inside the largest
 // cutoff into a pair queue instead and evaluates the queue 64 entries at a
 // time: the Fickian and random fluxes of each pair (Eqs. 8-10), summed per
@@ -29,6 +29,7 @@
 // production candidate path can be checked pair by pair.
 #pragma once
 
+#include <cstddef>
 #include <cstring>
 #include <type_traits>
 
@@ -410,10 +411,10 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(NS 
       sh.hgid[tid] = s.gid[p];
       sh.hinfo[tid] = s.info[p];
     }
-    if (lane < kH) {
-      sh.fa[w][0][lane] = sh.fa[w][1][lane] = sh.fa[w][2][lane] = 0.f;
-#pragma unroll
-      for (int sp = 0; sp < NS; ++sp) sh.qa[w][sp][lane] = 0.f;
+    {  // every wave's force and flux accumulators (fa and qa are adjacent)
+      static_assert(offsetof(Shm, qa) == offsetof(Shm, fa) + sizeof(sh.fa), "fa, qa adjacent");
+      float *acc = &sh.fa[0][0][0];
+      for (int e = tid; e < W * (3 + NS) * kH; e += 64 * W) acc[e] = 0.f;
     }
     __syncthreads();
     // this wave's cursors (wave-uniform): the force ring (head, tail), or
