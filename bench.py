@@ -41,7 +41,7 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 PAIR_SOURCES = ("pair_tiled.h", "kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h",
                 "launch.h", "membrane_cell.h")
 PAIR_TRAFFIC = {
-    "c5": {"sha256": "490abcc330e14f6131eec0f699a9586a3fe70fd628eb6784527ce2ceed6c9868",
+    "c5": {"sha256": "e6eb703f374376f416c50b1047d0ea9aa680f7939ae346603200b4e2a88c59f2",
            "tiles": {"2,3,1,1": [3.0650e+08, 4.9977e+07]}},
 }
 

@@ -213,19 +213,17 @@ struct PairEmit {
   uint32_t k;                   // step counter of the positions
 };
 
+// The in-place builds of up to two species and three register chunks ask
+// for six waves per SIMD (at most 80 VGPRs), which they fit without spills;
+// left to itself the compiler spends a few more registers and loses a wave.
 template <int NS, int W, int KC, bool SH, bool QF, bool EMIT = false>
-__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(NS <= 2 && !QF && !SH && KC <= 3 ? 6 : 1))) k_pair_tiled(PairConst pc,
-                                                            const BoxDev *__restrict__ boxes,
-                                                            State s,
-                                                            const uint32_t *__restrict__ cell_start,
-                                                            int64_t ncell, int split, int filter,
-                                                            int64_t per_xcd, int64_t n,
-                                                            const uint32_t *__restrict__ kdev,
-                                                            float *__restrict__ F,
-                                                            float *__restrict__ Q,
-                                                            unsigned long long *nzero,
-                                                            uint32_t *err, MemArgs ma, int nmemb,
-                                                            int vparts, PairEmit em) {
+__global__ void __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(NS <= 2 && !QF && !SH && KC <= 3 ? 6 : 1)))
+k_pair_tiled(PairConst pc, const BoxDev *__restrict__ boxes, State s,
+             const uint32_t *__restrict__ cell_start, int64_t ncell, int split, int filter,
+             int64_t per_xcd, int64_t n, const uint32_t *__restrict__ kdev,
+             float *__restrict__ F, float *__restrict__ Q, unsigned long long *nzero,
+             uint32_t *err, MemArgs ma, int nmemb, int vparts, PairEmit em) {
   using Shm = TiledShared<NS, W, KC, SH, QF>;
   __shared__ Shm sh;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
