@@ -239,18 +239,36 @@ k_pair_tiled(PairConst pc, const BoxDev *__restrict__ boxes, State s,
                         reinterpret_cast<char *>(&sh));
     return;
   }
-  // consecutive workgroups go to different XCDs; give each XCD a contiguous
-  // slab of cells so neighbouring cells share that XCD's L2
+  // Consecutive workgroups go to different XCDs; each XCD takes a
+  // contiguous range of the walk order, so neighbouring cells share its L2.
+  // The walk takes a box in blocks of kYBlk rows of cells along y, each
+  // block z layer by z layer (x fastest): the three z layers a cell's
+  // stencil spans then lie within about 3 kYBlk rows of the walk, which an
+  // XCD's L2 holds (the row-major order would put a whole y-x layer of the
+  // box between them).  Any order gives the same results: cells are
+  // independent.
+  constexpr int kYBlk = 8;
   const int64_t b = int64_t(blockIdx.x) - nmemb;
   const int64_t item = (b & 7) * per_xcd + (b >> 3);
   if (item >= ncell * split) return;
-  const int64_t cell = item / split;
-  const int part = int(item - cell * split);
+  const int64_t walk = item / split;  // position of the cell in the walk
+  const int part = int(item - walk * split);
   const int S = pc.n_species, T = pc.n_types;
-  const BoxDev &B = boxes[box_of_cell(boxes, pc.n_boxes, uint32_t(cell))];
+  const BoxDev &B = boxes[box_of_cell(boxes, pc.n_boxes, uint32_t(walk))];
   const int nx = B.nc[0], ny = B.nc[1], nz = B.nc[2];
-  const int64_t lc = cell - B.cell_base;  // cell index inside its box
-  const int cx = int(lc % nx), cy = int((lc / nx) % ny), cz = int(lc / (int64_t(nx) * ny));
+  int cx, cy, cz;
+  {  // (a box holds fewer than 2^31 cells)
+    const uint32_t lw = uint32_t(walk - B.cell_base), blk = uint32_t(kYBlk * nz) * uint32_t(nx);
+    const uint32_t yb = lw / blk, r = lw - yb * blk;
+    const uint32_t hb = uint32_t(min(kYBlk, ny - int(yb) * kYBlk));  // rows of this block
+    const uint32_t lay = hb * uint32_t(nx);                           // cells of a layer of it
+    cz = int(r / lay);
+    const uint32_t r2 = r - uint32_t(cz) * lay, row = r2 / uint32_t(nx);
+    cy = int(yb) * kYBlk + int(row);
+    cx = int(r2 - row * uint32_t(nx));
+  }
+  const int64_t lc = (int64_t(cz) * ny + cy) * nx + cx;  // cell index inside its box
+  const int64_t cell = B.cell_base + lc;
   // In a sheared box the neighbour row across the y boundary is displaced
   // by delta in x: its candidates come from the min(4, n_x) cells around
   // x -/+ delta, taken in the sheared image (the candidate lifted when the
