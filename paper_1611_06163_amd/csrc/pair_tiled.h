@@ -244,9 +244,10 @@ k_pair_tiled(PairConst pc, const BoxDev *__restrict__ boxes, State s,
   // The walk takes a box in blocks of kYBlk rows of cells along y, each
   // block z layer by z layer (x fastest): the three z layers a cell's
   // stencil spans then lie within about 3 kYBlk rows of the walk, which an
-  // XCD's L2 holds (the row-major order would put a whole y-x layer of the
-  // box between them).  Any order gives the same results: cells are
-  // independent.
+  // XCD's 4 MB L2 holds for rows of up to a few hundred cells at about 600
+  // bytes of particle data per cell (the row-major order would put a whole
+  // y-x layer of the box between them).  Any order gives the same results:
+  // cells are independent.
   constexpr int kYBlk = 8;
   const int64_t b = int64_t(blockIdx.x) - nmemb;
   const int64_t item = (b & 7) * per_xcd + (b >> 3);
