@@ -41,7 +41,7 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 PAIR_SOURCES = ("pair_tiled.h", "kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h",
                 "launch.h", "membrane_cell.h")
 PAIR_TRAFFIC = {
-    "c5": {"sha256": "91811cd5090a842f2e1170e0e7fdbedaed8cef9febbd9d85e5020b84fb1e8f15",
+    "c5": {"sha256": "61d8b992905b4b0e8d8fd6d4e114f08263501a0395c6a5e2e4f3e4ef2adeaf24",
            "tiles": {"2,3,1,1": [1.3824e+08, 5.0052e+07]}},
 }
 

@@ -428,9 +428,9 @@ k_pair_tiled(PairConst pc, const BoxDev *__restrict__ boxes, State s,
       sh.hgid[tid] = s.gid[p];
       sh.hinfo[tid] = s.info[p];
     }
-    {  // every wave's force and flux accumulators (fa and qa are adjacent)
+    {  // every wave's force and flux accumulators, fa and qa (adjacent)
       static_assert(offsetof(Shm, qa) == offsetof(Shm, fa) + sizeof(sh.fa), "fa, qa adjacent");
-      float *acc = &sh.fa[0][0][0];
+      float *acc = reinterpret_cast<float *>(reinterpret_cast<char *>(&sh) + offsetof(Shm, fa));
       for (int e = tid; e < W * (3 + NS) * kH; e += 64 * W) acc[e] = 0.f;
     }
     __syncthreads();
