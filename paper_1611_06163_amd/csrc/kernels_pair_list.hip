@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
                                                             ListDev L, float *__restrict__ F,
                                                             float *__restrict__ Q,
                                                             unsigned long long *nzero,
-                                                            uint32_t *err) {
+                                                            uint32_t *err, int64_t per_xcd) {
   __shared__ ListShared<NS> sh;
   const int tid = int(threadIdx.x);
   const int T = pc.n_types, S = pc.n_species;
@@ -97,7 +97,11 @@ __global__ void __launch_bounds__(kListThreads) k_pair_list(PairConst pc,
     sh.sigma[e] = pc.sigma[e];
   }
   __syncthreads();
-  const int64_t t = int64_t(blockIdx.x) * kListThreads + tid;
+  // consecutive workgroups go to different XCDs; each XCD takes a
+  // contiguous range of particles (cell order), so the neighbours its lists
+  // gather stay in its L2
+  const int64_t bb = int64_t(blockIdx.x);
+  const int64_t t = ((bb & 7) * per_xcd + (bb >> 3)) * kListThreads + tid;
   const int64_t i = t / LANES;  // the LANES lanes of i are adjacent in one wavefront
   const int lane = int(t % LANES);
   if (i >= n) return;
@@ -205,21 +209,21 @@ template <int LANES>
 static void launch_pair_list_lanes(const PairConst &pc, const BoxDev *boxes, State s, int64_t n,
                                    const uint32_t *kdev, const ListDev &L, float *F, float *Q,
                                    unsigned long long *nzero, uint32_t *err, hipStream_t st) {
-  const int64_t lanes = n * LANES;
-  const dim3 g(unsigned((lanes + kListThreads - 1) / kListThreads)), b(kListThreads);
+  const int64_t lanes = n * LANES, per_xcd = ((lanes + kListThreads - 1) / kListThreads + 7) / 8;
+  const dim3 g(unsigned(8 * per_xcd)), b(kListThreads);
   const int S = pc.n_species;
   if (S <= 1)
     hipLaunchKernelGGL((k_pair_list<1, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
-                       nzero, err);
+                       nzero, err, per_xcd);
   else if (S <= 2)
     hipLaunchKernelGGL((k_pair_list<2, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
-                       nzero, err);
+                       nzero, err, per_xcd);
   else if (S <= 4)
     hipLaunchKernelGGL((k_pair_list<4, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
-                       nzero, err);
+                       nzero, err, per_xcd);
   else
     hipLaunchKernelGGL((k_pair_list<kMaxS, LANES>), g, b, 0, st, pc, boxes, s, n, kdev, L, F, Q,
-                       nzero, err);
+                       nzero, err, per_xcd);
 }
 
 void launch_pair_list(const PairConst &pc, const BoxDev *boxes, State s, int64_t n,
@@ -251,13 +255,17 @@ __global__ void __launch_bounds__(kBuildThreads) k_list_build(const BoxDev *__re
                                                               int nbox, State s, int nspec,
                                                               const uint32_t *__restrict__ cell_start,
                                                               int64_t n, ListDev L,
-                                                              uint32_t *err) {
+                                                              uint32_t *err, int64_t ncell,
+                                                              int64_t per_xcd) {
   __shared__ float4 stage[kStageMax];
   __shared__ uint32_t cstart[27], cpref[28];
   __shared__ float cshift[27][3];
   __shared__ uint32_t wsum[kBuildThreads / 64];
   const int tid = int(threadIdx.x);
-  const uint32_t c = blockIdx.x;
+  // a contiguous range of cells per XCD, as in the pair kernels
+  const int64_t bb = int64_t(blockIdx.x), cw = (bb & 7) * per_xcd + (bb >> 3);
+  if (cw >= ncell) return;  // uniform over the workgroup
+  const uint32_t c = uint32_t(cw);
   const BoxDev &B = boxes[box_of_cell(boxes, nbox, c)];
   const uint32_t h0 = cell_start[c], h1 = cell_start[c + 1];
   if (h0 == h1) return;  // uniform over the workgroup
@@ -387,12 +395,13 @@ void launch_list_build(const BoxDev *boxes, int nbox, State s, int nspec,
                        const uint32_t *cell_start, int64_t ncell, int64_t n, const ListDev &L,
                        uint32_t *err, hipStream_t st) {
   if (n <= 0) return;
+  const int64_t per_xcd = (ncell + 7) / 8;
   if (L.lanes == 4)
-    hipLaunchKernelGGL(k_list_build<4>, dim3(unsigned(ncell)), dim3(kBuildThreads), 0, st, boxes,
-                       nbox, s, nspec, cell_start, n, L, err);
+    hipLaunchKernelGGL(k_list_build<4>, dim3(unsigned(8 * per_xcd)), dim3(kBuildThreads), 0, st,
+                       boxes, nbox, s, nspec, cell_start, n, L, err, ncell, per_xcd);
   else
-    hipLaunchKernelGGL(k_list_build<8>, dim3(unsigned(ncell)), dim3(kBuildThreads), 0, st, boxes,
-                       nbox, s, nspec, cell_start, n, L, err);
+    hipLaunchKernelGGL(k_list_build<8>, dim3(unsigned(8 * per_xcd)), dim3(kBuildThreads), 0, st,
+                       boxes, nbox, s, nspec, cell_start, n, L, err, ncell, per_xcd);
 }
 
 // ------------------------------------------------------------- pair listing
