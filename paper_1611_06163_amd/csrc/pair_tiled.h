@@ -59,14 +59,20 @@ __device__ __forceinline__ float dpp(float v) {
 // Sum over the 64 lanes with DPP: inclusive scans inside each 16-lane row
 // (row_shr 1, 2, 4, 8), then row_bcast 15 and 31 carry row totals upward;
 // lane 63 ends with the total (other lanes hold partial sums).  Fixed
-// order, registers only.
+// order, registers only.  The two row_bcast steps are single DPP adds whose
+// row mask leaves the other rows unwritten (as builtins they take a move of
+// zero, a DPP move and an add each); the s_nop gives the DPP read of the
+// register the previous VALU instruction wrote its two wait states.  Call
+// with all lanes active.
 __device__ __forceinline__ float wave_sum_to_last(float v) {
   v += dpp<0x111, 0xf>(v);
   v += dpp<0x112, 0xf>(v);
   v += dpp<0x114, 0xf>(v);
   v += dpp<0x118, 0xf>(v);
-  v += dpp<0x142, 0xa>(v);
-  v += dpp<0x143, 0xc>(v);
+  asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf"
+               : "+v"(v));
+  asm volatile("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+               : "+v"(v));
   return v;
 }
 
