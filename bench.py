@@ -41,8 +41,8 @@ METRIC = "tDPD particle-steps/s on 1 MI355X; batched & surrogate vs plain at tol
 PAIR_SOURCES = ("pair_tiled.h", "kernels_pair_tiled.hip", "pair_terms.h", "tdpd_device.h",
                 "launch.h", "membrane_cell.h")
 PAIR_TRAFFIC = {
-    "c5": {"sha256": "61d8b992905b4b0e8d8fd6d4e114f08263501a0395c6a5e2e4f3e4ef2adeaf24",
-           "tiles": {"2,3,1,1": [1.3824e+08, 5.0052e+07]}},
+    "c5": {"sha256": "4982a53a5b319c2e7b192a513be308b494493767d0c2737e9ddee7c41fd54ab9",
+           "tiles": {"2,3,1,1": [1.3824e+08, 5.0038e+07]}},
 }
 
 
