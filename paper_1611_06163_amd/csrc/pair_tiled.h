@@ -134,12 +134,13 @@ struct TiledShared {
   // words of a candidate's row in the block table: slot, info word, the
   // concentrations, padded to whole 16-byte loads
   static constexpr int kRow = kNarrow ? 2 : (2 + NS + 3) / 4 * 4;
+  // (first: its offsets fit the immediate offsets of the paired LDS reads)
+  float kap[NS][kMaxT * kMaxT];
   float hx[kH], hy[kH], hz[kH], hvx[kH], hvy[kH], hvz[kH];
   float hc[NS][kH];
   uint32_t hgid[kH], hinfo[kH];
   float fa[W][3][kH];
   float qa[W][NS][kH];
-  float kap[NS][kMaxT * kMaxT];
   int seg_start[kMaxSeg];
   int seg_pref[kMaxSeg + 1];
   int8_t seg_sg[kMaxSeg][4];  // periodic image per axis: -1, 0 or +1 box length
