@@ -36,7 +36,68 @@ def _ulp32(x):
     return (np.nextafter(x, np.float32(np.inf)) - x).astype(np.float64)
 
 
-def near_cutoff_sensitivity(o, cfg, pos, vel, k):
+def _pairs_of_sample(cfg, pos, which):
+    """Ordered pairs (i, j), i in the sample, |d| below r_c (1 + 1e-4) under
+    the minimum image (periodic k-d tree; no shear): a superset of the
+    sample's pairs whose distances could round across r_c."""
+    from scipy.spatial import cKDTree
+    assert float(getattr(cfg, "shear_rate", 0.0)) == 0.0
+    L = np.asarray(cfg.box, dtype=np.float64)
+    x = np.mod(pos.astype(np.float64), L)
+    x[x >= L] = 0.0
+    tree = cKDTree(x, boxsize=L)
+    idx = np.flatnonzero(which)
+    nb = tree.query_ball_point(x[idx], r=cfg.rc * (1.0 + 1e-4))  # (superset)
+    pi = np.concatenate([np.full(len(b), i, np.int64) for i, b in zip(idx, nb)])
+    pj = np.concatenate([np.asarray(b, np.int64) for b in nb])
+    keep = pi != pj
+    return np.stack([pi[keep], pj[keep]], axis=1)
+
+
+def flux_sensitivity(cfg, pos, conc, which):
+    """Per sampled particle and species, a bound on how far the FP32
+    rounding of its pair distances and of the flux weight can move its
+    Fickian flux (Eq. 8).  w = 1 - r/r_cc loses relative precision as r
+    nears r_cc, where a flux made of a few such pairs of one sign (a solvent
+    particle at C = 0 beside a cell's vertices) is then resolved to no better
+    than the pair's own weight error: per pair |dw| <= dr/r_cc + 2^-23 (dr
+    the rounding of r, as in near_cutoff_sensitivity; one rounding of the
+    fused 1 - r/r_cc and of 1/r_cc), and the flux term moves by at most
+    kappa_ij |C_j - C_i| (2 w_hi |dw| + dw^2) for the exponent 2 weight."""
+    from scipy.spatial import cKDTree
+    assert float(getattr(cfg, "shear_rate", 0.0)) == 0.0 and float(cfg.sc_exp) == 2.0
+    L = np.asarray(cfg.box, dtype=np.float64)
+    x = np.mod(pos.astype(np.float64), L)
+    x[x >= L] = 0.0
+    tree = cKDTree(x, boxsize=L)
+    idx = np.flatnonzero(which)
+    nb = tree.query_ball_point(x[idx], r=cfg.rcc * (1.0 + 1e-4))
+    pi = np.concatenate([np.full(len(b), i, np.int64) for i, b in zip(idx, nb)])
+    pj = np.concatenate([np.asarray(b, np.int64) for b in nb])
+    keep = pi != pj
+    pi, pj = pi[keep], pj[keep]
+    d = pos[pj].astype(np.float64) - pos[pi]
+    shift = -L * np.round(d / L)
+    d += shift
+    r = np.linalg.norm(d, axis=1)
+    # across the boundary the lifted coordinate (below 2 L) rounds to half an
+    # ulp of 2 L; the difference rounds to half an ulp of d
+    dd = np.where(shift != 0.0, 0.5 * _ulp32(2.0 * L)[None, :], 0.0) + 0.5 * _ulp32(d)
+    dr = (np.abs(d) / np.maximum(r, 1e-30)[:, None] * dd).sum(axis=1) + 3.0 * _ulp32(r)
+    dw = dr / cfg.rcc + 2.0 ** -23
+    whi = np.clip(1.0 - (r - dr) / cfg.rcc, 0.0, 1.0)
+    inside = r - dr < cfg.rcc
+    kap = np.asarray(cfg.kappa, dtype=np.float64)            # [species][type i][type j]
+    ti, tj = cfg.flags[pi] & 0xFF, cfg.flags[pj] & 0xFF       # flags: bits 0-7 the type
+    kp = kap[:, ti, tj].T                                     # [pair][species]
+    dC = np.abs(conc[pj].astype(np.float64) - conc[pi])
+    per = np.where(inside, 2.0 * whi * dw + dw * dw, 0.0)[:, None] * kp * dC
+    out = np.zeros((pos.shape[0], cfg.n_species))
+    np.add.at(out, pi, per)
+    return out
+
+
+def near_cutoff_sensitivity(o, cfg, pos, vel, k, which=None):
     """Per particle, a bound on how far the FP32 rounding of the pair
     distances can move its force.
 
@@ -50,8 +111,12 @@ def near_cutoff_sensitivity(o, cfg, pos, vel, k):
     weight is bounded by its values at w -/+ dr/r_c (the weights are
     monotone), so a pair moves the force by at most
     sigma |xi| dw_R / sqrt(dt) + gamma |v_ij| dw_D + alpha dr / r_c, with the
-    pair's own noise draw xi."""
-    p, _ = o.pairs(pos.astype(np.float32), 0, k=k)
+    pair's own noise draw xi.  With `which`, only the sampled particles get
+    a bound (from their own pairs; the others 0)."""
+    if which is None:
+        p, _ = o.pairs(pos.astype(np.float32), 0, k=k)
+    else:
+        p = _pairs_of_sample(cfg, pos, which)
     xi_ = pos[p[:, 0]].astype(np.float64)
     xj = pos[p[:, 1]].astype(np.float64)
     d = xj - xi_
@@ -90,7 +155,10 @@ def near_cutoff_sensitivity(o, cfg, pos, vel, k):
     dr = (np.abs(d) / r[:, None] * dd).sum(axis=1) + 3.0 * _ulp32(r)
     w = np.clip(1.0 - r / cfg.rc, 0.0, 1.0)
     dw = dr / cfg.rc
-    wlo, whi = np.maximum(w - dw, 0.0), np.minimum(w + dw, 1.0)
+    # (the same as w -/+ dw clipped to [0, 1] inside r_c; a sampled pair
+    # beyond r_c moves only if its rounding can bring it inside)
+    wlo = np.clip(1.0 - (r + dr) / cfg.rc, 0.0, 1.0)
+    whi = np.clip(1.0 - (r - dr) / cfg.rc, 0.0, 1.0)
     s = cfg.s_exp
 
     def spread(e):
@@ -107,17 +175,18 @@ def near_cutoff_sensitivity(o, cfg, pos, vel, k):
     sens = (sig * xi * spread(0.5 * s) / np.sqrt(cfg.dt) + gam * vij * spread(s) + alp * dw)
     tot = np.zeros(pos.shape[0])
     np.add.at(tot, p[:, 0], sens)
-    np.add.at(tot, p[:, 1], sens)
+    if which is None:  # unordered pairs: the bound is the partner's too
+        np.add.at(tot, p[:, 1], sens)
     mobile = (cfg.flags & tdpd.FLAG_FROZEN) == 0  # frozen particles have F = 0 exactly
     return np.where(mobile, tot, 0.0)
 
 
-def near_cutoff(o, cfg, pos, vel, ref, k, tol=TOL):
+def near_cutoff(o, cfg, pos, vel, ref, k, tol=TOL, which=None):
     """(mask, sens): particles whose force cannot be resolved to the parity
     bound in FP32 -- the rounding of their pair distances alone
     (near_cutoff_sensitivity, sens) may move the force by more than half of
     force_bound.  compare_forces checks them against force_bound + sens."""
-    sens = near_cutoff_sensitivity(o, cfg, pos, vel, k)
+    sens = near_cutoff_sensitivity(o, cfg, pos, vel, k, which=which)
     return sens > 0.5 * force_bound(ref, tol), sens
 
 
@@ -131,7 +200,7 @@ def force_bound(ref, tol=TOL, tol_mem=TOL_MEM):
 
 
 def compare_forces(F, Q, ref, exclude=None, tol=TOL, which=None, label="", tol_mem=TOL_MEM,
-                   sens=None):
+                   sens=None, sens_q=None):
     """Per-particle check |F - F_ref| <= force_bound(ref); |Q - Q_ref| <=
     tol * sum_j |Q_ij| (+ a floor).  Excluded particles (near_cutoff_mask)
     are checked against force_bound + sens when sens is given (badF_excl).
@@ -145,6 +214,8 @@ def compare_forces(F, Q, ref, exclude=None, tol=TOL, which=None, label="", tol_m
     bF = force_bound(ref, tol, tol_mem)
     eQ = np.abs(Q.astype(np.float64) - ref["Q"])
     bQ = tol * ref["Qabs"] + 4e-7 * np.abs(ref["Q"]) + 1e-7
+    if sens_q is not None:  # flux_sensitivity: the weight's rounding near r_cc
+        bQ = bQ + sens_q
     badF = sel & (eF > bF)
     badQ = sel[:, None] & (eQ > bQ)
     rF = (eF / np.maximum(ref["Fabs"], 1e-30))[sel]

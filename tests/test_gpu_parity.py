@@ -11,7 +11,7 @@ are counted, reported and bounded.
 import numpy as np
 import pytest
 
-from gpu_helpers import compare_forces, gpu_system, near_cutoff
+from gpu_helpers import compare_forces, flux_sensitivity, gpu_system, near_cutoff
 from oracle import Oracle
 from paper_1611_06163_amd import inputs as I
 from paper_1611_06163_amd import tdpd
@@ -333,6 +333,38 @@ def test_full_size_sampled_c3():
         rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, which=which, label=f"c3-full/k{kernel}")
         assert rep["badF"] == 0 and rep["badQ"] == 0
         sysg.close()
+
+
+def test_full_size_sampled_c5():
+    """The 1000-cell suspension at its full size (2,490,656 particles), in
+    the launch configuration bench.py times (the tiled kernel at tile
+    (2, 3, 1, 1), the membrane kernel on the second stream): forces and
+    fluxes of 3000 sampled particles and of one cell's 500 vertices against
+    the oracle, particle by particle (near-cutoff bounds from the sample's
+    own pairs; the flux checked against the rounding bound of its weight
+    near r_cc, flux_sensitivity, which at this size meets solvent particles
+    whose species-1 flux is a few vertex pairs near the flux cutoff)."""
+    cfg = I.c5()
+    rng = np.random.default_rng(0)
+    which = np.zeros(cfg.n, np.uint8)
+    which[rng.choice(cfg.n, 3000, replace=False)] = 1
+    which[cfg.rbc_first_gid[0]:cfg.rbc_first_gid[0] + 500] = 1
+    print("c5 sampled: generated", flush=True)
+    sysg = gpu_system(cfg, kernel=1)
+    sysg.tile = (2, 3, 1, 1)
+    sysg.compute_forces(3)
+    F, Q = sysg.get_forces()
+    pos, vel, conc = sysg.get_state()
+    sysg.close()
+    o = Oracle(cfg)
+    ref = o.forces(pos, vel, conc, k=3, which=which)
+    excl, sens = near_cutoff(o, cfg, pos, vel, ref, 3, which=which)
+    sens_q = flux_sensitivity(cfg, pos, conc, which)
+    rep = compare_forces(F, Q, ref, exclude=excl, sens=sens, which=which, label="c5-full",
+                         sens_q=sens_q)
+    print(rep, flush=True)
+    assert rep["n"] > 3000
+    assert rep["badF"] == 0 and rep["badQ"] == 0
 
 
 def test_checkpoint_resume_bitwise(tmp_path):
